@@ -1,0 +1,507 @@
+/*
+ * RAMBO oracle: a plain, slow, obviously correct CPU implementation of the
+ * multiple-set-membership index of Gupta, Yan, Coleman, Elworth, Medini,
+ * Treangen and Shrivastava, "RAMBO: Repeated And Merged BloOm Filter for
+ * Ultra-fast Multiple Set Membership Testing (MSMT) on Large-Scale Data"
+ * (arXiv 1910.02611).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU
+ * baseline of the benchmark are the only code that may load this library.
+ * It shares no code with the GPU library: every hash, encoding and table is
+ * written again here from its published definition.
+ *
+ * Data structure (Sec. 3, Fig. 1, Alg. 1): R tables of B cells; every cell
+ * is its own Bloom filter of m bits (a "BFU", Bloom filter of the union of
+ * the sets the partition hash puts in that cell).  Each BFU is a separate
+ * array.  Nothing is bit-sliced, blocked, fused or reordered.
+ *
+ * Conventions the paper leaves open (each is a reading, stated once here):
+ *  - Terms are k-mers over ACGT (Sec. 5.2).  Base values A=0, C=1, G=2, T=3,
+ *    case-insensitive; the first base of the window is the most significant
+ *    base-4 digit.  Any other byte breaks the window.
+ *  - A term is stored in canonical form: the smaller of its code and the
+ *    code of its reverse complement (complement of base b is 3-b).
+ *  - Partition hash phi_r (Alg. 1, Sec. 3.1), applied to the set identity:
+ *    phi_r(i) = ((a_r * i + b_r) mod P) mod B with P = 2^61 - 1, the
+ *    Carter-Wegman 2-universal family the paper cites; repetitions 0..R-1.
+ *  - Bloom-filter hash h_{r,j} (Sec. 2): pos = floor(mix64(x XOR s_{r,j}) * m
+ *    / 2^64), where mix64 is the output function of splitmix64 (Steele, Lea
+ *    and Flood, OOPSLA 2014) and the floor-of-product range reduction is
+ *    Lemire's (2019).  The eta seeds of a repetition are shared by the B
+ *    cells of that repetition and differ between repetitions.
+ *  - Seeds: one splitmix64 stream from the master seed yields, in order,
+ *    (a_r, b_r) for r = 0..R-1 with a_r = 1 + u mod (P-1), b_r = u mod P,
+ *    then s_{r,j} for r = 0..R-1, j = 0..eta-1.
+ *  - Answers are K-bit masks: set i is bit (i mod 32) of 32-bit word i/32.
+ *  - A sequence query with no valid k-mer answers the empty set.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-22)
+#define ORC_ENOMEM (-12)
+#define ORC_ERANGE (-34)
+
+#define ORC_FLAG_IDENTITY_PARTITION 1u
+#define ORC_NO_KMER UINT64_MAX
+
+static const uint64_t ORC_P61 = (1ULL << 61) - 1;
+
+/* ---------------------------------------------------------------- hashing */
+
+/* splitmix64 output function (Steele, Lea, Flood 2014). */
+uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* splitmix64 generator step: advance the Weyl state, then mix it. */
+uint64_t orc_splitmix64_next(uint64_t *state)
+{
+    *state += 0x9E3779B97F4A7C15ULL;
+    return orc_mix64(*state);
+}
+
+/* Partition hash phi (Alg. 1, Sec. 3.1): ((a*i + b) mod P) mod B. */
+uint32_t orc_partition_value(uint64_t a, uint64_t b, uint64_t i, uint32_t B)
+{
+    unsigned __int128 t = (unsigned __int128)a * i + b;
+    uint64_t modp = (uint64_t)(t % ORC_P61);
+    return (uint32_t)(modp % B);
+}
+
+/* Bloom-filter position (Sec. 2): floor(mix64(x ^ s) * m / 2^64). */
+uint64_t orc_position(uint64_t x, uint64_t seed, uint64_t m)
+{
+    uint64_t h = orc_mix64(x ^ seed);
+    return (uint64_t)(((unsigned __int128)h * m) >> 64);
+}
+
+/* ------------------------------------------------------------- k-mer code */
+
+static int orc_base_value(unsigned char c)
+{
+    switch (c) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+    }
+}
+
+/* Code of the k bases at s: base-4 number, first base most significant.
+ * Returns 1 and stores the code when all k bytes are bases, else 0. */
+int orc_encode_kmer(const unsigned char *s, uint32_t k, uint64_t *code)
+{
+    uint64_t v = 0;
+    for (uint32_t t = 0; t < k; t++) {
+        int b = orc_base_value(s[t]);
+        if (b < 0)
+            return 0;
+        v = v * 4 + (uint64_t)b;
+    }
+    *code = v;
+    return 1;
+}
+
+/* Reverse complement: read the digits from the last base to the first,
+ * replacing each base b by 3 - b. */
+uint64_t orc_revcomp(uint64_t code, uint32_t k)
+{
+    uint64_t r = 0;
+    for (uint32_t t = 0; t < k; t++) {
+        uint64_t b = code & 3;
+        code >>= 2;
+        r = r * 4 + (3 - b);
+    }
+    return r;
+}
+
+uint64_t orc_canonical(uint64_t code, uint32_t k)
+{
+    uint64_t rc = orc_revcomp(code, k);
+    return code < rc ? code : rc;
+}
+
+static int orc_code_in_range(uint64_t code, uint32_t k)
+{
+    return k >= 32 || code < (1ULL << (2 * k));
+}
+
+/* Canonical code of every window of every sequence.  out[offsets[s] + t] is
+ * the canonical code of the window starting at base t of sequence s, or
+ * ORC_NO_KMER where no valid window starts. */
+void orc_extract(const uint64_t *offsets, const unsigned char *chars, uint64_t n_seqs,
+                 uint32_t k, uint64_t *out)
+{
+    for (uint64_t s = 0; s < n_seqs; s++) {
+        uint64_t beg = offsets[s], end = offsets[s + 1];
+        for (uint64_t p = beg; p < end; p++) {
+            uint64_t code;
+            if (p + k <= end && orc_encode_kmer(chars + p, k, &code))
+                out[p] = orc_canonical(code, k);
+            else
+                out[p] = ORC_NO_KMER;
+        }
+    }
+}
+
+/* ------------------------------------------------------------ the index */
+
+typedef struct orc_index {
+    uint32_t K, B, R, eta, k, flags;
+    uint64_t m, seed;
+    uint64_t *pa, *pb;        /* partition hash parameters, [R] */
+    uint64_t *ps;             /* Bloom-filter hash seeds, [R*eta] */
+    uint32_t *phi;            /* phi_r(i) at [r*K + i] */
+    uint64_t *member_off;     /* SetIDs(M[b,r]): sets of cell (r,b) are */
+    uint32_t *member_ids;     /*   member_ids[member_off[r*B+b] .. +1) */
+    uint64_t words;           /* 64-bit words per BFU */
+    uint64_t **bfu;           /* bfu[r*B + b]: the m bits of cell (r,b) */
+} orc_index;
+
+static void orc_bit_set(uint64_t *a, uint64_t p) { a[p >> 6] |= 1ULL << (p & 63); }
+static int orc_bit_get(const uint64_t *a, uint64_t p) { return (int)((a[p >> 6] >> (p & 63)) & 1); }
+
+void orc_destroy(orc_index *h)
+{
+    if (!h)
+        return;
+    if (h->bfu) {
+        for (uint64_t c = 0; c < (uint64_t)h->R * h->B; c++)
+            free(h->bfu[c]);
+        free(h->bfu);
+    }
+    free(h->pa); free(h->pb); free(h->ps); free(h->phi);
+    free(h->member_off); free(h->member_ids);
+    free(h);
+}
+
+int orc_create(uint32_t K, uint32_t B, uint32_t R, uint32_t eta, uint32_t k, uint64_t m,
+               uint64_t seed, uint32_t flags, orc_index **out)
+{
+    *out = NULL;
+    if (K < 1 || B < 1 || B > K || R < 1 || eta < 1 || k < 1 || k > 32 || m < 64)
+        return ORC_EINVAL;
+    orc_index *h = calloc(1, sizeof *h);
+    if (!h)
+        return ORC_ENOMEM;
+    h->K = K; h->B = B; h->R = R; h->eta = eta; h->k = k; h->m = m;
+    h->seed = seed; h->flags = flags;
+    h->words = (m + 63) / 64;
+    h->pa = calloc(R, sizeof(uint64_t));
+    h->pb = calloc(R, sizeof(uint64_t));
+    h->ps = calloc((size_t)R * eta, sizeof(uint64_t));
+    h->phi = calloc((size_t)R * K, sizeof(uint32_t));
+    h->member_off = calloc((size_t)R * B + 1, sizeof(uint64_t));
+    h->member_ids = calloc((size_t)R * K, sizeof(uint32_t));
+    h->bfu = calloc((size_t)R * B, sizeof(uint64_t *));
+    if (!h->pa || !h->pb || !h->ps || !h->phi || !h->member_off || !h->member_ids || !h->bfu) {
+        orc_destroy(h);
+        return ORC_ENOMEM;
+    }
+
+    /* Seeds, in the documented order. */
+    uint64_t st = seed;
+    for (uint32_t r = 0; r < R; r++) {
+        h->pa[r] = 1 + orc_splitmix64_next(&st) % (ORC_P61 - 1);
+        h->pb[r] = orc_splitmix64_next(&st) % ORC_P61;
+    }
+    for (uint32_t r = 0; r < R; r++)
+        for (uint32_t j = 0; j < eta; j++)
+            h->ps[(size_t)r * eta + j] = orc_splitmix64_next(&st);
+
+    /* R independent partitions of the K sets into B cells (Alg. 1, line
+     * "generate R partition hash functions"). */
+    for (uint32_t r = 0; r < R; r++)
+        for (uint32_t i = 0; i < K; i++)
+            h->phi[(size_t)r * K + i] = (flags & ORC_FLAG_IDENTITY_PARTITION)
+                                            ? i % B
+                                            : orc_partition_value(h->pa[r], h->pb[r], i, B);
+
+    /* SetIDs(M[b,r]) (Alg. 2): the sets that cell (r,b) holds, ascending. */
+    uint64_t pos = 0;
+    for (uint32_t r = 0; r < R; r++)
+        for (uint32_t b = 0; b < B; b++) {
+            h->member_off[(size_t)r * B + b] = pos;
+            for (uint32_t i = 0; i < K; i++)
+                if (h->phi[(size_t)r * K + i] == b)
+                    h->member_ids[pos++] = i;
+        }
+    h->member_off[(size_t)R * B] = pos;
+
+    /* B x R array of Bloom filters, all bits 0 (Alg. 1, Sec. 2). */
+    for (uint64_t c = 0; c < (uint64_t)R * B; c++) {
+        h->bfu[c] = calloc(h->words, sizeof(uint64_t));
+        if (!h->bfu[c]) {
+            orc_destroy(h);
+            return ORC_ENOMEM;
+        }
+    }
+    *out = h;
+    return ORC_OK;
+}
+
+/* Parameters, for tests: a[R], b[R], s[R*eta], phi[R*K] (any may be NULL). */
+void orc_params(const orc_index *h, uint64_t *a, uint64_t *b, uint64_t *s, uint32_t *phi)
+{
+    if (a) memcpy(a, h->pa, h->R * sizeof(uint64_t));
+    if (b) memcpy(b, h->pb, h->R * sizeof(uint64_t));
+    if (s) memcpy(s, h->ps, (size_t)h->R * h->eta * sizeof(uint64_t));
+    if (phi) memcpy(phi, h->phi, (size_t)h->R * h->K * sizeof(uint32_t));
+}
+
+/* Bloom-filter insert of term x into one BFU (Sec. 2): set its eta bits. */
+static void orc_bf_insert(const orc_index *h, uint32_t r, uint32_t cell, uint64_t x)
+{
+    for (uint32_t j = 0; j < h->eta; j++)
+        orc_bit_set(h->bfu[(size_t)r * h->B + cell], orc_position(x, h->ps[(size_t)r * h->eta + j], h->m));
+}
+
+/* Bloom-filter query of term x in one BFU (Sec. 2): AND of its eta bits. */
+static int orc_bf_query(const orc_index *h, uint32_t r, uint32_t cell, uint64_t x)
+{
+    for (uint32_t j = 0; j < h->eta; j++)
+        if (!orc_bit_get(h->bfu[(size_t)r * h->B + cell], orc_position(x, h->ps[(size_t)r * h->eta + j], h->m)))
+            return 0;
+    return 1;
+}
+
+/* Alg. 1 for one term of one set: insert it into the set's cell of every
+ * repetition. */
+int orc_insert_kmer(orc_index *h, uint32_t set_id, uint64_t code)
+{
+    if (set_id >= h->K)
+        return ORC_ERANGE;
+    if (!orc_code_in_range(code, h->k))
+        return ORC_EINVAL;
+    uint64_t x = orc_canonical(code, h->k);
+    for (uint32_t r = 0; r < h->R; r++)
+        orc_bf_insert(h, r, h->phi[(size_t)r * h->K + set_id], x);
+    return ORC_OK;
+}
+
+/* Alg. 1 for every valid k-mer of one sequence of set set_id. */
+int orc_insert_seq(orc_index *h, uint32_t set_id, const unsigned char *chars, uint64_t len)
+{
+    if (set_id >= h->K)
+        return ORC_ERANGE;
+    for (uint64_t t = 0; t + h->k <= len; t++) {
+        uint64_t code;
+        if (orc_encode_kmer(chars + t, h->k, &code))
+            orc_insert_kmer(h, set_id, code);
+    }
+    return ORC_OK;
+}
+
+/* Alg. 1 over many sequences.  Threads own whole cells (r,b), so no two
+ * threads write one bit array; the result is the same as the serial loop
+ * because OR is order-free. */
+int orc_insert_seqs(orc_index *h, const uint32_t *set_ids, const uint64_t *offsets,
+                    const unsigned char *chars, uint64_t n_seqs, int nthreads)
+{
+    for (uint64_t s = 0; s < n_seqs; s++)
+        if (set_ids[s] >= h->K)
+            return ORC_ERANGE;
+    int64_t ncell = (int64_t)h->R * h->B;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t c = 0; c < ncell; c++) {
+        uint32_t r = (uint32_t)(c / h->B), cell = (uint32_t)(c % h->B);
+        for (uint64_t s = 0; s < n_seqs; s++) {
+            if (h->phi[(size_t)r * h->K + set_ids[s]] != cell)
+                continue;
+            for (uint64_t p = offsets[s]; p + h->k <= offsets[s + 1]; p++) {
+                uint64_t code;
+                if (orc_encode_kmer(chars + p, h->k, &code))
+                    orc_bf_insert(h, r, cell, orc_canonical(code, h->k));
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Same, from k-mer codes in CSR form (codes of set set_ids[s] are
+ * codes[offsets[s] .. offsets[s+1])). */
+int orc_insert_kmers(orc_index *h, const uint32_t *set_ids, const uint64_t *offsets,
+                     const uint64_t *codes, uint64_t n_sets, int nthreads)
+{
+    for (uint64_t s = 0; s < n_sets; s++) {
+        if (set_ids[s] >= h->K)
+            return ORC_ERANGE;
+        for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++)
+            if (!orc_code_in_range(codes[p], h->k))
+                return ORC_EINVAL;
+    }
+    int64_t ncell = (int64_t)h->R * h->B;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t c = 0; c < ncell; c++) {
+        uint32_t r = (uint32_t)(c / h->B), cell = (uint32_t)(c % h->B);
+        for (uint64_t s = 0; s < n_sets; s++) {
+            if (h->phi[(size_t)r * h->K + set_ids[s]] != cell)
+                continue;
+            for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++)
+                orc_bf_insert(h, r, cell, orc_canonical(codes[p], h->k));
+        }
+    }
+    return ORC_OK;
+}
+
+/* Alg. 2, the Bloom-filter tests: G[r*B + b] = 1 iff term x passes the BF
+ * test of cell (r,b). */
+void orc_query_cells(const orc_index *h, uint64_t code, unsigned char *G)
+{
+    uint64_t x = orc_canonical(code, h->k);
+    for (uint32_t r = 0; r < h->R; r++)
+        for (uint32_t b = 0; b < h->B; b++)
+            G[(size_t)r * h->B + b] = (unsigned char)orc_bf_query(h, r, b, x);
+}
+
+static void orc_mask_set(uint32_t *mask, uint32_t i) { mask[i >> 5] |= 1u << (i & 31); }
+
+/* Alg. 2 for one term: G_r = union of SetIDs(M[b,r]) over the cells b whose
+ * BF holds x; A = intersection over r of G_r.  mask has ceil(K/32) words.
+ * A code outside [0, 4^k) is not a term and answers the empty set. */
+int orc_query_kmer(const orc_index *h, uint64_t code, uint32_t *mask)
+{
+    uint32_t W = (h->K + 31) / 32;
+    memset(mask, 0, W * sizeof(uint32_t));
+    if (!orc_code_in_range(code, h->k))
+        return ORC_EINVAL;
+    unsigned char *G = malloc((size_t)h->R * h->B);
+    unsigned char *inG = malloc(h->K);
+    unsigned char *A = malloc(h->K);
+    if (!G || !inG || !A) {
+        free(G); free(inG); free(A);
+        return ORC_ENOMEM;
+    }
+    orc_query_cells(h, code, G);
+    for (uint32_t i = 0; i < h->K; i++)
+        A[i] = 1;
+    for (uint32_t r = 0; r < h->R; r++) {
+        memset(inG, 0, h->K);
+        for (uint32_t b = 0; b < h->B; b++) {
+            if (!G[(size_t)r * h->B + b])
+                continue;
+            for (uint64_t p = h->member_off[(size_t)r * h->B + b]; p < h->member_off[(size_t)r * h->B + b + 1]; p++)
+                inG[h->member_ids[p]] = 1;
+        }
+        for (uint32_t i = 0; i < h->K; i++)
+            A[i] = A[i] & inG[i];
+    }
+    for (uint32_t i = 0; i < h->K; i++)
+        if (A[i])
+            orc_mask_set(mask, i);
+    free(G); free(inG); free(A);
+    return ORC_OK;
+}
+
+/* Batch of term queries; out has n * ceil(K/32) words.  Threads split the
+ * queries, which only read the index. */
+void orc_query_kmers(const orc_index *h, const uint64_t *codes, uint64_t n, uint32_t *out,
+                     int nthreads)
+{
+    uint32_t W = (h->K + 31) / 32;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t q = 0; q < (int64_t)n; q++)
+        orc_query_kmer(h, codes[q], out + (size_t)q * W);
+}
+
+/* Sec. 3.2.1: the answer for a sequence is the conjunction of the answers of
+ * all its k-mers (the sliding window), taken literally, with no early exit.
+ * Returns the number of valid k-mers; with none, the answer is empty. */
+uint64_t orc_query_seq(const orc_index *h, const unsigned char *chars, uint64_t len, uint32_t *mask)
+{
+    uint32_t W = (h->K + 31) / 32;
+    uint32_t *one = malloc(W * sizeof(uint32_t));
+    uint64_t n = 0;
+    for (uint32_t w = 0; w < W; w++)
+        mask[w] = 0;
+    for (uint32_t i = 0; i < h->K; i++)
+        orc_mask_set(mask, i);
+    for (uint64_t t = 0; t + h->k <= len; t++) {
+        uint64_t code;
+        if (!orc_encode_kmer(chars + t, h->k, &code))
+            continue;
+        n++;
+        orc_query_kmer(h, code, one);
+        for (uint32_t w = 0; w < W; w++)
+            mask[w] &= one[w];
+    }
+    if (n == 0)
+        memset(mask, 0, W * sizeof(uint32_t));
+    free(one);
+    return n;
+}
+
+void orc_query_seqs(const orc_index *h, const uint64_t *offsets, const unsigned char *chars,
+                    uint64_t n_reads, uint32_t *out, uint64_t *nkmers, int nthreads)
+{
+    uint32_t W = (h->K + 31) / 32;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < (int64_t)n_reads; q++) {
+        uint64_t n = orc_query_seq(h, chars + offsets[q], offsets[q + 1] - offsets[q], out + (size_t)q * W);
+        if (nkmers)
+            nkmers[q] = n;
+    }
+}
+
+/* ------------------------------------------------------------ inspection */
+
+/* Number of 1 bits in every BFU, [R*B]. */
+void orc_fill_counts(const orc_index *h, uint64_t *out)
+{
+    for (uint64_t c = 0; c < (uint64_t)h->R * h->B; c++) {
+        uint64_t n = 0;
+        for (uint64_t w = 0; w < h->words; w++)
+            n += (uint64_t)__builtin_popcountll(h->bfu[c][w]);
+        out[c] = n;
+    }
+}
+
+/* The raw bits of BFU (r,b): ceil(m/64) words, bit p at word p/64, bit p%64. */
+void orc_copy_bfu(const orc_index *h, uint32_t r, uint32_t b, uint64_t *out)
+{
+    memcpy(out, h->bfu[(size_t)r * h->B + b], h->words * sizeof(uint64_t));
+}
+
+/* Bit p of every BFU of repetition r, for a list of positions:
+ * out[t*B + b] = bit rows[t] of cell (r,b). */
+void orc_bits_at(const orc_index *h, uint32_t r, const uint64_t *rows, uint64_t n, unsigned char *out)
+{
+    for (uint64_t t = 0; t < n; t++)
+        for (uint32_t b = 0; b < h->B; b++)
+            out[t * h->B + b] = (unsigned char)orc_bit_get(h->bfu[(size_t)r * h->B + b], rows[t]);
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

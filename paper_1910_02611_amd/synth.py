@@ -1,0 +1,195 @@
+"""Seeded synthetic workloads (genomes, k-mer queries, reads, request streams).
+
+Stand-ins for the paper's ENA whole-genome data (Sec. 5.2): each set is one
+genome, each term a 31-mer of an ACGT sequence.  Everything is drawn from a
+Philox counter-based generator (Salmon et al., SC'11) keyed by a seed, so the
+same seed yields the same bytes on every machine.  This module produces raw
+bytes and integers only; it holds no encoding, hashing or indexing
+arithmetic, and it serves the GPU path and the test oracle alike.
+
+Every workload is a CSR of byte sequences: ``chars`` (uint8, concatenated),
+``offsets`` (uint64, n+1) and, for sets, ``set_ids`` (uint32, n).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_LUT = np.frombuffer(b"ACGT", dtype=np.uint8)
+SIGMA_LOGNORMAL = math.log(10.0) / 3.0   # a decade is three sigma
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=int(seed)))
+
+
+@dataclass
+class SeqBatch:
+    chars: np.ndarray                  # uint8
+    offsets: np.ndarray                # uint64, n+1
+    set_ids: np.ndarray | None = None  # uint32, n (sets only)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.offsets.size - 1
+
+    def seq(self, i: int) -> bytes:
+        return self.chars[int(self.offsets[i]):int(self.offsets[i + 1])].tobytes()
+
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+
+def _csr(parts: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray]:
+    lens = np.array([p.size for p in parts], dtype=np.uint64)
+    offsets = np.zeros(len(parts) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    chars = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    return np.ascontiguousarray(chars, dtype=np.uint8), offsets
+
+
+def random_bases(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n uniform random bases as base indices 0..3."""
+    return rng.integers(0, 4, size=n, dtype=np.uint8)
+
+
+def substitute(rng: np.random.Generator, idx: np.ndarray, rate: float) -> np.ndarray:
+    """Every position independently, with probability `rate`, becomes one of
+    the other three bases, uniformly (a Bernoulli process drawn as geometric
+    gaps)."""
+    out = idx.copy()
+    L = out.size
+    if rate <= 0 or L == 0:
+        return out
+    mean = L * rate
+    draw = int(mean + 10 * math.sqrt(mean) + 16)
+    pos = np.cumsum(rng.geometric(rate, size=draw)) - 1
+    while pos[-1] < L:
+        more = np.cumsum(rng.geometric(rate, size=draw)) + pos[-1]
+        pos = np.concatenate([pos, more])
+    pos = pos[pos < L]
+    out[pos] = (out[pos] + rng.integers(1, 4, size=pos.size, dtype=np.uint8)) & 3
+    return out
+
+
+def lognormal_lengths(rng, n, median, lo, hi, sigma=SIGMA_LOGNORMAL) -> np.ndarray:
+    x = np.exp(rng.normal(math.log(median), sigma, size=n))
+    return np.clip(np.rint(x), lo, hi).astype(np.int64)
+
+
+def to_bytes(idx: np.ndarray) -> np.ndarray:
+    return _LUT[idx]
+
+
+# --------------------------------------------------------------------- sets
+
+def genome_sets(seed: int, K: int, n_ancestors: int, ancestor_len: int, *,
+                sub_rate: float = 0.01, median_len: int | None = None,
+                min_len: int | None = None, max_len: int | None = None) -> SeqBatch:
+    """K genomes: set i is a window of ancestor (i mod n_ancestors) with
+    independent substitutions.  With median_len None every set is the whole
+    ancestor; otherwise the window length is lognormal (clipped)."""
+    rng = rng_for(seed)
+    anc = [random_bases(rng, ancestor_len) for _ in range(n_ancestors)]
+    if median_len is None:
+        lens = np.full(K, ancestor_len, dtype=np.int64)
+    else:
+        lens = lognormal_lengths(rng, K, median_len, min_len, min(max_len, ancestor_len))
+    parts = []
+    for i in range(K):
+        a = anc[i % n_ancestors]
+        L = int(lens[i])
+        start = int(rng.integers(0, ancestor_len - L + 1))
+        parts.append(to_bytes(substitute(rng, a[start:start + L], sub_rate)))
+    chars, offsets = _csr(parts)
+    return SeqBatch(chars, offsets, np.arange(K, dtype=np.uint32),
+                    meta=dict(K=K, n_ancestors=n_ancestors, ancestor_len=ancestor_len,
+                              sub_rate=sub_rate, median_len=median_len))
+
+
+# ------------------------------------------------------------------ queries
+
+def kmer_queries(seed: int, sets: SeqBatch, n: int, k: int, present_frac: float = 0.5) -> SeqBatch:
+    """n single k-mer queries as k-byte sequences: the first round(n *
+    present_frac) are windows at a uniform (set, position) of the inserted
+    genomes, the rest uniform random ACGT strings.  Order is shuffled; the
+    'present' mask is kept in meta."""
+    rng = rng_for(seed)
+    n_pres = int(round(n * present_frac))
+    lens = sets.lengths().astype(np.int64)
+    ok = np.nonzero(lens >= k)[0]
+    which = ok[rng.integers(0, ok.size, size=n_pres)]
+    starts = sets.offsets[which].astype(np.int64) + (rng.random(n_pres) * (lens[which] - k + 1)).astype(np.int64)
+    out = np.empty((n, k), dtype=np.uint8)
+    step = 1 << 20
+    for lo in range(0, n_pres, step):
+        hi = min(n_pres, lo + step)
+        out[lo:hi] = sets.chars[starts[lo:hi, None] + np.arange(k)[None, :]]
+    out[n_pres:] = to_bytes(random_bases(rng, (n - n_pres) * k)).reshape(n - n_pres, k)
+    perm = rng.permutation(n)
+    out = out[perm]
+    present = np.zeros(n, dtype=bool)
+    present[:n_pres] = True
+    present = present[perm]
+    offsets = np.arange(n + 1, dtype=np.uint64) * np.uint64(k)
+    return SeqBatch(out.reshape(-1), offsets, None, meta=dict(present=present, k=k))
+
+
+def reads(seed: int, sets: SeqBatch, n: int, *, median_len: int, min_len: int, max_len: int,
+          substr_frac: float, read_sub_rate: float = 0.0, lengths: np.ndarray | None = None) -> SeqBatch:
+    """n reads.  A fraction substr_frac are substrings of a uniformly chosen
+    set genome (cut to the genome's length), optionally with further
+    substitutions; the rest are uniform random ACGT.  Lengths are lognormal
+    (clipped) unless given."""
+    rng = rng_for(seed)
+    if lengths is None:
+        lengths = lognormal_lengths(rng, n, median_len, min_len, max_len)
+    kind = rng.random(n) < substr_frac
+    glens = sets.lengths().astype(np.int64)
+    parts = []
+    src = np.full(n, -1, dtype=np.int64)
+    for q in range(n):
+        L = int(lengths[q])
+        if kind[q]:
+            g = int(rng.integers(0, sets.n))
+            L = min(L, int(glens[g]))
+            st = int(sets.offsets[g]) + int(rng.integers(0, int(glens[g]) - L + 1))
+            seq = sets.chars[st:st + L]
+            if read_sub_rate > 0:
+                back = np.searchsorted(_LUT, seq)  # bytes are exactly ACGT here
+                seq = to_bytes(substitute(rng, back.astype(np.uint8), read_sub_rate))
+            parts.append(np.ascontiguousarray(seq))
+            src[q] = g
+        else:
+            parts.append(to_bytes(random_bases(rng, L)))
+    chars, offsets = _csr(parts)
+    return SeqBatch(chars, offsets, None, meta=dict(source_set=src))
+
+
+# ---------------------------------------------------------------- workloads
+
+def config_tiny(seed: int = 1001) -> SeqBatch:
+    """64 sets, each one of 8 random 5 000 bp ancestors with 1% substitutions."""
+    return genome_sets(seed, K=64, n_ancestors=8, ancestor_len=5000)
+
+
+def config_mid(seed: int = 1002) -> SeqBatch:
+    """1 000 sets: lognormal windows (median 200 kbp, 20 kbp - 2 Mbp) of 50
+    random 2 Mbp ancestors, 1% substitutions (about 2.7e8 bases)."""
+    return genome_sets(seed, K=1000, n_ancestors=50, ancestor_len=2_000_000,
+                       median_len=200_000, min_len=20_000, max_len=2_000_000)
+
+
+def config_batched_reads(sets: SeqBatch, n: int = 100_000, seed: int = 3003) -> SeqBatch:
+    """Reads of lognormal length (median 1 000, 100 - 10 000 bp): 70% exact
+    substrings of a set genome, 30% random."""
+    return reads(seed, sets, n, median_len=1000, min_len=100, max_len=10_000, substr_frac=0.7)
+
+
+# Index parameters of the workloads: K sets, B cells, R repetitions, m bits per
+# cell, eta hashes, k-mer length.
+INDEX_TINY = dict(K=64, B=8, R=3, m=1 << 18, eta=2, k=31)
+INDEX_MID = dict(K=1000, B=50, R=4, m=1 << 28, eta=2, k=31)
