@@ -1,0 +1,182 @@
+/*
+ * rambo.h - C ABI of the MI355X (gfx950) RAMBO index.
+ *
+ * RAMBO (Repeated And Merged BloOm Filter, Gupta et al., arXiv 1910.02611)
+ * answers multiple-set-membership queries (Sec. 1): given K sets of terms
+ * and a query term q, return the sets that hold q.  The K sets are split by
+ * R independent partition hashes into B cells each (Sec. 3, Fig. 1); every
+ * cell is one Bloom filter of m bits over the union of its sets (a "BFU").
+ * Insertion is Alg. 1, a term query is Alg. 2 (union over positive cells,
+ * intersection over repetitions), a sequence query is the conjunction over
+ * all of its k-mers (Sec. 3.2.1).
+ *
+ * Terms are k-mers (Sec. 5.2), stored canonically: the smaller of the code
+ * and the code of the reverse complement, where a code packs A=0 C=1 G=2
+ * T=3 into base-4 digits with the first base most significant.  Bytes other
+ * than ACGTacgt break the k-window.
+ *
+ * Hashes (the paper fixes only their kind; these are this library's choice,
+ * fixed so that two implementations agree bit for bit):
+ *   splitmix64 stream from cfg.seed (Steele, Lea, Flood 2014): for r = 0..R-1
+ *   draw a_r = 1 + u mod (2^61-2), b_r = u mod (2^61-1); then for r, j draw
+ *   s_{r,j}.  phi_r(i) = ((a_r i + b_r) mod (2^61-1)) mod B (Carter-Wegman,
+ *   the 2-universal family of Sec. 3.1).  Position j of term x in repetition
+ *   r: floor(mix64(x XOR s_{r,j}) * m / 2^64), mix64 = splitmix64's output
+ *   function; the B cells of one repetition share these positions.
+ *
+ * Index layout in device memory (bit-sliced): repetition r is a block of
+ * words_per_rep 32-bit words; inside it, row p (a Bloom-filter position)
+ * holds the bits of all B cells at that position: bit p*S + b of the block
+ * (word (p*S+b)/32, bit (p*S+b)%32) is bit p of cell b, where the row
+ * stride S = max(8, next power of two >= B).  One row read therefore
+ * returns position p of every cell of the repetition.
+ *
+ * Answers: a K-bit mask per query, W = ceil(K/32) uint32 words; set i is bit
+ * i%32 of word i/32; bits >= K are 0.
+ *
+ * Conventions shared by every call:
+ *  - Array arguments are DEVICE pointers owned by the caller; they must stay
+ *    valid until the work on `stream` has finished.  Sizes are host values.
+ *  - Calls are asynchronous and ordered on `stream` (0 = the null stream).
+ *    One handle serves one host thread at a time.
+ *  - Return 0 on success or a negative RAMBO_E* code.  Errors found on the
+ *    host return at once and enqueue nothing.  Errors found on the device
+ *    (a set id >= K, a code >= 4^k) skip the item (insert) or give it an
+ *    empty answer (query) and set a sticky flag that rambo_sync_status()
+ *    reports and clears.
+ */
+#ifndef RAMBO_H
+#define RAMBO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAMBO_OK 0
+#define RAMBO_EINVAL (-22)     /* bad configuration or argument */
+#define RAMBO_ENOMEM (-12)     /* device allocation failed */
+#define RAMBO_ERANGE (-34)     /* a set id >= K was seen on the device */
+#define RAMBO_EOVERFLOW (-75)  /* output capacity too small */
+#define RAMBO_EHIP (-1000)     /* HIP runtime error; see rambo_last_error */
+#define RAMBO_ECODE (-1001)    /* a k-mer code >= 4^k was seen on the device */
+
+/* Test hook: phi_r(i) = i mod B for every r (with B = K and R = 1 the index
+ * is a plain array of Bloom filters, the special case of Sec. 4.3). */
+#define RAMBO_FLAG_IDENTITY_PARTITION 1u
+
+/* Limits of this implementation. */
+#define RAMBO_MAX_B 4096u
+#define RAMBO_MAX_R 16u
+#define RAMBO_MAX_RETA 32u     /* R * eta */
+
+typedef struct rambo_config {
+    uint32_t K;      /* number of sets, >= 1 */
+    uint32_t B;      /* cells per repetition, 1 <= B <= min(K, RAMBO_MAX_B) */
+    uint32_t R;      /* repetitions, 1 <= R <= RAMBO_MAX_R */
+    uint32_t eta;    /* Bloom-filter hashes per repetition, R*eta <= RAMBO_MAX_RETA */
+    uint32_t k;      /* k-mer length, 1 <= k <= 32 */
+    uint32_t flags;  /* RAMBO_FLAG_* */
+    uint64_t m;      /* bits per Bloom filter (positions per repetition), >= 64 */
+    uint64_t seed;   /* master seed of all hash functions */
+} rambo_config;
+
+typedef struct rambo_info {
+    uint32_t row_bits;       /* S, the row stride in bits */
+    uint32_t mask_words;     /* W = ceil(K/32) */
+    uint64_t words_per_rep;  /* 32-bit words per repetition block */
+    uint64_t index_bytes;    /* R * words_per_rep * 4 */
+    const uint32_t *index;   /* device pointer to the index (owned by the handle) */
+} rambo_info;
+
+typedef struct rambo rambo_t;
+
+/* Create an index: validate cfg, derive the seeds, build phi_r and the cell
+ * membership tables on the device (SetIDs(M[b,r]) of Alg. 2), allocate and
+ * zero the R*B Bloom filters (Alg. 1, first two steps).  Synchronous.
+ * Returns RAMBO_EINVAL for a bad cfg, RAMBO_ENOMEM, RAMBO_EHIP. */
+int rambo_create(const rambo_config *cfg, rambo_t **out);
+
+/* Free the index and every buffer of the handle after synchronising the
+ * device.  NULL is a no-op. */
+void rambo_destroy(rambo_t *h);
+
+/* Alg. 1 from k-mer codes.  Set set_ids[s] (s < n_sets) receives the codes
+ * codes[offsets[s] .. offsets[s+1]); offsets has n_sets+1 entries,
+ * non-decreasing, with offsets[n_sets] <= n_codes.  Codes need not be
+ * canonical.  Repeated calls OR into the same index (streaming updates,
+ * Sec. 3.1); order does not matter.  Device errors: RAMBO_ERANGE (set id),
+ * RAMBO_ECODE (code >= 4^k) - the item is skipped. */
+int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets,
+                       uint64_t n_sets, const uint64_t *codes, uint64_t n_codes,
+                       hipStream_t stream);
+
+/* Alg. 1 from sequences: every valid k-window of sequence s (bytes
+ * chars[offsets[s] .. offsets[s+1])) is inserted into set set_ids[s].
+ * Windows never span two sequences.  offsets: n_seqs+1 entries,
+ * non-decreasing, offsets[n_seqs] <= n_chars. */
+int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets,
+                      uint64_t n_seqs, const uint8_t *chars, uint64_t n_chars,
+                      hipStream_t stream);
+
+/* Alg. 2 for n k-mer codes: out_masks[q*W .. q*W+W) receives the answer of
+ * codes[q].  A code >= 4^k gets an empty mask (and RAMBO_ECODE). */
+int rambo_query_kmers(rambo_t *h, const uint64_t *codes, uint64_t n,
+                      uint32_t *out_masks, hipStream_t stream);
+
+/* Sec. 3.2.1 for n_reads sequences (bytes chars[offsets[q] .. offsets[q+1])):
+ * the answer is the intersection of the answers of all valid k-windows of
+ * the read.  A read with no valid window answers the empty set.
+ * out_masks: n_reads*W words.  out_nkmers (may be NULL): number of valid
+ * windows of each read. */
+int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
+                     const uint8_t *chars, uint64_t n_chars, uint32_t *out_masks,
+                     uint32_t *out_nkmers, hipStream_t stream);
+
+/* ---- support ---------------------------------------------------------- */
+
+/* Canonical code of the k-window starting at every byte (the term
+ * extraction of Sec. 3.2.1 / Sec. 5.2): out_codes[p] for p < n_chars, or
+ * UINT64_MAX where no valid window of the same sequence starts at p. */
+int rambo_extract_kmers(rambo_t *h, const uint64_t *offsets, uint64_t n_seqs,
+                        const uint8_t *chars, uint64_t n_chars, uint64_t *out_codes,
+                        hipStream_t stream);
+
+/* The "plain" path: the same answers as rambo_query_kmers /
+ * rambo_query_seqs, computed by one kernel launch per query. */
+int rambo_query_kmers_plain(rambo_t *h, const uint64_t *codes, uint64_t n,
+                            uint32_t *out_masks, hipStream_t stream);
+int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
+                           const uint8_t *chars, uint64_t n_chars, uint32_t *out_masks,
+                           uint32_t *out_nkmers, hipStream_t stream);
+
+/* Zero every Bloom filter (an empty index with the same hashes). */
+int rambo_clear(rambo_t *h, hipStream_t stream);
+
+/* Layout of the index (see above). */
+int rambo_get_info(const rambo_t *h, rambo_info *out);
+
+/* Copy n_words words of the index, starting at word word_offset, to dst
+ * (device or host memory; asynchronous on `stream` for device memory).
+ * RAMBO_EINVAL if the range is outside the index. */
+int rambo_copy_index(rambo_t *h, uint64_t word_offset, uint64_t n_words, void *dst, hipStream_t stream);
+
+/* phi_r(i) for all r, i, copied to host memory out[r*K + i] (R*K entries).
+ * Synchronous. */
+int rambo_get_partition(rambo_t *h, uint32_t *out);
+
+/* Synchronise `stream`, then return and clear the sticky device error:
+ * RAMBO_OK, RAMBO_ERANGE or RAMBO_ECODE (the first one seen). */
+int rambo_sync_status(rambo_t *h, hipStream_t stream);
+
+/* Text of the last error of the handle (or of the last failed create when
+ * h is NULL). */
+const char *rambo_last_error(const rambo_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAMBO_H */

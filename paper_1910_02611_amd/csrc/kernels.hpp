@@ -1,0 +1,453 @@
+// RAMBO kernels for gfx950.
+//
+//  k_build_partition  phi_r(i) for all (r, i)                     (Alg. 1, line 1)
+//  k_build_cellmask   SetIDs(M[b,r]) as K-bit masks                 (Alg. 2)
+//  k_extract          canonical code of every k-window            (Sec. 3.2.1, Sec. 5.2)
+//  k_insert_seqs      windows of set genomes -> atomicOr into rows (Alg. 1)
+//  k_insert_kmers     k-mer codes of sets -> atomicOr into rows    (Alg. 1)
+//  k_query_kmers      R*eta row gathers, AND, K-bit expansion      (Alg. 2)
+//  k_query_seqs       one wave per read: AND of group masks over all windows,
+//                     early exit on an empty repetition, one expansion
+//                     (Sec. 3.2.1)
+#pragma once
+
+#include "device.hpp"
+
+namespace rambo_dev {
+
+// ---------------------------------------------------------------- set-up
+
+struct PartitionArgs {
+    uint64_t a[RAMBO_MAX_R];
+    uint64_t b[RAMBO_MAX_R];
+};
+
+// (a*i + b) mod (2^61 - 1), from the 128-bit product: 2^64 = 8 (mod P) and
+// 2^61 = 1 (mod P), so the high part folds in with weight 8.
+__device__ __forceinline__ uint64_t affine_mod_p61(uint64_t a, uint64_t i, uint64_t b)
+{
+    constexpr uint64_t P = (1ull << 61) - 1;
+    uint64_t lo = a * i;
+    uint64_t hi = __umul64hi(a, i);
+    const uint64_t lo2 = lo + b;
+    hi += (lo2 < lo) ? 1u : 0u;
+    lo = lo2;
+    uint64_t s = (lo & P) + ((lo >> 61) | (hi << 3));
+    s = (s & P) + (s >> 61);
+    return s >= P ? s - P : s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_build_partition(PartitionArgs A, uint32_t K, uint32_t B, uint32_t R,
+                                                            uint32_t identity, uint16_t *phi)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (uint64_t)K * R)
+        return;
+    const uint32_t r = (uint32_t)(t / K), i = (uint32_t)(t % K);
+    const uint64_t v = identity ? i : affine_mod_p61(A.a[r], i, A.b[r]);
+    phi[t] = (uint16_t)(v % B);
+}
+
+// Thread (r, w) owns word w of every cell mask of repetition r.
+__global__ __launch_bounds__(kBlock) void k_build_cellmask(const uint16_t *phi, uint32_t K, uint32_t B, uint32_t R,
+                                                           uint32_t W, uint32_t *cellmask)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (uint64_t)R * W)
+        return;
+    const uint32_t r = (uint32_t)(t / W), w = (uint32_t)(t % W);
+    for (uint32_t bit = 0; bit < 32; ++bit) {
+        const uint32_t i = w * 32 + bit;
+        if (i >= K)
+            break;
+        const uint32_t cell = phi[(uint64_t)r * K + i];
+        cellmask[((uint64_t)r * B + cell) * W + w] |= 1u << bit;
+    }
+}
+
+// ------------------------------------------------------- window walking
+
+// Cursor over the CSR of sequences: the sequence s that holds byte p.
+struct SeqCursor {
+    uint64_t s, beg, end;
+    __device__ __forceinline__ void init(const uint64_t *offsets, uint64_t n, uint64_t p)
+    {
+        s = seq_of(offsets, n, p);
+        beg = offsets[s];
+        end = offsets[s + 1];
+    }
+    __device__ __forceinline__ void advance(const uint64_t *offsets, uint64_t n, uint64_t p)
+    {
+        while (p >= end && s + 1 < n) {
+            ++s;
+            beg = offsets[s];
+            end = offsets[s + 1];
+        }
+    }
+};
+
+// The wave visits the windows starting at bytes [p0, p_end) of a CSR of
+// sequences, 64 per step (lane l takes byte p + l), and calls
+// f(p, valid, canonical code, sequence) for each.
+template <class F>
+__device__ __forceinline__ void wave_windows(const uint64_t *offsets, uint64_t n_seqs, const uint8_t *chars,
+                                             uint64_t n_chars, uint64_t p0, uint64_t p_end, uint32_t k,
+                                             uint64_t kmask, F &&f)
+{
+    const uint32_t lane = lane_id();
+    SeqCursor ca;
+    ca.init(offsets, n_seqs, p0);
+    SeqCursor cb = ca;
+    auto classify = [&](SeqCursor &c, uint64_t p, uint32_t &v, bool &bad, bool &st) {
+        c.advance(offsets, n_seqs, p);
+        const bool in = p >= c.beg && p < c.end && p < n_chars;
+        v = in ? base_value(chars[p]) : 4u;
+        bad = v > 3u;
+        st = in && p == c.beg;
+    };
+    uint32_t v;
+    bool bad, st;
+    classify(ca, p0 + lane, v, bad, st);
+    Group A = pack_group(v, bad, st);
+    cb = ca;
+    for (uint64_t p = p0; p < p_end; p += kWave) {
+        classify(cb, p + kWave + lane, v, bad, st);
+        const Group Bg = pack_group(v, bad, st);
+        const uint64_t pw = p + lane;
+        uint64_t canon = 0;
+        const bool valid = window_code(A, Bg, lane, k, kmask, canon);
+        if (pw < p_end)
+            f(pw, valid, canon, ca.s);
+        A = Bg;
+        ca = cb;
+    }
+}
+
+// One wave per chunk of `chunk` bytes (a multiple of 64).
+__global__ __launch_bounds__(kBlock) void k_extract(uint32_t k, uint64_t kmask, const uint64_t *offsets,
+                                                    uint64_t n_seqs, const uint8_t *chars, uint64_t n_chars,
+                                                    uint64_t chunk, uint64_t *out)
+{
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const uint64_t p0 = wave * chunk;
+    if (p0 >= n_chars)
+        return;
+    const uint64_t pe = min(p0 + chunk, n_chars);
+    wave_windows(offsets, n_seqs, chars, n_chars, p0, pe, k, kmask,
+                 [&](uint64_t p, bool valid, uint64_t canon, uint64_t) { out[p] = valid ? canon : ~0ull; });
+}
+
+// ------------------------------------------------------------- insertion
+
+// Alg. 1: every valid window of sequence s goes into the cell phi_r(set) of
+// each repetition r, at its eta positions.
+__global__ __launch_bounds__(kBlock) void k_insert_seqs(Params P, const uint32_t *set_ids, const uint64_t *offsets,
+                                                        uint64_t n_seqs, const uint8_t *chars, uint64_t n_chars,
+                                                        uint64_t chunk)
+{
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const uint64_t p0 = wave * chunk;
+    if (p0 >= n_chars)
+        return;
+    const uint64_t pe = min(p0 + chunk, n_chars);
+    wave_windows(offsets, n_seqs, chars, n_chars, p0, pe, P.k, P.kmask,
+                 [&](uint64_t, bool valid, uint64_t x, uint64_t s) {
+                     if (!valid)
+                         return;
+                     const uint32_t set = set_ids[s];
+                     if (set >= P.K) {
+                         atomicOr(P.err, kErrSetId);
+                         return;
+                     }
+                     for (uint32_t r = 0; r < P.R; ++r) {
+                         const uint32_t col = P.phi[(uint64_t)r * P.K + set];
+                         for (uint32_t j = 0; j < P.eta; ++j)
+                             set_cell_bit(P, r, bf_position(x, P.seeds[r * P.eta + j], P), col);
+                     }
+                 });
+}
+
+// Alg. 1 from codes: thread per code; the set of code c is the s with
+// offsets[s] <= c < offsets[s+1].
+__global__ __launch_bounds__(kBlock) void k_insert_kmers(Params P, const uint32_t *set_ids, const uint64_t *offsets,
+                                                         uint64_t n_sets, const uint64_t *codes, uint64_t n_codes)
+{
+    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t wave_first = idx - lane_id();
+    if (wave_first >= n_codes)
+        return;
+    SeqCursor c;
+    c.init(offsets, n_sets, wave_first);
+    c.advance(offsets, n_sets, idx);
+    if (idx >= n_codes || idx < c.beg || idx >= c.end)
+        return;
+    const uint32_t set = set_ids[c.s];
+    const uint64_t code = codes[idx];
+    if (set >= P.K) {
+        atomicOr(P.err, kErrSetId);
+        return;
+    }
+    if (code > P.kmask) {
+        atomicOr(P.err, kErrCode);
+        return;
+    }
+    const uint64_t x = canonical(code, P.k);
+    for (uint32_t r = 0; r < P.R; ++r) {
+        const uint32_t col = P.phi[(uint64_t)r * P.K + set];
+        for (uint32_t j = 0; j < P.eta; ++j)
+            set_cell_bit(P, r, bf_position(x, P.seeds[r * P.eta + j], P), col);
+    }
+}
+
+// ------------------------------------------------------------------ probe
+
+// Group masks of term x for row words [w0, w0+L): g[r][.] = AND over j of
+// row pos_{r,j}(x) of repetition r (Alg. 2, "Q in BF(M[b,r])" for all b of
+// repetition r at once).  Compile-time R_T/ETA_T issue all R*eta loads
+// before the first use; R_T == 0 is the run-time-sized path.
+template <int SW, int L, int R_T, int ETA_T>
+struct Probe {
+    static constexpr int RN = R_T > 0 ? R_T : 1;
+    // Fixed-size path: every load in flight at once.
+    __device__ __forceinline__ static void run(const Params &P, uint64_t x, int w0, bool ok, uint32_t (&g)[RN][L])
+    {
+        static_assert(R_T > 0 && ETA_T > 0, "fixed path");
+        uint32_t rows[R_T * ETA_T][L];
+#pragma unroll
+        for (int t = 0; t < R_T * ETA_T; ++t) {
+            if (ok) {
+                load_row<SW, L>(P, t / ETA_T, bf_position(x, P.seeds[t], P), w0, rows[t]);
+            } else {
+#pragma unroll
+                for (int w = 0; w < L; ++w)
+                    rows[t][w] = 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R_T; ++r) {
+#pragma unroll
+            for (int w = 0; w < L; ++w) {
+                uint32_t a = rows[r * ETA_T][w];
+#pragma unroll
+                for (int j = 1; j < ETA_T; ++j)
+                    a &= rows[r * ETA_T + j][w];
+                g[r][w] = a;
+            }
+        }
+    }
+};
+
+// Run-time R and eta: one repetition at a time.
+template <int SW, int L>
+__device__ __forceinline__ void probe_rep(const Params &P, uint64_t x, uint32_t r, int w0, bool ok, uint32_t (&acc)[L])
+{
+#pragma unroll
+    for (int w = 0; w < L; ++w)
+        acc[w] = ok ? ~0u : 0u;
+    if (!ok)
+        return;
+    for (uint32_t j = 0; j < P.eta; ++j) {
+        uint32_t row[L];
+        load_row<SW, L>(P, r, bf_position(x, P.seeds[r * P.eta + j], P), w0, row);
+#pragma unroll
+        for (int w = 0; w < L; ++w)
+            acc[w] &= row[w];
+    }
+}
+
+// K-bit answer word w from the group masks g (R x SW words, uniform across
+// the lanes that share it): AND over r of the union of SetIDs(M[b,r]) over
+// the cells b set in g_r (Alg. 2).
+__device__ __forceinline__ uint32_t expand_word(const Params &P, const uint32_t *g, uint32_t SW, uint32_t w)
+{
+    uint32_t acc = ~0u;
+    for (uint32_t r = 0; r < P.R; ++r) {
+        uint32_t u = 0;
+        for (uint32_t sw = 0; sw < SW; ++sw) {
+            uint32_t bits = g[r * SW + sw];
+            while (bits) {
+                const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1;
+                u |= P.cellmask[((uint64_t)r * P.B + b) * P.W + w];
+            }
+        }
+        acc &= u;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ bool any_rep_empty(const uint32_t *g, uint32_t R, uint32_t SW)
+{
+    for (uint32_t r = 0; r < R; ++r) {
+        uint32_t o = 0;
+        for (uint32_t sw = 0; sw < SW; ++sw)
+            o |= g[r * SW + sw];
+        if (!o)
+            return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------- term queries
+
+// Alg. 2 for a batch of codes.  G lanes share one query when a row is wider
+// than 4 words; each lane gathers L words of each of the R*eta rows.  The
+// group masks go to LDS; then sub-groups of the wave expand one query each
+// into its W answer words with coalesced stores.
+template <int SW, int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t *codes, uint64_t n, uint32_t *out)
+{
+    constexpr int G = SW > 4 ? SW / 4 : 1;
+    constexpr int L = SW / G;
+    constexpr int QPW = kWave / G;
+    constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
+    __shared__ uint32_t gs[kWavesPerBlock * QPW * RMAX * SW];
+
+    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t ql = lane / G, part = lane % G;
+    const uint64_t qbase = ((uint64_t)blockIdx.x * kWavesPerBlock + wv) * QPW;
+    const uint64_t q = qbase + ql;
+    uint32_t *gq = gs + (wv * QPW + ql) * RMAX * SW;
+
+    const bool live = q < n;
+    const uint64_t code = live ? codes[q] : 0;
+    const bool ok = live && code <= P.kmask;
+    if (live && !ok && part == 0)
+        atomicOr(P.err, kErrCode);
+    const uint64_t x = canonical(code & P.kmask, P.k);
+
+    if constexpr (R_T > 0) {
+        uint32_t g[R_T][L];
+        Probe<SW, L, R_T, ETA_T>::run(P, x, part * L, ok, g);
+#pragma unroll
+        for (int r = 0; r < R_T; ++r)
+#pragma unroll
+            for (int w = 0; w < L; ++w)
+                gq[r * SW + part * L + w] = g[r][w];
+    } else {
+        for (uint32_t r = 0; r < R; ++r) {
+            uint32_t acc[L];
+            probe_rep<SW, L>(P, x, r, part * L, ok, acc);
+#pragma unroll
+            for (int w = 0; w < L; ++w)
+                gq[r * SW + part * L + w] = acc[w];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // Expansion: sub-groups of WG lanes, one query per sub-group at a time.
+    uint32_t WG = 1;
+    while (WG < P.W && WG < (uint32_t)kWave)
+        WG <<= 1;
+    const uint32_t nsg = kWave / WG, sg = lane / WG, wl = lane % WG;
+    for (uint32_t qi = sg; qi < (uint32_t)QPW; qi += nsg) {
+        const uint64_t q2 = qbase + qi;
+        if (q2 >= n)
+            break;
+        const uint32_t *g2 = gs + (wv * QPW + qi) * RMAX * SW;
+        const bool empty = any_rep_empty(g2, R, SW);
+        uint32_t *o = out + q2 * P.W;
+        for (uint32_t w = wl; w < P.W; w += WG)
+            o[w] = empty ? 0u : expand_word(P, g2, SW, w);
+    }
+}
+
+// ------------------------------------------------------ sequence queries
+
+// Sec. 3.2.1: one wave per read.  Each step takes 64 windows (one per lane),
+// gathers their rows, ANDs the group masks over the lanes and into the read's
+// running masks G (LDS), and stops probing once some repetition is empty (the
+// first conclusive FALSE).  Valid windows are still counted to the end.  The
+// read is expanded once: by the partition identity, AND over k-mers of the
+// expanded answers equals the expansion of the AND of the group masks.
+template <int SW, int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t *offsets, uint64_t n_reads,
+                                                       const uint8_t *chars, uint64_t n_chars, uint32_t *out,
+                                                       uint32_t *out_nk)
+{
+    constexpr int L = SW < 4 ? SW : 4;
+    constexpr int NSL = SW / L;
+    constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
+    __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
+
+    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (q >= n_reads)
+        return;
+    uint32_t *G = Gs[wv];
+    for (uint32_t i = lane; i < R * SW; i += kWave)
+        G[i] = ~0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    uint64_t p0 = offsets[q];
+    const uint64_t pe = min(offsets[q + 1], n_chars);
+    if (p0 > pe)
+        p0 = pe;
+    const uint64_t kmask = P.kmask;
+    auto read_byte = [&](uint64_t p, uint32_t &v, bool &bad) {
+        v = p < pe ? base_value(chars[p]) : 4u;
+        bad = v > 3u;
+    };
+    uint32_t v;
+    bool bad;
+    read_byte(p0 + lane, v, bad);
+    Group A = pack_group(v, bad, false);
+    uint32_t nk = 0;
+    bool dead = false;
+    for (uint64_t p = p0; p < pe; p += kWave) {
+        read_byte(p + kWave + lane, v, bad);
+        const Group Bg = pack_group(v, bad, false);
+        uint64_t x = 0;
+        const bool valid = (p + lane < pe) && window_code(A, Bg, lane, P.k, kmask, x);
+        nk += (uint32_t)__popcll(__ballot(valid));
+        if (!dead) {
+#pragma unroll 1
+            for (int sl = 0; sl < NSL; ++sl) {
+                if constexpr (R_T > 0) {
+                    uint32_t g[R_T][L];
+                    Probe<SW, L, R_T, ETA_T>::run(P, x, sl * L, valid, g);
+#pragma unroll
+                    for (int r = 0; r < R_T; ++r)
+#pragma unroll
+                        for (int w = 0; w < L; ++w) {
+                            const uint32_t a = wave_and(valid ? g[r][w] : ~0u);
+                            if (lane == 0)
+                                G[r * SW + sl * L + w] &= a;
+                        }
+                } else {
+                    for (uint32_t r = 0; r < R; ++r) {
+                        uint32_t acc[L];
+                        probe_rep<SW, L>(P, x, r, sl * L, valid, acc);
+#pragma unroll
+                        for (int w = 0; w < L; ++w) {
+                            const uint32_t a = wave_and(valid ? acc[w] : ~0u);
+                            if (lane == 0)
+                                G[r * SW + sl * L + w] &= a;
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            dead = any_rep_empty(G, R, SW);
+        }
+        A = Bg;
+    }
+    if (out_nk && lane == 0)
+        out_nk[q] = nk;
+    uint32_t *o = out + q * P.W;
+    const bool empty = dead || nk == 0;
+    for (uint32_t w = lane; w < P.W; w += kWave)
+        o[w] = empty ? 0u : expand_word(P, G, SW, w);
+}
+
+}  // namespace rambo_dev

@@ -1,0 +1,445 @@
+// Host runtime and C ABI of the RAMBO index (declared in include/rambo.h).
+//
+// The handle owns the bit-sliced index, the partition table phi, the cell
+// membership masks and a sticky device error word.  Every call checks its
+// arguments on the host, then enqueues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.hpp"
+#include "rambo.h"
+
+using namespace rambo_dev;
+
+struct rambo {
+    rambo_config cfg{};
+    Params P{};
+    uint32_t S = 0, SW = 0, W = 0;
+    uint64_t words_per_rep = 0;
+    uint64_t index_bytes = 0;
+    uint32_t *index = nullptr;
+    uint16_t *phi = nullptr;
+    uint32_t *cellmask = nullptr;
+    int *err = nullptr;
+    std::string last_error;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr uint64_t kP61 = (1ull << 61) - 1;
+constexpr uint64_t kChunk = 1024;   // bytes per wave in the window walkers
+
+uint64_t splitmix64_next(uint64_t &state)
+{
+    state += 0x9E3779B97F4A7C15ull;
+    return mix64(state);
+}
+
+int fail(rambo *h, int code, const std::string &msg)
+{
+    if (h)
+        h->last_error = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int hip_check(rambo *h, hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return RAMBO_OK;
+    return fail(h, RAMBO_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int launch_check(rambo *h, const char *what)
+{
+    return hip_check(h, hipGetLastError(), what);
+}
+
+uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- dispatch
+
+template <int SW, int R_T, int ETA_T>
+void launch_query_kmers_t(const rambo *h, const uint64_t *codes, uint64_t n, uint32_t *out, hipStream_t st)
+{
+    constexpr int G = SW > 4 ? SW / 4 : 1;
+    constexpr uint64_t QPB = kBlock / G;
+    hipLaunchKernelGGL((k_query_kmers<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n, QPB)), dim3(kBlock), 0, st, h->P,
+                       codes, n, out);
+}
+
+template <int SW, int R_T, int ETA_T>
+void launch_query_seqs_t(const rambo *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
+                         uint64_t n_chars, uint32_t *out, uint32_t *nk, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_query_seqs<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_reads, kWavesPerBlock)),
+                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk);
+}
+
+// Row widths of the workloads get kernels with compile-time R and eta (all
+// gathers of a term in flight at once); everything else takes the run-time
+// path.
+template <int SW>
+constexpr bool kSpecialised = SW == 1 || SW == 2 || SW == 8 || SW == 32;
+
+template <int SW, class F>
+void with_shape(const rambo *h, F &&f)
+{
+    const uint32_t R = h->cfg.R, E = h->cfg.eta;
+    if constexpr (kSpecialised<SW>) {
+        if (E == 2) {
+            switch (R) {
+            case 3: f.template operator()<SW, 3, 2>(); return;
+            case 4: f.template operator()<SW, 4, 2>(); return;
+            case 5: f.template operator()<SW, 5, 2>(); return;
+            case 6: f.template operator()<SW, 6, 2>(); return;
+            default: break;
+            }
+        }
+    }
+    f.template operator()<SW, 0, 0>();
+}
+
+template <class F>
+void with_row_words(const rambo *h, F &&f)
+{
+    switch (h->SW) {
+    case 1: with_shape<1>(h, f); break;
+    case 2: with_shape<2>(h, f); break;
+    case 4: with_shape<4>(h, f); break;
+    case 8: with_shape<8>(h, f); break;
+    case 16: with_shape<16>(h, f); break;
+    case 32: with_shape<32>(h, f); break;
+    case 64: with_shape<64>(h, f); break;
+    default: with_shape<128>(h, f); break;
+    }
+}
+
+struct QueryKmersLaunch {
+    const rambo *h;
+    const uint64_t *codes;
+    uint64_t n;
+    uint32_t *out;
+    hipStream_t st;
+    template <int SW, int R_T, int ETA_T>
+    void operator()() const { launch_query_kmers_t<SW, R_T, ETA_T>(h, codes, n, out, st); }
+};
+
+struct QuerySeqsLaunch {
+    const rambo *h;
+    const uint64_t *offsets;
+    uint64_t n_reads;
+    const uint8_t *chars;
+    uint64_t n_chars;
+    uint32_t *out;
+    uint32_t *nk;
+    hipStream_t st;
+    template <int SW, int R_T, int ETA_T>
+    void operator()() const { launch_query_seqs_t<SW, R_T, ETA_T>(h, offsets, n_reads, chars, n_chars, out, nk, st); }
+};
+
+uint32_t next_pow2(uint32_t v)
+{
+    uint32_t p = 1;
+    while (p < v)
+        p <<= 1;
+    return p;
+}
+
+uint32_t log2_exact(uint64_t v)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < v)
+        ++l;
+    return l;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
+{
+    if (!out)
+        return fail(nullptr, RAMBO_EINVAL, "rambo_create: out is NULL");
+    *out = nullptr;
+    if (!cfg)
+        return fail(nullptr, RAMBO_EINVAL, "rambo_create: cfg is NULL");
+    const rambo_config c = *cfg;
+    if (c.K < 1 || c.B < 1 || c.B > c.K || c.B > RAMBO_MAX_B || c.R < 1 || c.R > RAMBO_MAX_R || c.eta < 1 ||
+        (uint64_t)c.R * c.eta > RAMBO_MAX_RETA || c.k < 1 || c.k > 32 || c.m < 64 || c.m > (1ull << 48) ||
+        (c.flags & ~RAMBO_FLAG_IDENTITY_PARTITION))
+        return fail(nullptr, RAMBO_EINVAL, "rambo_create: configuration out of range");
+
+    rambo *h = new (std::nothrow) rambo();
+    if (!h)
+        return fail(nullptr, RAMBO_ENOMEM, "rambo_create: host allocation failed");
+    h->cfg = c;
+    h->S = next_pow2(c.B < 8 ? 8u : c.B);
+    h->SW = h->S >= 32 ? h->S / 32 : 1;
+    h->W = (c.K + 31) / 32;
+    // words per repetition, rounded up to 4 so every row block is 16-byte aligned
+    h->words_per_rep = div_up(div_up(c.m * h->S, 32), 4) * 4;
+    h->index_bytes = (uint64_t)c.R * h->words_per_rep * 4;
+
+    // Seeds: one splitmix64 stream, in the documented order.
+    uint64_t st = c.seed;
+    PartitionArgs pa{};
+    for (uint32_t r = 0; r < c.R; ++r) {
+        pa.a[r] = 1 + splitmix64_next(st) % (kP61 - 1);
+        pa.b[r] = splitmix64_next(st) % kP61;
+    }
+    Params &P = h->P;
+    for (uint32_t r = 0; r < c.R; ++r)
+        for (uint32_t j = 0; j < c.eta; ++j) {
+            const uint32_t t = r * c.eta + j;
+            P.seeds[t] = splitmix64_next(st);
+            P.rep_of[t] = (uint8_t)r;
+            if (j == 0)
+                P.rep_first |= 1u << t;
+            if (j + 1 == c.eta)
+                P.rep_last |= 1u << t;
+        }
+    P.m = c.m;
+    P.words_per_rep = h->words_per_rep;
+    P.kmask = c.k >= 32 ? ~0ull : ((1ull << (2 * c.k)) - 1);
+    P.K = c.K;
+    P.B = c.B;
+    P.R = c.R;
+    P.eta = c.eta;
+    P.k = c.k;
+    P.W = h->W;
+    P.S_log2 = log2_exact(h->S);
+    P.m_log2 = ((c.m & (c.m - 1)) == 0) ? log2_exact(c.m) : 0;
+
+    int rc = RAMBO_OK;
+    const uint64_t cm_words = (uint64_t)c.R * c.B * h->W;
+    if (hipMalloc(&h->index, h->index_bytes) != hipSuccess || hipMalloc(&h->phi, (uint64_t)c.R * c.K * 2) != hipSuccess ||
+        hipMalloc(&h->cellmask, cm_words * 4) != hipSuccess || hipMalloc(&h->err, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        g_create_error = "rambo_create: device allocation failed";
+        rambo_destroy(h);
+        return RAMBO_ENOMEM;
+    }
+    P.index = h->index;
+    P.phi = h->phi;
+    P.cellmask = h->cellmask;
+    P.err = h->err;
+    if ((rc = hip_check(h, hipMemset(h->index, 0, h->index_bytes), "memset index")) ||
+        (rc = hip_check(h, hipMemset(h->cellmask, 0, cm_words * 4), "memset cellmask")) ||
+        (rc = hip_check(h, hipMemset(h->err, 0, sizeof(int)), "memset err"))) {
+        g_create_error = h->last_error;
+        rambo_destroy(h);
+        return rc;
+    }
+    const uint64_t nphi = (uint64_t)c.R * c.K;
+    hipLaunchKernelGGL(k_build_partition, dim3((uint32_t)div_up(nphi, kBlock)), dim3(kBlock), 0, 0, pa, c.K, c.B,
+                       c.R, (uint32_t)(c.flags & RAMBO_FLAG_IDENTITY_PARTITION), h->phi);
+    const uint64_t ncm = (uint64_t)c.R * h->W;
+    hipLaunchKernelGGL(k_build_cellmask, dim3((uint32_t)div_up(ncm, kBlock)), dim3(kBlock), 0, 0, h->phi, c.K, c.B,
+                       c.R, h->W, h->cellmask);
+    if ((rc = launch_check(h, "build tables")) || (rc = hip_check(h, hipDeviceSynchronize(), "build tables"))) {
+        g_create_error = h->last_error;
+        rambo_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return RAMBO_OK;
+}
+
+extern "C" void rambo_destroy(rambo_t *h)
+{
+    if (!h)
+        return;
+    (void)hipDeviceSynchronize();
+    if (h->index)
+        (void)hipFree(h->index);
+    if (h->phi)
+        (void)hipFree(h->phi);
+    if (h->cellmask)
+        (void)hipFree(h->cellmask);
+    if (h->err)
+        (void)hipFree(h->err);
+    delete h;
+}
+
+extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_sets,
+                                  const uint64_t *codes, uint64_t n_codes, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n_sets == 0 || n_codes == 0)
+        return RAMBO_OK;
+    if (!set_ids || !offsets || !codes)
+        return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
+    hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,
+                       set_ids, offsets, n_sets, codes, n_codes);
+    return launch_check(h, "rambo_insert_kmers");
+}
+
+extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
+                                 const uint8_t *chars, uint64_t n_chars, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n_seqs == 0 || n_chars == 0)
+        return RAMBO_OK;
+    if (!set_ids || !offsets || !chars)
+        return fail(h, RAMBO_EINVAL, "rambo_insert_seqs: NULL array");
+    const uint64_t waves = div_up(n_chars, kChunk);
+    hipLaunchKernelGGL(k_insert_seqs, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P,
+                       set_ids, offsets, n_seqs, chars, n_chars, kChunk);
+    return launch_check(h, "rambo_insert_seqs");
+}
+
+extern "C" int rambo_query_kmers(rambo_t *h, const uint64_t *codes, uint64_t n, uint32_t *out_masks,
+                                 hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n == 0)
+        return RAMBO_OK;
+    if (!codes || !out_masks)
+        return fail(h, RAMBO_EINVAL, "rambo_query_kmers: NULL array");
+    with_row_words(h, QueryKmersLaunch{h, codes, n, out_masks, stream});
+    return launch_check(h, "rambo_query_kmers");
+}
+
+extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
+                                uint64_t n_chars, uint32_t *out_masks, uint32_t *out_nkmers, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n_reads == 0)
+        return RAMBO_OK;
+    if (!offsets || !out_masks || (n_chars > 0 && !chars))
+        return fail(h, RAMBO_EINVAL, "rambo_query_seqs: NULL array");
+    with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream});
+    return launch_check(h, "rambo_query_seqs");
+}
+
+extern "C" int rambo_extract_kmers(rambo_t *h, const uint64_t *offsets, uint64_t n_seqs, const uint8_t *chars,
+                                   uint64_t n_chars, uint64_t *out_codes, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n_chars == 0)
+        return RAMBO_OK;
+    if (!chars || !out_codes || (n_seqs > 0 && !offsets))
+        return fail(h, RAMBO_EINVAL, "rambo_extract_kmers: NULL array");
+    if (n_seqs == 0)
+        return hip_check(h, hipMemsetAsync(out_codes, 0xFF, n_chars * 8, stream), "rambo_extract_kmers");
+    const uint64_t waves = div_up(n_chars, kChunk);
+    hipLaunchKernelGGL(k_extract, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->cfg.k,
+                       h->P.kmask, offsets, n_seqs, chars, n_chars, kChunk, out_codes);
+    return launch_check(h, "rambo_extract_kmers");
+}
+
+extern "C" int rambo_query_kmers_plain(rambo_t *h, const uint64_t *codes, uint64_t n, uint32_t *out_masks,
+                                       hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n == 0)
+        return RAMBO_OK;
+    if (!codes || !out_masks)
+        return fail(h, RAMBO_EINVAL, "rambo_query_kmers_plain: NULL array");
+    for (uint64_t q = 0; q < n; ++q)
+        with_row_words(h, QueryKmersLaunch{h, codes + q, 1, out_masks + q * h->W, stream});
+    return launch_check(h, "rambo_query_kmers_plain");
+}
+
+extern "C" int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
+                                      uint64_t n_chars, uint32_t *out_masks, uint32_t *out_nkmers,
+                                      hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n_reads == 0)
+        return RAMBO_OK;
+    if (!offsets || !out_masks || (n_chars > 0 && !chars))
+        return fail(h, RAMBO_EINVAL, "rambo_query_seqs_plain: NULL array");
+    for (uint64_t q = 0; q < n_reads; ++q)
+        with_row_words(h, QuerySeqsLaunch{h, offsets + q, 1, chars, n_chars, out_masks + q * h->W,
+                                          out_nkmers ? out_nkmers + q : nullptr, stream});
+    return launch_check(h, "rambo_query_seqs_plain");
+}
+
+extern "C" int rambo_clear(rambo_t *h, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    return hip_check(h, hipMemsetAsync(h->index, 0, h->index_bytes, stream), "rambo_clear");
+}
+
+extern "C" int rambo_get_info(const rambo_t *h, rambo_info *out)
+{
+    if (!h || !out)
+        return RAMBO_EINVAL;
+    out->row_bits = h->S;
+    out->mask_words = h->W;
+    out->words_per_rep = h->words_per_rep;
+    out->index_bytes = h->index_bytes;
+    out->index = h->index;
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_copy_index(rambo_t *h, uint64_t word_offset, uint64_t n_words, void *dst, hipStream_t stream)
+{
+    if (!h || (n_words && !dst))
+        return RAMBO_EINVAL;
+    const uint64_t total = h->index_bytes / 4;
+    if (word_offset > total || n_words > total - word_offset)
+        return fail(h, RAMBO_EINVAL, "rambo_copy_index: range outside the index");
+    if (n_words == 0)
+        return RAMBO_OK;
+    return hip_check(h, hipMemcpyAsync(dst, h->index + word_offset, n_words * 4, hipMemcpyDefault, stream),
+                     "rambo_copy_index");
+}
+
+extern "C" int rambo_get_partition(rambo_t *h, uint32_t *out)
+{
+    if (!h || !out)
+        return RAMBO_EINVAL;
+    const uint64_t n = (uint64_t)h->cfg.R * h->cfg.K;
+    uint16_t *tmp = new (std::nothrow) uint16_t[n];
+    if (!tmp)
+        return fail(h, RAMBO_ENOMEM, "rambo_get_partition: host allocation failed");
+    const int rc = hip_check(h, hipMemcpy(tmp, h->phi, n * 2, hipMemcpyDeviceToHost), "rambo_get_partition");
+    if (rc == RAMBO_OK)
+        for (uint64_t i = 0; i < n; ++i)
+            out[i] = tmp[i];
+    delete[] tmp;
+    return rc;
+}
+
+extern "C" int rambo_sync_status(rambo_t *h, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    int rc = hip_check(h, hipStreamSynchronize(stream), "rambo_sync_status");
+    if (rc)
+        return rc;
+    int e = 0;
+    if ((rc = hip_check(h, hipMemcpy(&e, h->err, sizeof(int), hipMemcpyDeviceToHost), "rambo_sync_status")))
+        return rc;
+    if (e && (rc = hip_check(h, hipMemset(h->err, 0, sizeof(int)), "rambo_sync_status")))
+        return rc;
+    if (e & kErrSetId)
+        return fail(h, RAMBO_ERANGE, "a set id >= K was seen on the device");
+    if (e & kErrCode)
+        return fail(h, RAMBO_ECODE, "a k-mer code >= 4^k was seen on the device");
+    return RAMBO_OK;
+}
+
+extern "C" const char *rambo_last_error(const rambo_t *h)
+{
+    return h ? h->last_error.c_str() : g_create_error.c_str();
+}

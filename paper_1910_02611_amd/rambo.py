@@ -1,0 +1,234 @@
+"""Python binding of librambo.so (include/rambo.h): argument marshalling only.
+
+Device buffers are torch tensors on the GPU; every call passes their data
+pointers and the current torch stream to the C ABI, and all work runs in the
+library's HIP kernels.  There is no fallback: without the built library or a
+GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librambo.so")
+
+OK = 0
+EINVAL = -22
+ENOMEM = -12
+ERANGE = -34
+EOVERFLOW = -75
+EHIP = -1000
+ECODE = -1001
+FLAG_IDENTITY_PARTITION = 1
+NO_KMER = -1   # UINT64_MAX viewed as int64
+
+MAX_B = 4096
+MAX_R = 16
+MAX_RETA = 32
+
+
+class RamboError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_uint32), ("B", ctypes.c_uint32), ("R", ctypes.c_uint32),
+                ("eta", ctypes.c_uint32), ("k", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("m", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("row_bits", ctypes.c_uint32), ("mask_words", ctypes.c_uint32),
+                ("words_per_rep", ctypes.c_uint64), ("index_bytes", ctypes.c_uint64),
+                ("index", ctypes.c_void_p)]
+
+
+_lib = None
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "rambo_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]),
+    "rambo_destroy": (None, [ctypes.c_void_p]),
+    "rambo_insert_kmers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "rambo_insert_seqs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "rambo_query_kmers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "rambo_query_seqs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                        ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_extract_kmers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                           ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_query_kmers_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_query_seqs_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                              ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "rambo_copy_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "rambo_get_partition": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+}
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load librambo.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("librambo.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+_U32 = (torch.int32, torch.uint32)
+_U64 = (torch.int64, torch.uint64)
+
+
+def _dptr(t: torch.Tensor | None, dtypes, name: str) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if t.dtype not in dtypes:
+        raise ValueError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+class Rambo:
+    """A RAMBO index resident in GPU memory (one handle of the C ABI)."""
+
+    def __init__(self, K: int, B: int, R: int, eta: int, k: int, m: int, seed: int, flags: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Rambo needs a GPU")
+        self.K, self.B, self.R, self.eta, self.k, self.m, self.seed = K, B, R, eta, k, m, seed
+        cfg = Config(K, B, R, eta, k, flags, m, seed)
+        h = ctypes.c_void_p()
+        rc = lib().rambo_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != OK:
+            raise RamboError(rc, "rambo_create: " + (lib().rambo_last_error(None) or b"").decode())
+        self._h = h
+        info = Info()
+        lib().rambo_get_info(self._h, ctypes.byref(info))
+        self.row_bits = info.row_bits
+        self.W = info.mask_words
+        self.words_per_rep = info.words_per_rep
+        self.index_bytes = info.index_bytes
+        self._index_ptr = info.index
+
+    # lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rambo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            raise RamboError(rc, "%s: %s" % (what, (lib().rambo_last_error(self._h) or b"").decode()))
+
+    # calls ------------------------------------------------------------------
+    def insert_kmers(self, set_ids, offsets, codes, stream=None):
+        n_sets = offsets.numel() - 1
+        self._check(lib().rambo_insert_kmers(self._h, _dptr(set_ids, _U32, "set_ids"),
+                                             _dptr(offsets, _U64, "offsets"), n_sets,
+                                             _dptr(codes, _U64, "codes"), codes.numel(), _stream(stream)),
+                    "rambo_insert_kmers")
+
+    def insert_seqs(self, set_ids, offsets, chars, stream=None):
+        n = offsets.numel() - 1
+        self._check(lib().rambo_insert_seqs(self._h, _dptr(set_ids, _U32, "set_ids"),
+                                            _dptr(offsets, _U64, "offsets"), n,
+                                            _dptr(chars, (torch.uint8,), "chars"), chars.numel(),
+                                            _stream(stream)),
+                    "rambo_insert_seqs")
+
+    def query_kmers(self, codes, out=None, stream=None, plain=False):
+        n = codes.numel()
+        if out is None:
+            out = torch.empty((n, self.W), dtype=torch.int32, device=codes.device)
+        fn = lib().rambo_query_kmers_plain if plain else lib().rambo_query_kmers
+        self._check(fn(self._h, _dptr(codes, _U64, "codes"), n, _dptr(out, _U32, "out"), _stream(stream)),
+                    "rambo_query_kmers")
+        return out
+
+    def query_seqs(self, offsets, chars, out=None, nkmers=None, stream=None, plain=False, want_nkmers=True):
+        n = offsets.numel() - 1
+        dev = offsets.device
+        if out is None:
+            out = torch.empty((n, self.W), dtype=torch.int32, device=dev)
+        if nkmers is None and want_nkmers:
+            nkmers = torch.empty(n, dtype=torch.int32, device=dev)
+        fn = lib().rambo_query_seqs_plain if plain else lib().rambo_query_seqs
+        self._check(fn(self._h, _dptr(offsets, _U64, "offsets"), n, _dptr(chars, (torch.uint8,), "chars"),
+                       chars.numel(), _dptr(out, _U32, "out"), _dptr(nkmers, _U32, "nkmers"), _stream(stream)),
+                    "rambo_query_seqs")
+        return out, nkmers
+
+    def extract_kmers(self, offsets, chars, out=None, stream=None):
+        n = chars.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.int64, device=chars.device)
+        self._check(lib().rambo_extract_kmers(self._h, _dptr(offsets, _U64, "offsets"), offsets.numel() - 1,
+                                              _dptr(chars, (torch.uint8,), "chars"), n,
+                                              _dptr(out, _U64, "out"), _stream(stream)),
+                    "rambo_extract_kmers")
+        return out
+
+    def clear(self, stream=None):
+        self._check(lib().rambo_clear(self._h, _stream(stream)), "rambo_clear")
+
+    def sync_status(self, stream=None) -> int:
+        """Synchronise and return (and clear) the sticky device error code."""
+        return int(lib().rambo_sync_status(self._h, _stream(stream)))
+
+    def partition(self):
+        import numpy as np
+        out = np.zeros(self.R * self.K, dtype=np.uint32)
+        self._check(lib().rambo_get_partition(self._h, out.ctypes.data), "rambo_get_partition")
+        return out.reshape(self.R, self.K)
+
+    def index_words(self, word_offset: int = 0, n_words: int | None = None, stream=None) -> torch.Tensor:
+        """A device copy of index words [word_offset, word_offset + n_words)
+        as int32 (all R * words_per_rep words by default)."""
+        total = self.index_bytes // 4
+        if n_words is None:
+            n_words = total - word_offset
+        out = torch.empty(n_words, dtype=torch.int32, device="cuda")
+        self._check(lib().rambo_copy_index(self._h, word_offset, n_words, out.data_ptr(), _stream(stream)),
+                    "rambo_copy_index")
+        return out

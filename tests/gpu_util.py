@@ -1,0 +1,92 @@
+"""Helpers shared by the GPU parity tests (data movement and layout decoding
+only; no index arithmetic)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_1910_02611_amd.rambo import Rambo
+
+
+def dev(a: np.ndarray, view=None) -> torch.Tensor:
+    a = np.ascontiguousarray(a)
+    if view is not None:
+        a = a.view(view)
+    return torch.from_numpy(a).to("cuda")
+
+
+def host_u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def host_u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make_pair(cfg: dict, seed: int, flags: int = 0):
+    o = oracle.OracleIndex(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed, flags)
+    g = Rambo(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed, flags)
+    return o, g
+
+
+def gpu_insert_seqs(g: Rambo, batch):
+    g.insert_seqs(dev(batch.set_ids, np.int32), dev(batch.offsets, np.int64), dev(batch.chars, np.uint8))
+
+
+def gpu_extract(g: Rambo, batch) -> np.ndarray:
+    return host_u64(g.extract_kmers(dev(batch.offsets, np.int64), dev(batch.chars, np.uint8)))
+
+
+def first_codes_gpu(g: Rambo, q) -> torch.Tensor:
+    """Device codes of the first window of every sequence of q, extracted by
+    the GPU library."""
+    codes = g.extract_kmers(dev(q.offsets, np.int64), dev(q.chars, np.uint8))
+    idx = torch.from_numpy(q.offsets[:-1].astype(np.int64)).to("cuda")
+    return codes[idx].contiguous()
+
+
+def first_codes_oracle(q, k) -> np.ndarray:
+    return oracle.extract(q.offsets, q.chars, k)[q.offsets[:-1].astype(np.int64)]
+
+
+def gpu_index_bits(g: Rambo) -> np.ndarray:
+    """Decode the bit-sliced index (layout of include/rambo.h) into an
+    (R, B, m) 0/1 array: [r, b, p] = bit p of cell b of repetition r."""
+    words = host_u32(g.index_words()).reshape(g.R, g.words_per_rep)
+    bits = np.unpackbits(words.view(np.uint8), axis=1, bitorder="little")
+    S = g.row_bits
+    bits = bits[:, : g.m * S].reshape(g.R, g.m, S)[:, :, : g.B]
+    return np.ascontiguousarray(bits.transpose(0, 2, 1))
+
+
+def oracle_index_bits(o) -> np.ndarray:
+    out = np.zeros((o.R, o.B, o.m), np.uint8)
+    for r in range(o.R):
+        for b in range(o.B):
+            out[r, b] = o.bfu_bits(r, b)
+    return out
+
+
+def gpu_rows(g: Rambo, r: int, rows: np.ndarray) -> np.ndarray:
+    """Bits of all B cells at the given positions of repetition r, read from
+    the device index: out[t, b]."""
+    S = g.row_bits
+    rows = np.asarray(rows, np.int64)
+    if S >= 32:
+        spw = S // 32
+        word0 = r * g.words_per_rep + rows * spw
+        lo, hi = int(word0.min()), int(word0.max()) + spw
+        w = host_u32(g.index_words(lo, hi - lo))
+        sel = np.stack([w[word0 - lo + i] for i in range(spw)], axis=1)
+        bits = np.unpackbits(sel.view(np.uint8), axis=1, bitorder="little")
+        return bits[:, : g.B]
+    rpw = 32 // S
+    word = r * g.words_per_rep + rows // rpw
+    lo, hi = int(word.min()), int(word.max()) + 1
+    w = host_u32(g.index_words(lo, hi - lo))[word - lo]
+    shift = (rows % rpw) * S
+    out = np.zeros((rows.size, g.B), np.uint8)
+    for b in range(g.B):
+        out[:, b] = (w >> (shift + b).astype(np.uint32)) & 1
+    return out
