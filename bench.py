@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""RAMBO on one MI355X: bulk insertion and batched k-mer queries.
+
+Workload (synthetic, seeded): K = 1 000 genome sets, lognormal lengths
+(median 200 kbp, 20 kbp - 2 Mbp) cut from 50 random 2 Mbp ancestors with 1%
+substitutions (~2.7e8 31-mers); index B = 50, R = 4, m = 2^28 bits per cell,
+eta = 2 (8 GiB bit-sliced); 1e7 single 31-mer queries, half drawn from the
+inserted genomes, half uniform random.
+
+One step = zero the index + insert every set (k_insert_seqs) + answer every
+query (k_query_kmers).  Inputs are resident in device memory before timing.
+`value` is k-mer queries per second of the query phase; inserts per second
+of the insert phase are reported beside it.  Phase times come from HIP
+events recorded on the stream the kernels run on.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+SECTOR = 64             # bytes moved per random access at HBM (one sector)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(n_queries: int):
+    from paper_1910_02611_amd import synth
+    t = time.time()
+    sets = synth.config_mid()
+    q = synth.kmer_queries(3002, sets, n_queries, 31)
+    log("workload: %d sets, %d bases, %d queries (%.1f s)" % (sets.n, sets.chars.size, q.n, time.time() - t))
+    return sets, q
+
+
+def to_dev(a, view):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(view)).to("cuda")
+
+
+def time_steps(g, dsets, codes, out, steps: int, warmup: int):
+    import torch
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+
+    def one_step(e=None):
+        if e: e[0].record(stream)
+        g.clear()
+        if e: e[1].record(stream)
+        g.insert_seqs(*dsets)
+        if e: e[2].record(stream)
+        g.query_kmers(codes, out=out)
+        if e: e[3].record(stream)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        one_step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    clear = np.mean([e[0].elapsed_time(e[1]) for e in ev])
+    ins = np.mean([e[1].elapsed_time(e[2]) for e in ev])
+    qry = np.mean([e[2].elapsed_time(e[3]) for e in ev])
+    return wall, clear, ins, qry
+
+
+def plain_path(g, codes, out_batched, n_prefix: int):
+    """The one-launch-per-query GPU path on a prefix, with identical answers."""
+    import torch
+    pre = codes[:n_prefix].contiguous()
+    g.query_kmers(pre, plain=True)   # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = g.query_kmers(pre, plain=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    same = bool(torch.equal(got, out_batched[:n_prefix]))
+    return n_prefix / dt, same
+
+
+def cpu_baseline(sets, q, cfg, budget_s: float = 20.0):
+    """The oracle, as it stands, on a bounded sample: the index built from the
+    first sets (until ~1.2e7 k-mers), then a sample of the same queries."""
+    import oracle
+    nthreads = min(os.cpu_count() or 1, 16)
+    lens = sets.lengths().astype(np.int64)
+    n_sets = int(np.searchsorted(np.cumsum(lens), 12_000_000)) + 1
+    n_sets = max(1, min(n_sets, sets.n))
+    sub_off = sets.offsets[: n_sets + 1].copy()
+    sub_chars = sets.chars[: int(sub_off[-1])]
+    n_ins = int(np.sum(np.maximum(lens[:n_sets] - cfg["k"] + 1, 0)))
+    o = oracle.OracleIndex(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], 2002)
+    t0 = time.perf_counter()
+    o.insert_seqs(sets.set_ids[:n_sets], sub_off, sub_chars, nthreads)
+    t_ins = time.perf_counter() - t0
+    codes = oracle.extract(q.offsets[:400_001], q.chars[: 400_000 * 31], cfg["k"])[
+        q.offsets[:400_000].astype(np.int64)]
+    n_q = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s / 2 and n_q < codes.size:
+        o.query_kmers(codes[n_q:n_q + 100_000], nthreads)
+        n_q += 100_000
+    t_q = time.perf_counter() - t0
+    o.close()
+    return {
+        "value": n_q / t_q, "unit": "k-mer queries/s", "cores": nthreads, "kind": "oracle",
+        "sample": "%d queries of the same stream against an index of the first %d of %d sets; "
+                  "oracle insert of those sets: %d inserts in %.1f s (%.3g inserts/s)"
+                  % (n_q, n_sets, sets.n, n_ins, t_ins, n_ins / t_ins),
+        "inserts_per_s": n_ins / t_ins,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--queries", type=int, default=10_000_000)
+    ap.add_argument("--plain-prefix", type=int, default=10_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: RAMBO's hot path here has no multi-GPU part "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_02611_amd import synth
+    from paper_1910_02611_amd.rambo import Rambo
+
+    torch.cuda.set_device(0)
+    cfg = synth.INDEX_MID
+    sets, q = build_workload(args.queries)
+    g = Rambo(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed=2002)
+    dsets = (to_dev(sets.set_ids, np.int32), to_dev(sets.offsets, np.int64), to_dev(sets.chars, np.uint8))
+    qoff = to_dev(q.offsets, np.int64)
+    qchars = to_dev(q.chars, np.uint8)
+    codes = g.extract_kmers(qoff, qchars)[qoff[:-1]].contiguous()
+    del qchars
+    out = torch.empty((q.n, g.W), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    log("index: %.2f GiB, row %d bits, %d answer words" % (g.index_bytes / 2**30, g.row_bits, g.W))
+
+    wall, t_clear, t_ins, t_q = time_steps(g, dsets, codes, out, args.steps, args.warmup)
+    if g.sync_status() != 0:
+        raise SystemExit("device error flag set")
+    n_ins = int(np.sum(np.maximum(sets.lengths().astype(np.int64) - cfg["k"] + 1, 0)))
+    ins_per_s = n_ins / (t_ins / 1e3)
+    q_per_s = q.n / (t_q / 1e3)
+    ms_per_step = wall / args.steps * 1e3
+    log("step %.2f ms: clear %.2f, insert %.2f (%.3g inserts/s), query %.2f (%.3g queries/s)"
+        % (ms_per_step, t_clear, t_ins, ins_per_s, t_q, q_per_s))
+
+    R, eta, S, W = cfg["R"], cfg["eta"], g.row_bits, g.W
+    ins_bytes = R * eta * 2 * SECTOR                    # RMW of one sector per target
+    q_bytes = R * eta * max(SECTOR, S // 8) + 4 * W + 8  # row sectors + answer + code
+    roof_ins = {"kernel": "k_insert_seqs", "bound": "hbm", "achieved": ins_per_s * ins_bytes / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                "bytes_per_unit": ins_bytes, "units_per_launch": n_ins}
+    roof_q = {"kernel": "k_query_kmers", "bound": "hbm", "achieved": q_per_s * q_bytes / 1e9,
+              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+              "bytes_per_unit": q_bytes, "units_per_launch": q.n}
+    for r in (roof_ins, roof_q):
+        r["frac"] = r["achieved"] / r["peak"]
+    dominant, other = (roof_ins, roof_q) if t_ins >= t_q else (roof_q, roof_ins)
+
+    plain_rate, plain_same = plain_path(g, codes, out, min(args.plain_prefix, q.n))
+    log("plain one-launch-per-query path: %.3g queries/s on %d, identical=%s"
+        % (plain_rate, args.plain_prefix, plain_same))
+
+    res = {
+        "metric": "k-mer queries/s and inserts/s on 1 GPU (% of random-HBM roofline); p50/p99 latency",
+        "value": q_per_s, "unit": "k-mer queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "mid: K=1000 genome sets (~2.7e8 31-mers), B=50, R=4, m=2^28, eta=2; "
+                               "1e7 single 31-mer queries (50% present)",
+                   "K": cfg["K"], "B": cfg["B"], "R": cfg["R"], "m": cfg["m"], "eta": cfg["eta"],
+                   "k": cfg["k"], "inserts": n_ins, "queries": q.n},
+        "inserts_per_s": ins_per_s,
+        "phase_ms": {"clear": t_clear, "insert": t_ins, "query": t_q},
+        "roofline": dominant, "roofline_other": other,
+        "plain_path": {"k_mer_queries_per_s": plain_rate, "prefix": args.plain_prefix,
+                       "identical": plain_same, "speedup_batched": q_per_s / plain_rate},
+    }
+    g.close()
+    del out, codes, dsets
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        t = time.time()
+        res["cpu_baseline"] = cpu_baseline(sets, q, cfg)
+        log("cpu baseline: %.3g queries/s (%.1f s)" % (res["cpu_baseline"]["value"], time.time() - t))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
