@@ -93,13 +93,14 @@ def plain_path(g, codes, out_batched, n_prefix: int):
     return n_prefix / dt, same
 
 
-def cpu_baseline(sets, q, cfg, budget_s: float = 20.0):
+def cpu_baseline(sets, q, cfg, query_budget_s: float = 12.0):
     """The oracle, as it stands, on a bounded sample: the index built from the
-    first sets (until ~1.2e7 k-mers), then a sample of the same queries."""
+    first sets (until ~5e7 k-mers), then queries of the same stream, repeated
+    for about query_budget_s seconds."""
     import oracle
     nthreads = min(os.cpu_count() or 1, 16)
     lens = sets.lengths().astype(np.int64)
-    n_sets = int(np.searchsorted(np.cumsum(lens), 12_000_000)) + 1
+    n_sets = int(np.searchsorted(np.cumsum(lens), 50_000_000)) + 1
     n_sets = max(1, min(n_sets, sets.n))
     sub_off = sets.offsets[: n_sets + 1].copy()
     sub_chars = sets.chars[: int(sub_off[-1])]
@@ -108,20 +109,22 @@ def cpu_baseline(sets, q, cfg, budget_s: float = 20.0):
     t0 = time.perf_counter()
     o.insert_seqs(sets.set_ids[:n_sets], sub_off, sub_chars, nthreads)
     t_ins = time.perf_counter() - t0
-    codes = oracle.extract(q.offsets[:400_001], q.chars[: 400_000 * 31], cfg["k"])[
-        q.offsets[:400_000].astype(np.int64)]
-    n_q = 0
+    nq = min(q.n, 2_000_000)
+    k = cfg["k"]
+    codes = oracle.extract(q.offsets[: nq + 1], q.chars[: nq * k], k)[q.offsets[:nq].astype(np.int64)]
+    n_q, pos, chunk = 0, 0, 200_000
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s / 2 and n_q < codes.size:
-        o.query_kmers(codes[n_q:n_q + 100_000], nthreads)
-        n_q += 100_000
+    while time.perf_counter() - t0 < query_budget_s:
+        o.query_kmers(codes[pos:pos + chunk], nthreads)
+        n_q += min(chunk, nq - pos)
+        pos = (pos + chunk) % nq
     t_q = time.perf_counter() - t0
     o.close()
     return {
         "value": n_q / t_q, "unit": "k-mer queries/s", "cores": nthreads, "kind": "oracle",
-        "sample": "%d queries of the same stream against an index of the first %d of %d sets; "
-                  "oracle insert of those sets: %d inserts in %.1f s (%.3g inserts/s)"
-                  % (n_q, n_sets, sets.n, n_ins, t_ins, n_ins / t_ins),
+        "sample": "%d k-mer queries (the first %d of the same stream, cycled) against the oracle index of "
+                  "the first %d of %d sets; oracle insert of those sets: %d inserts in %.1f s (%.3g inserts/s)"
+                  % (n_q, nq, n_sets, sets.n, n_ins, t_ins, n_ins / t_ins),
         "inserts_per_s": n_ins / t_ins,
     }
 
@@ -134,6 +137,8 @@ def main():
     ap.add_argument("--queries", type=int, default=10_000_000)
     ap.add_argument("--plain-prefix", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run one streaming copy of this size (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: RAMBO's hot path here has no multi-GPU part "
@@ -180,9 +185,20 @@ def main():
         r["frac"] = r["achieved"] / r["peak"]
     dominant, other = (roof_ins, roof_q) if t_ins >= t_q else (roof_q, roof_ins)
 
-    plain_rate, plain_same = plain_path(g, codes, out, min(args.plain_prefix, q.n))
-    log("plain one-launch-per-query path: %.3g queries/s on %d, identical=%s"
-        % (plain_rate, args.plain_prefix, plain_same))
+    if args.calib_copy_gib > 0:
+        # a streaming copy of known size: the scale of the memory counters
+        from paper_1910_02611_amd.rambo import lib
+        n = int(args.calib_copy_gib * 2**30) // 16 * 16
+        buf = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+        assert lib().rambo_roofline_copy(buf.data_ptr(), buf.data_ptr() + n, n,
+                                         torch.cuda.current_stream().cuda_stream) == 0
+        torch.cuda.synchronize()
+        del buf
+    plain_rate, plain_same = float("nan"), None
+    if args.plain_prefix > 0:
+        plain_rate, plain_same = plain_path(g, codes, out, min(args.plain_prefix, q.n))
+        log("plain one-launch-per-query path: %.3g queries/s on %d, identical=%s"
+            % (plain_rate, args.plain_prefix, plain_same))
 
     res = {
         "metric": "k-mer queries/s and inserts/s on 1 GPU (% of random-HBM roofline); p50/p99 latency",

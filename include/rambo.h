@@ -152,6 +152,19 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
                            const uint8_t *chars, uint64_t n_chars, uint32_t *out_masks,
                            uint32_t *out_nkmers, hipStream_t stream);
 
+/* How rambo_insert_seqs applies bits (the result is the same either way):
+ * DIRECT issues one atomicOr per bit target (Alg. 1 as written); PARTITIONED
+ * sorts the targets by address into regions of the index and ORs each region
+ * in on-chip memory, which avoids the device's atomic-rate limit on bulk
+ * inserts; AUTO picks by the number of targets.  scratch_bytes caps the
+ * device scratch of the partitioned path (0 = a quarter of free memory, at
+ * most 32 GiB); larger inserts are processed in batches.  The scratch is
+ * allocated at the first partitioned insert and kept by the handle. */
+#define RAMBO_INSERT_AUTO 0
+#define RAMBO_INSERT_DIRECT 1
+#define RAMBO_INSERT_PARTITIONED 2
+int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
+
 /* Zero every Bloom filter (an empty index with the same hashes). */
 int rambo_clear(rambo_t *h, hipStream_t stream);
 

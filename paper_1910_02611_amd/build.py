@@ -8,8 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librambo.so")
-SOURCES = ["rambo_api.hip"]
-HEADERS = ["device.hpp", "kernels.hpp"]
+SOURCES = ["rambo_api.hip", "roofline.hip"]
+HEADERS = ["device.hpp", "kernels.hpp", "insert_part.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++20", "-fPIC", "-shared", "-Wall",
@@ -20,7 +20,7 @@ HIPCC_FLAGS = [
 
 def sources():
     return [os.path.join(CSRC, s) for s in SOURCES] + [os.path.join(CSRC, h) for h in HEADERS] + \
-        [os.path.join(ROOT, "include", "rambo.h")]
+        [os.path.join(ROOT, "include", h) for h in ("rambo.h", "rambo_roofline.h")]
 
 
 def build(verbose: bool = False) -> str:

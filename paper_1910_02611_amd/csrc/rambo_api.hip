@@ -10,6 +10,7 @@
 #include <new>
 #include <string>
 
+#include "insert_part.hpp"
 #include "kernels.hpp"
 #include "rambo.h"
 
@@ -26,6 +27,13 @@ struct rambo {
     uint32_t *cellmask = nullptr;
     int *err = nullptr;
     std::string last_error;
+    // partitioned insertion
+    int insert_mode = RAMBO_INSERT_AUTO;
+    uint64_t scratch_limit = 0;      // 0: chosen at first use
+    bool part_ok = false;            // geometry supports the partitioned path
+    BinGeom bin{};
+    uint64_t bin_targets = 0;        // targets per batch the scratch holds
+    void *bin_mem = nullptr;
 };
 
 namespace {
@@ -161,6 +169,123 @@ uint32_t log2_exact(uint64_t v)
     return l;
 }
 
+// ------------------------------------------------- partitioned insertion
+
+constexpr uint32_t kRegionLog2 = 19;        // 2^19 bits = 64 KiB of LDS per region
+constexpr uint32_t kMaxCoarse = 8192;       // stage-A LDS: 2 * 8192 counters
+constexpr double kAtomicRate = 1.7e10;      // measured random atomicOr/s over a large buffer
+constexpr double kStreamRate = 4.0e12;      // streaming bytes/s the partitioned path sustains
+
+void plan_partition(rambo *h)
+{
+    const uint64_t total_words = (uint64_t)h->cfg.R * h->words_per_rep;
+    const uint64_t total_bits = total_words * 32;
+    const uint32_t bits = log2_exact(total_bits);
+    BinGeom &G = h->bin;
+    G.rb = kRegionLog2;
+    G.fb = bits > G.rb + 10 + 8 ? bits - G.rb - 10 : 8;
+    if (G.fb > 12)
+        G.fb = 12;
+    G.nf = 1u << G.fb;
+    const uint64_t na = div_up(total_bits, 1ull << (G.rb + G.fb));
+    G.na = (uint32_t)na;
+    G.total_words = total_words;
+    h->part_ok = na <= kMaxCoarse;
+}
+
+uint64_t scratch_bytes_for(const BinGeom &G, uint64_t T, uint64_t &capA, uint64_t &capB)
+{
+    capA = (uint64_t)((double)T / G.na * 1.04) + 4096;
+    capB = (uint64_t)((double)T / ((double)G.na * G.nf) * 1.08) + 512;
+    capA = div_up(capA, 4) * 4;
+    capB = div_up(capB, 4) * 4;
+    return 4 * ((uint64_t)G.na * capA + (uint64_t)G.na * G.nf * capB + G.na + (uint64_t)G.na * G.nf);
+}
+
+// Allocate the scratch of the partitioned path once: as many targets per
+// batch as fit the limit (default: a quarter of free memory, at most 32 GiB).
+int ensure_scratch(rambo *h, uint64_t want_targets)
+{
+    if (h->bin_mem)
+        return RAMBO_OK;
+    uint64_t limit = h->scratch_limit;
+    if (limit == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+            return fail(h, RAMBO_EHIP, "hipMemGetInfo failed");
+        limit = free_b / 4;
+        if (limit > (32ull << 30))
+            limit = 32ull << 30;
+    }
+    uint64_t capA = 0, capB = 0;
+    uint64_t T = want_targets > (1ull << 24) ? want_targets : (1ull << 24);
+    if (T > (1ull << 31))
+        T = 1ull << 31;
+    while (T > 4096 && scratch_bytes_for(h->bin, T, capA, capB) > limit)
+        T = T / 4 * 3;
+    const uint64_t bytes = scratch_bytes_for(h->bin, T, capA, capB);
+    if (bytes > limit)
+        return fail(h, RAMBO_ENOMEM, "insert scratch limit too small");
+    if (hipMalloc(&h->bin_mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        h->bin_mem = nullptr;
+        return fail(h, RAMBO_ENOMEM, "insert scratch allocation failed");
+    }
+    BinGeom &G = h->bin;
+    G.capA = capA;
+    G.capB = capB;
+    uint32_t *p = static_cast<uint32_t *>(h->bin_mem);
+    G.slabA = p;
+    p += (uint64_t)G.na * capA;
+    G.slabB = p;
+    p += (uint64_t)G.na * G.nf * capB;
+    G.fillA = p;
+    p += G.na;
+    G.fillB = p;
+    h->bin_targets = T;
+    return RAMBO_OK;
+}
+
+bool use_partitioned(const rambo *h, uint64_t n_chars)
+{
+    if (!h->part_ok || h->insert_mode == RAMBO_INSERT_DIRECT)
+        return false;
+    if (h->insert_mode == RAMBO_INSERT_PARTITIONED)
+        return true;
+    const double T = (double)n_chars * h->cfg.R * h->cfg.eta;
+    const double regions = (double)h->bin.na * h->bin.nf;
+    const double t_direct = T / kAtomicRate;
+    const double t_part = (T * 20.0 + (T < regions ? T : regions) * 2.0 * (1u << (kRegionLog2 - 3))) / kStreamRate +
+                          100e-6;
+    return t_part < t_direct;
+}
+
+int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
+                            const uint8_t *chars, uint64_t n_chars, hipStream_t stream)
+{
+    const uint64_t RE = (uint64_t)h->cfg.R * h->cfg.eta;
+    int rc = ensure_scratch(h, n_chars * RE);
+    if (rc)
+        return rc;
+    BinGeom &G = h->bin;
+    const uint64_t batch_windows = h->bin_targets / RE;
+    const uint64_t tile_windows = (uint64_t)kWavesPerBlock * kWindowsPerWaveA;
+    const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
+    const size_t ldsA = 2ull * G.na * 4, ldsB = (kTileB + 2ull * G.nf) * 4, ldsC = (1ull << (G.rb - 5)) * 4;
+    for (uint64_t p = 0; p < n_chars; p += batch_windows) {
+        const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
+                           (uint64_t)G.na + (uint64_t)G.na * G.nf);
+        hipLaunchKernelGGL(k_bin_windows, dim3((uint32_t)div_up(pe - p, tile_windows)), dim3(kBlock), ldsA, stream,
+                           h->P, G, set_ids, offsets, n_seqs, chars, n_chars, p, pe);
+        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlock), ldsB, stream, h->P, G, tpb);
+        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G);
+        if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
+            return rc;
+    }
+    return RAMBO_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -188,6 +313,7 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
     // words per repetition, rounded up to 4 so every row block is 16-byte aligned
     h->words_per_rep = div_up(div_up(c.m * h->S, 32), 4) * 4;
     h->index_bytes = (uint64_t)c.R * h->words_per_rep * 4;
+    plan_partition(h);
 
     // Seeds: one splitmix64 stream, in the documented order.
     uint64_t st = c.seed;
@@ -267,7 +393,25 @@ extern "C" void rambo_destroy(rambo_t *h)
         (void)hipFree(h->cellmask);
     if (h->err)
         (void)hipFree(h->err);
+    if (h->bin_mem)
+        (void)hipFree(h->bin_mem);
     delete h;
+}
+
+extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes)
+{
+    if (!h || mode < RAMBO_INSERT_AUTO || mode > RAMBO_INSERT_PARTITIONED)
+        return RAMBO_EINVAL;
+    if (scratch_bytes != h->scratch_limit && h->bin_mem) {
+        const int rc = hip_check(h, hipDeviceSynchronize(), "rambo_set_insert_policy");
+        if (rc)
+            return rc;
+        (void)hipFree(h->bin_mem);
+        h->bin_mem = nullptr;
+    }
+    h->insert_mode = mode;
+    h->scratch_limit = scratch_bytes;
+    return RAMBO_OK;
 }
 
 extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_sets,
@@ -293,6 +437,8 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
         return RAMBO_OK;
     if (!set_ids || !offsets || !chars)
         return fail(h, RAMBO_EINVAL, "rambo_insert_seqs: NULL array");
+    if (use_partitioned(h, n_chars))
+        return insert_seqs_partitioned(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
     const uint64_t waves = div_up(n_chars, kChunk);
     hipLaunchKernelGGL(k_insert_seqs, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P,
                        set_ids, offsets, n_seqs, chars, n_chars, kChunk);

@@ -22,6 +22,7 @@ EOVERFLOW = -75
 EHIP = -1000
 ECODE = -1001
 FLAG_IDENTITY_PARTITION = 1
+INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED = 0, 1, 2
 NO_KMER = -1   # UINT64_MAX viewed as int64
 
 MAX_B = 4096
@@ -68,6 +69,7 @@ EXPORTS = {
     "rambo_query_seqs_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                               ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_set_insert_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]),
     "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rambo_copy_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
@@ -75,6 +77,12 @@ EXPORTS = {
     "rambo_get_partition": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    # include/rambo_roofline.h
+    "rambo_roofline_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_roofline_atomic_or": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                                ctypes.c_void_p]),
+    "rambo_roofline_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
 }
 
 
@@ -208,6 +216,10 @@ class Rambo:
                                               _dptr(out, _U64, "out"), _stream(stream)),
                     "rambo_extract_kmers")
         return out
+
+    def set_insert_policy(self, mode: int = 0, scratch_bytes: int = 0):
+        """INSERT_AUTO / INSERT_DIRECT / INSERT_PARTITIONED; same index bits."""
+        self._check(lib().rambo_set_insert_policy(self._h, mode, scratch_bytes), "rambo_set_insert_policy")
 
     def clear(self, stream=None):
         self._check(lib().rambo_clear(self._h, _stream(stream)), "rambo_clear")

@@ -253,3 +253,57 @@ def test_zero_sized_calls_are_noops(tiny):
     assert out.shape[0] == 0
     g.query_seqs(torch.zeros(1, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.uint8, device="cuda"))
     assert g.sync_status() == 0
+
+
+# ---------------------------------------------------------------- partitioned insertion
+
+def _partitioned_pair(cfg, seed, scratch=0):
+    o, g = make_pair(cfg, seed=seed)
+    g.set_insert_policy(rb.INSERT_PARTITIONED, scratch)
+    return o, g
+
+
+def test_partitioned_insert_matches_oracle(tiny):
+    cfg, sets, o, _ = tiny
+    _, g = _partitioned_pair(cfg, 2001)
+    gpu_insert_seqs(g, sets)
+    assert g.sync_status() == 0
+    assert np.array_equal(gpu_index_bits(g), oracle_index_bits(o))
+
+
+def test_partitioned_insert_in_many_batches(tiny):
+    cfg, sets, o, g_direct = tiny
+    _, g = _partitioned_pair(cfg, 2001, scratch=1 << 20)   # ~50k targets per batch
+    gpu_insert_seqs(g, sets)
+    assert g.sync_status() == 0
+    assert torch.equal(g.index_words(), g_direct.index_words())
+
+
+def test_partitioned_insert_overflow_falls_back():
+    # one k-mer repeated thousands of times crowds one region past its slab
+    cfg = dict(K=8, B=4, R=3, eta=2, k=21, m=1 << 16)
+    rng = np.random.default_rng(8)
+    parts = [np.frombuffer(b"A" * 20000, np.uint8), np.frombuffer(b"ACGT" * 5000, np.uint8)]
+    parts += [rng.choice(np.frombuffer(b"ACGT", np.uint8), size=3000) for _ in range(6)]
+    offsets = np.zeros(len(parts) + 1, np.uint64)
+    offsets[1:] = np.cumsum([p.size for p in parts])
+    b = synth.SeqBatch(np.concatenate(parts), offsets, np.arange(len(parts), dtype=np.uint32))
+    o, g = _partitioned_pair(cfg, 5, scratch=1 << 20)
+    o.insert_seqs(b.set_ids, b.offsets, b.chars)
+    gpu_insert_seqs(g, b)
+    assert g.sync_status() == 0
+    assert np.array_equal(gpu_index_bits(g), oracle_index_bits(o))
+
+
+@pytest.mark.parametrize("cfg", SHAPES, ids=lambda c: "K%(K)d-B%(B)d-R%(R)d-e%(eta)d-k%(k)d-m%(m)d" % c)
+def test_partitioned_shapes_match_direct(cfg):
+    K = cfg["K"]
+    sets = synth.genome_sets(K + cfg["B"] + 1, K=K, n_ancestors=5, ancestor_len=400, sub_rate=0.02)
+    _, gd = make_pair(cfg, seed=cfg["B"] * 3 + 1)
+    gd.set_insert_policy(rb.INSERT_DIRECT)
+    _, gp = _partitioned_pair(cfg, cfg["B"] * 3 + 1, scratch=4 << 20)
+    gpu_insert_seqs(gd, sets)
+    gpu_insert_seqs(gp, sets)
+    gpu_insert_seqs(gp, sets)   # a second call ORs into the same regions
+    assert gd.sync_status() == 0 and gp.sync_status() == 0
+    assert torch.equal(gp.index_words(), gd.index_words())
