@@ -12,6 +12,10 @@
 
 namespace rambo_dev {
 
+// Four packed 32-bit words: one 16-byte vector load or store.  (A native
+// vector type keeps register arrays of them in registers.)
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                 // four waves per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;

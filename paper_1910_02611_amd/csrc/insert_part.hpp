@@ -1,14 +1,16 @@
 // Partitioned bulk insertion (Alg. 1 without global atomics).
 //
-// A random atomicOr per bit target is bound by the device's atomic rate, not
-// by HBM bandwidth.  For bulk inserts the targets are instead partitioned by
+// A random atomicOr per bit target is bound by the device's atomic rate, and
+// a scattered 4-byte store per target by the L2's request rate, not by HBM
+// bandwidth.  For bulk inserts the targets are instead partitioned by
 // address, twice, and applied region by region in LDS:
 //
-//  A  k_bin_windows : every window's R*eta targets (global bit addresses of
-//                     the bit-sliced index) are counted per coarse bucket in
-//                     LDS, one run per bucket is reserved in the bucket's slab
-//                     with one atomicAdd per bucket and tile, and a second
-//                     pass scatters the low bits of every target into its run.
+//  A  k_bin_windows : a workgroup takes the R*eta targets (global bit
+//                     addresses of the bit-sliced index) of a tile of windows,
+//                     counting-sorts them in LDS by coarse bucket, reserves one
+//                     run per bucket in the bucket's slab (one atomicAdd per
+//                     bucket and tile) and writes each run with coalesced
+//                     stores.
 //  B  k_bin_regions : each tile of a coarse bucket's slab is split the same
 //                     way into the bucket's fine buckets (index regions of
 //                     2^rb bits).
@@ -24,10 +26,15 @@
 
 namespace rambo_dev {
 
+constexpr uint32_t kRegionLog2Max = 19;         // regions of at most 2^19 bits (64 KiB of LDS)
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kFail = 0xFFFFFFFFu;
-constexpr uint32_t kWindowsPerWaveA = 4096;     // windows per wave in stage A
+constexpr uint16_t kNoBucket = 0xFFFFu;
+constexpr int kBlockP = 512;                    // workgroup of stages A and B
+constexpr int kWavesP = kBlockP / kWave;
+constexpr uint32_t kTileA = 8192;               // targets per round in stage A
 constexpr uint32_t kTileB = 8192;               // slab entries per tile in stage B
+constexpr uint32_t kMaxTargetsPerWindow = kTileA / kBlockP;   // R*eta the partitioned path supports
 
 struct BinGeom {
     uint32_t rb;          // log2 of the bits in one region
@@ -43,109 +50,190 @@ struct BinGeom {
     uint64_t total_words; // words of the index (all repetitions)
 };
 
-// Every target of a valid window: global bit address of (r, row, col).
-template <class F>
-__device__ __forceinline__ void for_each_target(const Params &P, uint64_t x, uint32_t set, F &&f)
+__host__ __device__ constexpr size_t lds_bytes_stage_a(uint32_t na) { return kTileA * 12ull + na * 12ull + 64; }
+__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 8ull + nf * 12ull + 64; }
+
+// Exclusive prefix sum of cnt[0..n) into start[0..n) by the whole
+// workgroup; returns the total.  wsum holds kWavesP words of LDS.
+__device__ __forceinline__ uint32_t block_exclusive_scan(const uint32_t *cnt, uint32_t *start, uint32_t n,
+                                                         uint32_t *wsum)
 {
-    const uint64_t rep_bits = P.words_per_rep * 32;
-    for (uint32_t r = 0; r < P.R; ++r) {
-        const uint32_t col = P.phi[(uint64_t)r * P.K + set];
-        const uint64_t base = r * rep_bits + col;
-        for (uint32_t j = 0; j < P.eta; ++j)
-            f(base + (bf_position(x, P.seeds[r * P.eta + j], P) << P.S_log2));
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t per = (n + kBlockP - 1) / kBlockP;
+    const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
+    uint32_t s = 0;
+    for (uint32_t b = b0; b < b1; ++b)
+        s += cnt[b];
+    uint32_t incl = s;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, kWave);
+        if ((int)lane >= off)
+            incl += t;
     }
+    if (lane == kWave - 1)
+        wsum[wv] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesP; ++w) {
+        const uint32_t ws = wsum[w];
+        wbase += (uint32_t)w < wv ? ws : 0u;
+        total += ws;
+    }
+    uint32_t run = wbase + incl - s;
+    for (uint32_t b = b0; b < b1; ++b) {
+        start[b] = run;
+        run += cnt[b];
+    }
+    __syncthreads();
+    return total;
 }
 
-__device__ __forceinline__ void direct_or(const Params &P, uint64_t gb)
-{
-    atomicOr(P.index + (gb >> 5), 1u << (gb & 31u));
-}
+// Reserving one run per bucket takes a global atomicAdd round trip.  The
+// reservation is split so that the LDS scatter runs while the atomics are in
+// flight: issue() starts them (cnt[b] entries for bucket b, at most
+// kMaxBucketsPerThread buckets per thread) and resets cnt[b] to 0, the run
+// cursor; finish() stores gbase[b], the run's first slab entry, or kFail for
+// a run that does not fit - whose slab tail, if it starts inside the slab, is
+// filled with sentinels so readers skip it.
+constexpr uint32_t kMaxBucketsPerThread = 8;   // 4096 buckets / 512 threads
 
-// Reserve one run per bucket: hist[b] targets of this tile.  On success
-// base[b] is the run's first slab entry and hist[b] becomes the run cursor
-// (0); a run that does not fit is marked kFail and, if it starts inside the
-// slab, its slab tail is filled with sentinels so readers skip it.
-__device__ __forceinline__ void reserve_runs(uint32_t *hist, uint32_t *base, uint32_t nb, uint32_t *fill,
-                                             uint32_t *slab, uint64_t cap)
-{
-    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
-        const uint32_t c = hist[b];
-        hist[b] = 0;
-        if (c == 0) {
-            base[b] = kFail;
-            continue;
-        }
-        const uint64_t pos = atomicAdd(fill + b, c);
-        if (pos + c <= cap) {
-            base[b] = (uint32_t)pos;
-        } else {
-            base[b] = kFail;
-            for (uint64_t i = pos; i < cap; ++i)
-                slab[(uint64_t)b * cap + i] = kSentinel;
+struct RunReservation {
+    uint32_t pos[kMaxBucketsPerThread];
+    uint32_t c[kMaxBucketsPerThread];
+
+    __device__ __forceinline__ void issue(uint32_t *cnt, uint32_t nb, uint32_t *fill)
+    {
+#pragma unroll
+        for (uint32_t i = 0; i < kMaxBucketsPerThread; ++i) {
+            const uint32_t b = threadIdx.x + i * kBlockP;
+            c[i] = 0;
+            pos[i] = 0;
+            if (b < nb) {
+                c[i] = cnt[b];
+                cnt[b] = 0;
+                if (c[i])
+                    pos[i] = atomicAdd(fill + b, c[i]);
+            }
         }
     }
-}
 
-// Stage A over the windows starting in [p_begin, p_end).
-__global__ __launch_bounds__(kBlock) void k_bin_windows(Params P, BinGeom G, const uint32_t *set_ids,
-                                                        const uint64_t *offsets, uint64_t n_seqs,
-                                                        const uint8_t *chars, uint64_t n_chars, uint64_t p_begin,
-                                                        uint64_t p_end)
+    __device__ __forceinline__ void finish(uint32_t *gbase, uint32_t nb, uint32_t *slab, uint64_t cap)
+    {
+#pragma unroll
+        for (uint32_t i = 0; i < kMaxBucketsPerThread; ++i) {
+            const uint32_t b = threadIdx.x + i * kBlockP;
+            if (b >= nb)
+                continue;
+            if (c[i] == 0) {
+                gbase[b] = kFail;
+            } else if ((uint64_t)pos[i] + c[i] <= cap) {
+                gbase[b] = pos[i];
+            } else {
+                gbase[b] = kFail;
+                for (uint64_t e = pos[i]; e < cap; ++e)
+                    slab[(uint64_t)b * cap + e] = kSentinel;
+            }
+        }
+    }
+};
+
+// Stage A over the windows starting in [p_begin, p_end).  Wave w of block g
+// walks `rounds * steps * 64` consecutive windows; each round the workgroup
+// gathers the targets of `steps` steps of every wave (at most kTileA), sorts
+// them by coarse bucket in LDS and writes them out run by run.
+template <int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, const uint32_t *set_ids,
+                                                         const uint64_t *offsets, uint64_t n_seqs,
+                                                         const uint8_t *chars, uint64_t n_chars, uint64_t p_begin,
+                                                         uint64_t p_end, uint32_t steps, uint32_t rounds)
 {
     extern __shared__ uint32_t lds[];
-    uint32_t *hist = lds;          // na counters, then run cursors
-    uint32_t *base = lds + G.na;   // na run starts
+    uint32_t *ent = lds;                                          // kTileA: low bits of each target
+    uint32_t *srt = ent + kTileA;                                 // kTileA: the same, sorted by bucket
+    uint16_t *bkt = reinterpret_cast<uint16_t *>(srt + kTileA);   // kTileA: bucket of each target
+    uint16_t *sbk = bkt + kTileA;                                 // kTileA: bucket, sorted
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(sbk + kTileA);   // na: counts, then run cursors
+    uint32_t *lbase = cnt + G.na;                                 // na: first sorted slot of each bucket
+    uint32_t *gbase = lbase + G.na;                               // na: first slab entry of each run
+    uint32_t *wsum = gbase + G.na;                                // kWavesP
     const uint32_t shA = G.rb + G.fb;
     const uint64_t maskA = (1ull << shA) - 1;
-    for (uint32_t b = threadIdx.x; b < G.na; b += kBlock)
-        hist[b] = 0;
-    __syncthreads();
-
-    const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t w0 = p_begin + ((uint64_t)blockIdx.x * kWavesPerBlock + wv) * kWindowsPerWaveA;
-    const uint64_t w1 = min(w0 + kWindowsPerWaveA, p_end);
+    const uint32_t RE = P.R * P.eta;
+    const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t span = (uint64_t)rounds * steps * kWave;
+    const uint64_t w0 = p_begin + ((uint64_t)blockIdx.x * kWavesP + wv) * span;
+    const uint64_t w1 = min(w0 + span, p_end);
     const bool busy = w0 < p_end;
+    WindowWalker walker;
+    if (busy)
+        walker.init(offsets, n_seqs, chars, n_chars, w0, w1, P.k, P.kmask);
+    SetCache cache;
+    cache.init_seeds(P);
 
-    auto visit = [&](auto &&on_target) {
-        if (!busy)
-            return;
-        wave_windows(offsets, n_seqs, chars, n_chars, w0, w1, P.k, P.kmask,
-                     [&](uint64_t, bool valid, uint64_t x, uint64_t s) {
-                         if (!valid)
-                             return;
-                         const uint32_t set = set_ids[s];
-                         if (set >= P.K) {
-                             atomicOr(P.err, kErrSetId);
-                             return;
-                         }
-                         for_each_target(P, x, set, on_target);
-                     });
-    };
-    // pass 1: count targets per coarse bucket
-    visit([&](uint64_t gb) { atomicAdd(&hist[gb >> shA], 1u); });
-    __syncthreads();
-    reserve_runs(hist, base, G.na, G.fillA, G.slabA, G.capA);
-    __syncthreads();
-    // pass 2: the same targets again, scattered into the reserved runs
-    visit([&](uint64_t gb) {
-        const uint32_t b = (uint32_t)(gb >> shA);
-        const uint32_t start = base[b];
-        if (start == kFail) {
-            direct_or(P, gb);
-            return;
+    for (uint32_t round = 0; round < rounds; ++round) {
+        for (uint32_t b = threadIdx.x; b < G.na; b += kBlockP)
+            cnt[b] = 0;
+        for (uint32_t i = threadIdx.x; i < kTileA; i += kBlockP)
+            bkt[i] = kNoBucket;
+        __syncthreads();
+        if (busy) {
+            for (uint32_t st = 0; st < steps; ++st) {
+                bool valid = false;
+                uint64_t x = 0, s = 0;
+                if (walker.p < w1)
+                    walker.step(valid, x, s);
+                // target t of lane l goes to slot (step_base + t) * 64 + l: the
+                // lanes of one LDS write hit consecutive words (no bank conflict)
+                uint32_t slot = (wv * steps + st) * RE * kWave + lane;
+                wave_targets<R_T, ETA_T>(P, set_ids, cache, valid, x, s, [&](uint64_t gb) {
+                    const uint32_t b = (uint32_t)(gb >> shA);
+                    bkt[slot] = (uint16_t)b;
+                    ent[slot] = (uint32_t)(gb & maskA);
+                    slot += kWave;
+                    atomicAdd(&cnt[b], 1u);
+                });
+            }
         }
-        const uint32_t rank = atomicAdd(&hist[b], 1u);
-        G.slabA[(uint64_t)b * G.capA + start + rank] = (uint32_t)(gb & maskA);
-    });
+        __syncthreads();
+        const uint32_t total = block_exclusive_scan(cnt, lbase, G.na, wsum);
+        RunReservation res;
+        res.issue(cnt, G.na, G.fillA);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kTileA; i += kBlockP) {
+            const uint32_t b = bkt[i];
+            if (b == kNoBucket)
+                continue;
+            const uint32_t pos = lbase[b] + atomicAdd(&cnt[b], 1u);
+            srt[pos] = ent[i];
+            sbk[pos] = (uint16_t)b;
+        }
+        res.finish(gbase, G.na, G.slabA, G.capA);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < total; i += kBlockP) {
+            const uint32_t b = sbk[i];
+            const uint32_t e = srt[i];
+            const uint32_t g = gbase[b];
+            if (g == kFail)
+                direct_or(P, ((uint64_t)b << shA) | e);
+            else
+                G.slabA[(uint64_t)b * G.capA + g + (i - lbase[b])] = e;
+        }
+        __syncthreads();
+    }
 }
 
 // Stage B: block = (coarse bucket, tile of its slab).
-__global__ __launch_bounds__(kBlock) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
+__global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
 {
     extern __shared__ uint32_t lds[];
-    uint32_t *ent = lds;                    // kTileB entries
-    uint32_t *hist = lds + kTileB;          // nf counters, then run cursors
-    uint32_t *base = hist + G.nf;           // nf run starts
+    uint32_t *ent = lds;                // kTileB entries as read
+    uint32_t *srt = ent + kTileB;       // kTileB entries sorted by region
+    uint32_t *cnt = srt + kTileB;       // nf counts, then run cursors
+    uint32_t *lbase = cnt + G.nf;       // nf first sorted slots
+    uint32_t *gbase = lbase + G.nf;     // nf first slab entries of the runs
+    uint32_t *wsum = gbase + G.nf;      // kWavesP
     const uint32_t c = blockIdx.x / tiles_per_bucket;
     const uint32_t tile = blockIdx.x % tiles_per_bucket;
     const uint64_t n_c = min((uint64_t)G.fillA[c], G.capA);
@@ -153,36 +241,58 @@ __global__ __launch_bounds__(kBlock) void k_bin_regions(Params P, BinGeom G, uin
     if (t0 >= n_c)
         return;
     const uint32_t n = (uint32_t)min((uint64_t)kTileB, n_c - t0);
-    const uint32_t *src = G.slabA + (uint64_t)c * G.capA + t0;
-    for (uint32_t b = threadIdx.x; b < G.nf; b += kBlock)
-        hist[b] = 0;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock)
-        ent[i] = src[i];
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
-        const uint32_t e = ent[i];
-        if (e != kSentinel)
-            atomicAdd(&hist[e >> G.rb], 1u);
+    const uint32_t *src = G.slabA + (uint64_t)c * G.capA + t0;   // 16-byte aligned: capA, t0 are multiples of 4
+    for (uint32_t b = threadIdx.x; b < G.nf; b += kBlockP)
+        cnt[b] = 0;
+    {
+        // unconditional loads (clamped to the last vector) so none waits for
+        // another; only ent[0..n) is used below
+        constexpr int kV = kTileB / 4 / kBlockP;
+        u32x4 v[kV];
+        const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+        const uint32_t n4 = (n + 3) / 4;
+#pragma unroll
+        for (int i = 0; i < kV; ++i)
+            v[i] = s4[min((uint32_t)(i * kBlockP) + threadIdx.x, n4 - 1)];
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const uint32_t j = i * kBlockP + threadIdx.x;
+            if (j < n4)
+                reinterpret_cast<u32x4 *>(ent)[j] = v[i];
+        }
     }
     __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kBlockP) {
+        const uint32_t e = ent[i];
+        if (e != kSentinel)
+            atomicAdd(&cnt[e >> G.rb], 1u);
+    }
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan(cnt, lbase, G.nf, wsum);
     uint32_t *fill = G.fillB + (uint64_t)c * G.nf;
     uint32_t *slab = G.slabB + (uint64_t)c * G.nf * G.capB;
-    reserve_runs(hist, base, G.nf, fill, slab, G.capB);
+    RunReservation res;
+    res.issue(cnt, G.nf, fill);
     __syncthreads();
-    const uint32_t maskB = (1u << G.rb) - 1;
-    const uint64_t cbit = (uint64_t)c << (G.rb + G.fb);
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < n; i += kBlockP) {
         const uint32_t e = ent[i];
         if (e == kSentinel)
             continue;
         const uint32_t f = e >> G.rb;
-        const uint32_t start = base[f];
-        if (start == kFail) {
+        srt[lbase[f] + atomicAdd(&cnt[f], 1u)] = e;
+    }
+    res.finish(gbase, G.nf, slab, G.capB);
+    __syncthreads();
+    const uint32_t maskB = (1u << G.rb) - 1;
+    const uint64_t cbit = (uint64_t)c << (G.rb + G.fb);
+    for (uint32_t i = threadIdx.x; i < total; i += kBlockP) {
+        const uint32_t e = srt[i];
+        const uint32_t f = e >> G.rb;
+        const uint32_t g = gbase[f];
+        if (g == kFail)
             direct_or(P, cbit + e);
-            continue;
-        }
-        const uint32_t rank = atomicAdd(&hist[f], 1u);
-        slab[(uint64_t)f * G.capB + start + rank] = e & maskB;
+        else
+            slab[(uint64_t)f * G.capB + g + (i - lbase[f])] = e & maskB;
     }
 }
 
@@ -199,20 +309,54 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G)
     if (w0 >= G.total_words)
         return;
     const uint32_t nw = (uint32_t)min((uint64_t)rwords, G.total_words - w0);   // a multiple of 4
-    uint4 *l4 = reinterpret_cast<uint4 *>(lds);
-    const uint4 *g4 = reinterpret_cast<const uint4 *>(P.index + w0);
-    for (uint32_t i = threadIdx.x; i < nw / 4; i += kBlock)
-        l4[i] = g4[i];
-    __syncthreads();
-    const uint32_t *src = G.slabB + g * G.capB;
-    for (uint64_t i = threadIdx.x; i < n; i += kBlock) {
-        const uint32_t e = src[i];
-        if (e != kSentinel)
-            atomicOr(&lds[e >> 5], 1u << (e & 31u));
+    u32x4 *l4 = reinterpret_cast<u32x4 *>(lds);
+    const u32x4 *g4 = reinterpret_cast<const u32x4 *>(P.index + w0);
+    const uint32_t nw4 = nw / 4;
+    constexpr int kRegion4PerThread = (1u << (kRegionLog2Max - 5)) / 4 / kBlock;
+    constexpr int kBatch = 8;
+    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(G.slabB + g * G.capB);   // capB is a multiple of 4
+    const uint64_t n4 = (n + 3) / 4;
+    // The region and the first batch of its targets are loaded together:
+    // every load is unconditional (clamped to an in-bounds vector) so all of
+    // them are in flight before the first use.
+    u32x4 ev[kBatch];
+    {
+        u32x4 rv[kRegion4PerThread];
+#pragma unroll
+        for (int i = 0; i < kRegion4PerThread; ++i)
+            rv[i] = g4[min((uint32_t)(i * kBlock) + threadIdx.x, nw4 - 1)];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            ev[i] = s4[min((uint64_t)i * kBlock + threadIdx.x, n4 - 1)];
+#pragma unroll
+        for (int i = 0; i < kRegion4PerThread; ++i) {
+            const uint32_t j = i * kBlock + threadIdx.x;
+            if (j < nw4)
+                l4[j] = rv[i];
+        }
     }
     __syncthreads();
-    uint4 *o4 = reinterpret_cast<uint4 *>(P.index + w0);
-    for (uint32_t i = threadIdx.x; i < nw / 4; i += kBlock)
+    auto apply = [&](uint64_t j0) {
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const uint64_t j = j0 + (uint64_t)i * kBlock + threadIdx.x;
+            const uint32_t e[4] = {ev[i].x, ev[i].y, ev[i].z, ev[i].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j * 4 + q < n && e[q] != kSentinel)
+                    atomicOr(&lds[e[q] >> 5], 1u << (e[q] & 31u));
+        }
+    };
+    apply(0);
+    for (uint64_t j0 = (uint64_t)kBatch * kBlock; j0 < n4; j0 += (uint64_t)kBatch * kBlock) {
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            ev[i] = s4[min(j0 + (uint64_t)i * kBlock + threadIdx.x, n4 - 1)];
+        apply(j0);
+    }
+    __syncthreads();
+    u32x4 *o4 = reinterpret_cast<u32x4 *>(P.index + w0);
+    for (uint32_t i = threadIdx.x; i < nw4; i += kBlock)
         o4[i] = l4[i];
 }
 

@@ -86,40 +86,90 @@ struct SeqCursor {
     }
 };
 
-// The wave visits the windows starting at bytes [p0, p_end) of a CSR of
-// sequences, 64 per step (lane l takes byte p + l), and calls
-// f(p, valid, canonical code, sequence) for each.
+// Walks the windows starting at bytes [p0, p_end) of a CSR of sequences, 64
+// per step: at each step lane l holds the window starting at byte p + l.
+// Bytes are fetched one group (64 bytes) ahead of their use.
+struct WindowWalker {
+    const uint64_t *offsets;
+    uint64_t n_seqs;
+    const uint8_t *chars;
+    uint64_t n_chars;
+    uint32_t k;
+    uint64_t kmask;
+    uint64_t p, p_end;
+    SeqCursor ca, cb;
+    Group A;
+    uint32_t raw_next;
+
+    __device__ __forceinline__ uint32_t fetch(uint64_t q) const { return q < n_chars ? chars[q] : 0u; }
+
+    __device__ __forceinline__ void classify(SeqCursor &c, uint64_t q, uint32_t raw, uint32_t &v, bool &bad,
+                                             bool &st) const
+    {
+        c.advance(offsets, n_seqs, q);
+        const bool in = q >= c.beg && q < c.end && q < n_chars;
+        v = in ? base_value(raw) : 4u;
+        bad = v > 3u;
+        st = in && q == c.beg;
+    }
+
+    __device__ __forceinline__ void init(const uint64_t *offsets_, uint64_t n_seqs_, const uint8_t *chars_,
+                                         uint64_t n_chars_, uint64_t p0, uint64_t p_end_, uint32_t k_,
+                                         uint64_t kmask_)
+    {
+        offsets = offsets_;
+        n_seqs = n_seqs_;
+        chars = chars_;
+        n_chars = n_chars_;
+        k = k_;
+        kmask = kmask_;
+        p = p0;
+        p_end = p_end_;
+        const uint32_t lane = lane_id();
+        ca.init(offsets, n_seqs, p0);
+        uint32_t v;
+        bool bad, st;
+        classify(ca, p0 + lane, fetch(p0 + lane), v, bad, st);
+        A = pack_group(v, bad, st);
+        cb = ca;
+        raw_next = fetch(p0 + kWave + lane);
+    }
+
+    // The next 64 windows (valid is false past p_end).  Call on every lane.
+    __device__ __forceinline__ void step(bool &valid, uint64_t &canon, uint64_t &seq)
+    {
+        const uint32_t lane = lane_id();
+        const uint32_t raw = raw_next;
+        raw_next = fetch(p + 2 * kWave + lane);
+        uint32_t v;
+        bool bad, st;
+        classify(cb, p + kWave + lane, raw, v, bad, st);
+        const Group Bg = pack_group(v, bad, st);
+        canon = 0;
+        valid = window_code(A, Bg, lane, k, kmask, canon) && p + lane < p_end;
+        seq = ca.s;
+        A = Bg;
+        ca = cb;
+        p += kWave;
+    }
+};
+
+// The wave visits the windows starting at bytes [p0, p_end) and calls
+// f(p, valid, canonical code, sequence) on every lane of the wave together
+// (valid is false past p_end), so f may use wave-wide operations.
 template <class F>
 __device__ __forceinline__ void wave_windows(const uint64_t *offsets, uint64_t n_seqs, const uint8_t *chars,
                                              uint64_t n_chars, uint64_t p0, uint64_t p_end, uint32_t k,
                                              uint64_t kmask, F &&f)
 {
-    const uint32_t lane = lane_id();
-    SeqCursor ca;
-    ca.init(offsets, n_seqs, p0);
-    SeqCursor cb = ca;
-    auto classify = [&](SeqCursor &c, uint64_t p, uint32_t &v, bool &bad, bool &st) {
-        c.advance(offsets, n_seqs, p);
-        const bool in = p >= c.beg && p < c.end && p < n_chars;
-        v = in ? base_value(chars[p]) : 4u;
-        bad = v > 3u;
-        st = in && p == c.beg;
-    };
-    uint32_t v;
-    bool bad, st;
-    classify(ca, p0 + lane, v, bad, st);
-    Group A = pack_group(v, bad, st);
-    cb = ca;
-    for (uint64_t p = p0; p < p_end; p += kWave) {
-        classify(cb, p + kWave + lane, v, bad, st);
-        const Group Bg = pack_group(v, bad, st);
-        const uint64_t pw = p + lane;
-        uint64_t canon = 0;
-        const bool valid = window_code(A, Bg, lane, k, kmask, canon);
-        if (pw < p_end)
-            f(pw, valid, canon, ca.s);
-        A = Bg;
-        ca = cb;
+    WindowWalker w;
+    w.init(offsets, n_seqs, chars, n_chars, p0, p_end, k, kmask);
+    while (w.p < p_end) {
+        const uint64_t pw = w.p + lane_id();
+        bool valid;
+        uint64_t canon, s;
+        w.step(valid, canon, s);
+        f(pw, valid, canon, s);
     }
 }
 
@@ -133,14 +183,158 @@ __global__ __launch_bounds__(kBlock) void k_extract(uint32_t k, uint64_t kmask, 
     if (p0 >= n_chars)
         return;
     const uint64_t pe = min(p0 + chunk, n_chars);
-    wave_windows(offsets, n_seqs, chars, n_chars, p0, pe, k, kmask,
-                 [&](uint64_t p, bool valid, uint64_t canon, uint64_t) { out[p] = valid ? canon : ~0ull; });
+    wave_windows(offsets, n_seqs, chars, n_chars, p0, pe, k, kmask, [&](uint64_t p, bool valid, uint64_t canon, uint64_t) {
+        if (p < pe)
+            out[p] = valid ? canon : ~0ull;
+    });
 }
 
 // ------------------------------------------------------------- insertion
 
+__device__ __forceinline__ uint64_t readfirstlane64(uint64_t v)
+{
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+// The partition columns of the sequence a wave is in: lane r holds phi_r(set)
+// (r < R), read back with readlane, so the hot loop issues no memory load
+// for them.  Refilled only when the wave moves to another sequence.  Lane t
+// also holds the position seed s_t (t = r*eta + j), filled once: reading a
+// seed with readlane avoids a scalar load (and its wait, which would also
+// drain pending LDS operations) per bit target.
+struct SetCache {
+    uint64_t s = ~0ull;
+    uint32_t set = 0;
+    uint32_t cols = 0;
+    uint64_t seed = 0;
+
+    __device__ __forceinline__ void init_seeds(const Params &P)
+    {
+        const uint32_t lane = lane_id();
+#pragma unroll
+        for (uint32_t t = 0; t < RAMBO_MAX_RETA; ++t)
+            if (lane == t)
+                seed = P.seeds[t];
+    }
+};
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l)
+{
+    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((uint32_t)v, l);
+}
+
+// Alg. 1 for the windows the wave holds: each lane with a valid window (term
+// x of sequence s) gets on_target(gb) for each of its R*eta bit targets, gb
+// being the global bit address in the bit-sliced index of (repetition r,
+// row pos_{r,j}(x), column phi_r(set)).  When every valid lane is in the same
+// sequence - the common case - the set and its columns come from the cache.
+// With compile-time R_T and ETA_T all R*eta hashes of a window are computed
+// as independent chains before the first target is emitted (instruction-level
+// parallelism for the 64-bit multiplies); R_T == 0 is the run-time path.
+template <int R_T, int ETA_T, class F>
+__device__ __forceinline__ void wave_targets(const Params &P, const uint32_t *set_ids, SetCache &cache, bool valid,
+                                             uint64_t x, uint64_t s, F &&on_target)
+{
+    if constexpr (R_T > 0) {
+        const uint64_t live = __ballot(valid);
+        if (!live)
+            return;
+        const uint64_t rep_bits = P.words_per_rep * 32;
+        const int first = __builtin_ctzll(live);
+        const uint64_t s0 = readfirstlane64(__shfl(s, first, kWave));
+        const bool uniform = __ballot(valid && s != s0) == 0;
+        uint32_t cols[R_T];
+        bool ok = valid;
+        if (uniform) {
+            if (s0 != cache.s) {
+                cache.s = s0;
+                cache.set = __builtin_amdgcn_readfirstlane(set_ids[s0]);
+                const uint32_t lane = lane_id();
+                cache.cols = (cache.set < P.K && lane < P.R) ? P.phi[(uint64_t)lane * P.K + cache.set] : 0u;
+            }
+            if (cache.set >= P.K) {
+                if ((int)lane_id() == first)
+                    atomicOr(P.err, kErrSetId);
+                return;
+            }
+#pragma unroll
+            for (int r = 0; r < R_T; ++r)
+                cols[r] = (uint32_t)__builtin_amdgcn_readlane(cache.cols, r);
+        } else {
+            const uint32_t set = valid ? set_ids[s] : 0u;
+            if (valid && set >= P.K)
+                atomicOr(P.err, kErrSetId);
+            ok = valid && set < P.K;
+#pragma unroll
+            for (int r = 0; r < R_T; ++r)
+                cols[r] = ok ? P.phi[(uint64_t)r * P.K + set] : 0u;
+        }
+        uint64_t gb[R_T * ETA_T];
+#pragma unroll
+        for (int t = 0; t < R_T * ETA_T; ++t)
+            gb[t] = (uint64_t)(t / ETA_T) * rep_bits + cols[t / ETA_T] +
+                    (bf_position(x, readlane64(cache.seed, t), P) << P.S_log2);
+        if (ok) {
+#pragma unroll
+            for (int t = 0; t < R_T * ETA_T; ++t)
+                on_target(gb[t]);
+        }
+        return;
+    }
+    const uint64_t live = __ballot(valid);
+    if (!live)
+        return;
+    const uint64_t rep_bits = P.words_per_rep * 32;
+    const int first = __builtin_ctzll(live);
+    const uint64_t s0 = readfirstlane64(__shfl(s, first, kWave));
+    if (__ballot(valid && s != s0) == 0) {
+        if (s0 != cache.s) {
+            cache.s = s0;
+            cache.set = __builtin_amdgcn_readfirstlane(set_ids[s0]);
+            const uint32_t lane = lane_id();
+            cache.cols = (cache.set < P.K && lane < P.R) ? P.phi[(uint64_t)lane * P.K + cache.set] : 0u;
+        }
+        if (cache.set >= P.K) {
+            if ((int)lane_id() == first)
+                atomicOr(P.err, kErrSetId);
+            return;
+        }
+        for (uint32_t r = 0, t = 0; r < P.R; ++r) {
+            const uint64_t base = r * rep_bits + (uint32_t)__builtin_amdgcn_readlane(cache.cols, r);
+            for (uint32_t j = 0; j < P.eta; ++j, ++t) {
+                const uint64_t seed = readlane64(cache.seed, t);
+                if (valid)
+                    on_target(base + (bf_position(x, seed, P) << P.S_log2));
+            }
+        }
+        return;
+    }
+    const uint32_t set = valid ? set_ids[s] : 0u;
+    if (valid && set >= P.K)
+        atomicOr(P.err, kErrSetId);
+    const bool ok = valid && set < P.K;
+    for (uint32_t r = 0, t = 0; r < P.R; ++r) {
+        const uint64_t base = r * rep_bits + (ok ? P.phi[(uint64_t)r * P.K + set] : 0u);
+        for (uint32_t j = 0; j < P.eta; ++j, ++t) {
+            const uint64_t seed = readlane64(cache.seed, t);
+            if (ok)
+                on_target(base + (bf_position(x, seed, P) << P.S_log2));
+        }
+    }
+}
+
+// Set one bit target with a global atomic (the result is not used, so this is
+// a non-returning atomic; OR is order-free and idempotent).
+__device__ __forceinline__ void direct_or(const Params &P, uint64_t gb)
+{
+    atomicOr(P.index + (gb >> 5), 1u << (gb & 31u));
+}
+
 // Alg. 1: every valid window of sequence s goes into the cell phi_r(set) of
 // each repetition r, at its eta positions.
+template <int R_T, int ETA_T>
 __global__ __launch_bounds__(kBlock) void k_insert_seqs(Params P, const uint32_t *set_ids, const uint64_t *offsets,
                                                         uint64_t n_seqs, const uint8_t *chars, uint64_t n_chars,
                                                         uint64_t chunk)
@@ -150,20 +344,12 @@ __global__ __launch_bounds__(kBlock) void k_insert_seqs(Params P, const uint32_t
     if (p0 >= n_chars)
         return;
     const uint64_t pe = min(p0 + chunk, n_chars);
+    SetCache cache;
+    cache.init_seeds(P);
     wave_windows(offsets, n_seqs, chars, n_chars, p0, pe, P.k, P.kmask,
                  [&](uint64_t, bool valid, uint64_t x, uint64_t s) {
-                     if (!valid)
-                         return;
-                     const uint32_t set = set_ids[s];
-                     if (set >= P.K) {
-                         atomicOr(P.err, kErrSetId);
-                         return;
-                     }
-                     for (uint32_t r = 0; r < P.R; ++r) {
-                         const uint32_t col = P.phi[(uint64_t)r * P.K + set];
-                         for (uint32_t j = 0; j < P.eta; ++j)
-                             set_cell_bit(P, r, bf_position(x, P.seeds[r * P.eta + j], P), col);
-                     }
+                     wave_targets<R_T, ETA_T>(P, set_ids, cache, valid, x, s,
+                                              [&](uint64_t gb) { direct_or(P, gb); });
                  });
 }
 

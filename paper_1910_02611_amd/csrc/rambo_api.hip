@@ -169,12 +169,45 @@ uint32_t log2_exact(uint64_t v)
     return l;
 }
 
+// Insert kernels with compile-time R and eta for the shapes of the
+// workloads, the run-time kernel for every other shape.
+using InsertSeqsFn = void (*)(Params, const uint32_t *, const uint64_t *, uint64_t, const uint8_t *, uint64_t,
+                              uint64_t);
+using BinWindowsFn = void (*)(Params, BinGeom, const uint32_t *, const uint64_t *, uint64_t, const uint8_t *,
+                              uint64_t, uint64_t, uint64_t, uint32_t, uint32_t);
+
+template <class Fn, template <int, int> class K>
+Fn pick_shape(uint32_t R, uint32_t eta)
+{
+    if (eta == 2) {
+        switch (R) {
+        case 3: return K<3, 2>::fn;
+        case 4: return K<4, 2>::fn;
+        case 5: return K<5, 2>::fn;
+        case 6: return K<6, 2>::fn;
+        default: break;
+        }
+    }
+    return K<0, 0>::fn;
+}
+
+template <int R_T, int ETA_T>
+struct InsertSeqsK {
+    static constexpr InsertSeqsFn fn = k_insert_seqs<R_T, ETA_T>;
+};
+template <int R_T, int ETA_T>
+struct BinWindowsK {
+    static constexpr BinWindowsFn fn = k_bin_windows<R_T, ETA_T>;
+};
+
 // ------------------------------------------------- partitioned insertion
 
-constexpr uint32_t kRegionLog2 = 19;        // 2^19 bits = 64 KiB of LDS per region
-constexpr uint32_t kMaxCoarse = 8192;       // stage-A LDS: 2 * 8192 counters
+constexpr uint32_t kRegionLog2 = kRegionLog2Max;   // 64 KiB of LDS per region
+constexpr uint32_t kMaxCoarse = 4096;       // stage-A LDS: tile plus 3 words per coarse bucket
+constexpr size_t kMaxLds = 160 * 1024;      // LDS per workgroup on gfx950
 constexpr double kAtomicRate = 1.7e10;      // measured random atomicOr/s over a large buffer
 constexpr double kStreamRate = 4.0e12;      // streaming bytes/s the partitioned path sustains
+constexpr uint32_t kStageAWindowsPerWave = 2048;
 
 void plan_partition(rambo *h)
 {
@@ -190,7 +223,8 @@ void plan_partition(rambo *h)
     const uint64_t na = div_up(total_bits, 1ull << (G.rb + G.fb));
     G.na = (uint32_t)na;
     G.total_words = total_words;
-    h->part_ok = na <= kMaxCoarse;
+    h->part_ok = na <= kMaxCoarse && (uint64_t)h->cfg.R * h->cfg.eta <= kMaxTargetsPerWindow &&
+                 lds_bytes_stage_a(G.na) <= kMaxLds && lds_bytes_stage_b(G.nf) <= kMaxLds;
 }
 
 uint64_t scratch_bytes_for(const BinGeom &G, uint64_t T, uint64_t &capA, uint64_t &capB)
@@ -232,6 +266,16 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
         return fail(h, RAMBO_ENOMEM, "insert scratch allocation failed");
     }
     BinGeom &G = h->bin;
+    // stages A and B use more than the default 64 KiB of dynamic LDS
+    const BinWindowsFn binA = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(binA),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_a(G.na)) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_bin_regions),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_b(G.nf)) != hipSuccess) {
+        (void)hipFree(h->bin_mem);
+        h->bin_mem = nullptr;
+        return fail(h, RAMBO_EHIP, "cannot raise the LDS limit of the insert kernels");
+    }
     G.capA = capA;
     G.capB = capB;
     uint32_t *p = static_cast<uint32_t *>(h->bin_mem);
@@ -269,16 +313,20 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
         return rc;
     BinGeom &G = h->bin;
     const uint64_t batch_windows = h->bin_targets / RE;
-    const uint64_t tile_windows = (uint64_t)kWavesPerBlock * kWindowsPerWaveA;
+    // stage A: each round takes `steps` steps of every wave (at most kTileA targets)
+    const uint32_t steps = (uint32_t)(kTileA / (kBlockP * RE));
+    const uint32_t rounds = (uint32_t)div_up(kStageAWindowsPerWave, (uint64_t)steps * kWave);
+    const uint64_t block_windows = (uint64_t)kWavesP * rounds * steps * kWave;
     const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
-    const size_t ldsA = 2ull * G.na * 4, ldsB = (kTileB + 2ull * G.nf) * 4, ldsC = (1ull << (G.rb - 5)) * 4;
+    const size_t ldsA = lds_bytes_stage_a(G.na), ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     for (uint64_t p = 0; p < n_chars; p += batch_windows) {
         const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
         hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
                            (uint64_t)G.na + (uint64_t)G.na * G.nf);
-        hipLaunchKernelGGL(k_bin_windows, dim3((uint32_t)div_up(pe - p, tile_windows)), dim3(kBlock), ldsA, stream,
-                           h->P, G, set_ids, offsets, n_seqs, chars, n_chars, p, pe);
-        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlock), ldsB, stream, h->P, G, tpb);
+        const BinWindowsFn binA = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
+        hipLaunchKernelGGL(binA, dim3((uint32_t)div_up(pe - p, block_windows)), dim3(kBlockP), ldsA, stream, h->P, G,
+                           set_ids, offsets, n_seqs, chars, n_chars, p, pe, steps, rounds);
+        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb);
         hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G);
         if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
             return rc;
@@ -440,8 +488,9 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
     if (use_partitioned(h, n_chars))
         return insert_seqs_partitioned(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
     const uint64_t waves = div_up(n_chars, kChunk);
-    hipLaunchKernelGGL(k_insert_seqs, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P,
-                       set_ids, offsets, n_seqs, chars, n_chars, kChunk);
+    const InsertSeqsFn ins = pick_shape<InsertSeqsFn, InsertSeqsK>(h->cfg.R, h->cfg.eta);
+    hipLaunchKernelGGL(ins, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P, set_ids,
+                       offsets, n_seqs, chars, n_chars, kChunk);
     return launch_check(h, "rambo_insert_seqs");
 }
 
