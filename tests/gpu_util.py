@@ -77,9 +77,10 @@ def gpu_rows(g: Rambo, r: int, rows: np.ndarray) -> np.ndarray:
         spw = S // 32
         word0 = r * g.words_per_rep + rows * spw
         lo, hi = int(word0.min()), int(word0.max()) + spw
-        w = host_u32(g.index_words(lo, hi - lo))
-        sel = np.stack([w[word0 - lo + i] for i in range(spw)], axis=1)
-        bits = np.unpackbits(sel.view(np.uint8), axis=1, bitorder="little")
+        w = g.index_words(lo, hi - lo)      # device copy; gathered on the device
+        idx = torch.from_numpy(word0 - lo).to(w.device)
+        sel = np.stack([host_u32(w[idx + i]) for i in range(spw)], axis=1)
+        bits = np.unpackbits(np.ascontiguousarray(sel).view(np.uint8), axis=1, bitorder="little")
         return bits[:, : g.B]
     rpw = 32 // S
     word = r * g.words_per_rep + rows // rpw

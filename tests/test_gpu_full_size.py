@@ -1,0 +1,78 @@
+"""Parity at the full size of the mid workload (K = 1 000 genome sets, B = 50,
+R = 4, m = 2^28, eta = 2; ~2.7e8 inserts), in the launch configuration
+bench.py times (rambo_insert_seqs with the automatic policy, batched
+rambo_query_kmers).  The oracle builds the whole index on the host; the GPU
+index is compared through per-cell fill counts over every bit, sampled rows,
+and sampled queries and reads."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_02611_amd import synth
+from gpu_util import dev, host_u32, make_pair, gpu_insert_seqs, first_codes_gpu, first_codes_oracle, gpu_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _column_popcounts(g) -> np.ndarray:
+    """Number of set bits of every cell (r, b), counted on the GPU over the
+    whole bit-sliced index (layout of include/rambo.h)."""
+    S = g.row_bits
+    assert S >= 32   # one or more whole words per row
+    out = np.zeros((g.R, g.B), np.int64)
+    for r in range(g.R):
+        rows = g.index_words(r * g.words_per_rep, g.m * S // 32).view(g.m, S // 32)
+        for b in range(g.B):
+            bit = b % 32
+            mask = (1 << bit) if bit < 31 else -(1 << 31)   # int32 view of bit 31
+            out[r, b] = int(torch.count_nonzero(torch.bitwise_and(rows[:, b // 32], mask)))
+        del rows
+    return out
+
+
+@pytest.fixture(scope="module")
+def mid():
+    cfg = synth.INDEX_MID
+    sets = synth.config_mid()
+    o, g = make_pair(cfg, seed=2002)
+    gpu_insert_seqs(g, sets)
+    assert g.sync_status() == 0
+    nthreads = min(os.cpu_count() or 1, 16)
+    assert o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, nthreads) == 0
+    return cfg, sets, o, g, nthreads
+
+
+def test_mid_fill_counts_every_cell(mid):
+    cfg, sets, o, g, _ = mid
+    assert np.array_equal(_column_popcounts(g), o.fill_counts().astype(np.int64))
+
+
+def test_mid_sampled_rows(mid):
+    cfg, sets, o, g, _ = mid
+    rng = np.random.default_rng(7)
+    for r in range(cfg["R"]):
+        rows = np.sort(rng.choice(cfg["m"], size=20_000, replace=False)).astype(np.uint64)
+        assert np.array_equal(gpu_rows(g, r, rows), o.bits_at(r, rows)), r
+
+
+def test_mid_sampled_queries(mid):
+    cfg, sets, o, g, nthreads = mid
+    q = synth.kmer_queries(3002, sets, 200_000, cfg["k"])   # a prefix-sized sample of the bench's stream
+    codes = first_codes_gpu(g, q)
+    got = host_u32(g.query_kmers(codes))
+    want = o.query_kmers(first_codes_oracle(q, cfg["k"]), nthreads)
+    assert np.array_equal(got, want)
+    # present queries always report at least one set (zero false negatives)
+    assert (got[q.meta["present"]].any(axis=1)).all()
+
+
+def test_mid_sampled_reads(mid):
+    cfg, sets, o, g, nthreads = mid
+    rd = synth.reads(3005, sets, 1500, median_len=300, min_len=31, max_len=3000, substr_frac=0.7)
+    m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    want, wn = o.query_seqs(rd.offsets, rd.chars, nthreads)
+    assert np.array_equal(host_u32(nk), wn.astype(np.uint32))
+    assert np.array_equal(host_u32(m), want)
