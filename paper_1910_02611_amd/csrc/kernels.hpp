@@ -544,39 +544,28 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
 
 // ------------------------------------------------------ sequence queries
 
-// Sec. 3.2.1: one wave per read.  Each step takes 64 windows (one per lane),
-// gathers their rows, ANDs the group masks over the lanes and into the read's
-// running masks G (LDS), and stops probing once some repetition is empty (the
-// first conclusive FALSE).  Valid windows are still counted to the end.  The
-// read is expanded once: by the partition identity, AND over k-mers of the
-// expanded answers equals the expansion of the AND of the group masks.
-template <int SW, int R_T, int ETA_T>
-__global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t *offsets, uint64_t n_reads,
-                                                       const uint8_t *chars, uint64_t n_chars, uint32_t *out,
-                                                       uint32_t *out_nk)
+__device__ __forceinline__ void wave_sync_lds()
 {
-    constexpr int L = SW < 4 ? SW : 4;
-    constexpr int NSL = SW / L;
-    constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
-    __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
-
-    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
-    const uint32_t lane = lane_id();
-    const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
-    if (q >= n_reads)
-        return;
-    uint32_t *G = Gs[wv];
-    for (uint32_t i = lane; i < R * SW; i += kWave)
-        G[i] = ~0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    uint64_t p0 = offsets[q];
-    const uint64_t pe = min(offsets[q + 1], n_chars);
-    if (p0 > pe)
-        p0 = pe;
+// Sec. 3.2.1 for the windows of one read (bytes end at pe) that start in
+// [p_start, p_stop): each step takes 64 windows (one per lane), gathers their
+// rows, ANDs the group masks over the lanes and into the running masks G
+// (R x SW words of LDS, wave-private), and stops probing once some repetition
+// is empty (the first conclusive FALSE).  Valid windows are still counted, in
+// nk, to the end of the range.
+template <int SW, int R_T, int ETA_T>
+__device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t *chars, uint64_t pe,
+                                                 uint64_t p_start, uint64_t p_stop, uint32_t *G, uint32_t &nk,
+                                                 bool &dead)
+{
+    constexpr int L = SW < 4 ? SW : 4;
+    constexpr int NSL = SW / L;
+    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
+    const uint32_t lane = lane_id();
     const uint64_t kmask = P.kmask;
     auto read_byte = [&](uint64_t p, uint32_t &v, bool &bad) {
         v = p < pe ? base_value(chars[p]) : 4u;
@@ -584,15 +573,13 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
     };
     uint32_t v;
     bool bad;
-    read_byte(p0 + lane, v, bad);
+    read_byte(p_start + lane, v, bad);
     Group A = pack_group(v, bad, false);
-    uint32_t nk = 0;
-    bool dead = false;
-    for (uint64_t p = p0; p < pe; p += kWave) {
+    for (uint64_t p = p_start; p < p_stop; p += kWave) {
         read_byte(p + kWave + lane, v, bad);
         const Group Bg = pack_group(v, bad, false);
         uint64_t x = 0;
-        const bool valid = (p + lane < pe) && window_code(A, Bg, lane, P.k, kmask, x);
+        const bool valid = (p + lane < p_stop) && window_code(A, Bg, lane, P.k, kmask, x);
         nk += (uint32_t)__popcll(__ballot(valid));
         if (!dead) {
 #pragma unroll 1
@@ -621,13 +608,42 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync_lds();
             dead = any_rep_empty(G, R, SW);
         }
         A = Bg;
     }
+}
+
+// Sec. 3.2.1: one wave per read.  The read is expanded once: by the partition
+// identity, AND over k-mers of the expanded answers equals the expansion of
+// the AND of the group masks.
+template <int SW, int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t *offsets, uint64_t n_reads,
+                                                       const uint8_t *chars, uint64_t n_chars, uint32_t *out,
+                                                       uint32_t *out_nk)
+{
+    constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
+    __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
+
+    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (q >= n_reads)
+        return;
+    uint32_t *G = Gs[wv];
+    for (uint32_t i = lane; i < R * SW; i += kWave)
+        G[i] = ~0u;
+    wave_sync_lds();
+
+    uint64_t p0 = offsets[q];
+    const uint64_t pe = min(offsets[q + 1], n_chars);
+    if (p0 > pe)
+        p0 = pe;
+    uint32_t nk = 0;
+    bool dead = false;
+    read_windows_and<SW, R_T, ETA_T>(P, chars, pe, p0, pe, G, nk, dead);
     if (out_nk && lane == 0)
         out_nk[q] = nk;
     uint32_t *o = out + q * P.W;

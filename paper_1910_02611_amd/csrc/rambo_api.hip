@@ -5,12 +5,14 @@
 // arguments on the host, then enqueues kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
 
 #include "insert_part.hpp"
+#include "query_queue.hpp"
 #include "kernels.hpp"
 #include "rambo.h"
 
@@ -34,6 +36,14 @@ struct rambo {
     BinGeom bin{};
     uint64_t bin_targets = 0;        // targets per batch the scratch holds
     void *bin_mem = nullptr;
+    // batched sequence queries
+    int query_mode = RAMBO_QUERY_AUTO;
+    uint32_t query_chunk = 512;        // bytes per work item
+    uint32_t query_waves_per_cu = 16;  // persistent grid
+    int num_cus = 256;
+    void *rq_mem = nullptr;
+    uint64_t rq_cap = 0;               // reads the queue state holds
+    ReadQueue rq{};
 };
 
 namespace {
@@ -153,6 +163,26 @@ struct QuerySeqsLaunch {
     void operator()() const { launch_query_seqs_t<SW, R_T, ETA_T>(h, offsets, n_reads, chars, n_chars, out, nk, st); }
 };
 
+// The persistent work-queue launch (k_rq_persist); its per-read state is
+// already set up by k_rq_setup and k_rq_scan.
+struct QuerySeqsQueueLaunch {
+    const rambo *h;
+    const uint64_t *offsets;
+    uint64_t n_reads;
+    const uint8_t *chars;
+    uint64_t n_chars;
+    uint32_t *out;
+    uint32_t *nk;
+    hipStream_t st;
+    uint32_t grid;
+    template <int SW, int R_T, int ETA_T>
+    void operator()() const
+    {
+        hipLaunchKernelGGL((k_rq_persist<SW, R_T, ETA_T>), dim3(grid), dim3(kBlock), 0, st, h->P, h->rq, offsets,
+                           n_reads, chars, n_chars, h->query_chunk, out, nk);
+    }
+};
+
 uint32_t next_pow2(uint32_t v)
 {
     uint32_t p = 1;
@@ -199,6 +229,47 @@ template <int R_T, int ETA_T>
 struct BinWindowsK {
     static constexpr BinWindowsFn fn = k_bin_windows<R_T, ETA_T>;
 };
+
+// ------------------------------------------------ batched read queries
+
+// Per-read state of the work-queue launch, grown to hold n_reads reads.
+int ensure_read_queue(rambo *h, uint64_t n_reads)
+{
+    if (n_reads <= h->rq_cap && h->rq_mem)
+        return RAMBO_OK;
+    uint64_t cap = h->rq_cap ? h->rq_cap : 1024;
+    while (cap < n_reads)
+        cap *= 2;
+    const uint64_t rsw = (uint64_t)h->cfg.R * h->SW;
+    const uint64_t words = cap * (rsw + 4) + (cap + 1) + 1;
+    if (h->rq_mem) {
+        const int rc = hip_check(h, hipDeviceSynchronize(), "read queue resize");
+        if (rc)
+            return rc;
+        (void)hipFree(h->rq_mem);
+        h->rq_mem = nullptr;
+        h->rq_cap = 0;
+    }
+    if (hipMalloc(&h->rq_mem, words * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        h->rq_mem = nullptr;
+        return fail(h, RAMBO_ENOMEM, "read queue allocation failed");
+    }
+    uint32_t *p = static_cast<uint32_t *>(h->rq_mem);
+    h->rq.G = p;
+    p += cap * rsw;
+    h->rq.nk = p;
+    p += cap;
+    h->rq.dead = p;
+    p += cap;
+    h->rq.remaining = p;
+    p += cap;
+    h->rq.items = p;
+    p += cap + 1;
+    h->rq.counter = p;
+    h->rq_cap = cap;
+    return RAMBO_OK;
+}
 
 // ------------------------------------------------- partitioned insertion
 
@@ -362,6 +433,13 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
     h->words_per_rep = div_up(div_up(c.m * h->S, 32), 4) * 4;
     h->index_bytes = (uint64_t)c.R * h->words_per_rep * 4;
     plan_partition(h);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            h->num_cus = cus;
+        (void)hipGetLastError();
+    }
 
     // Seeds: one splitmix64 stream, in the documented order.
     uint64_t st = c.seed;
@@ -443,7 +521,20 @@ extern "C" void rambo_destroy(rambo_t *h)
         (void)hipFree(h->err);
     if (h->bin_mem)
         (void)hipFree(h->bin_mem);
+    if (h->rq_mem)
+        (void)hipFree(h->rq_mem);
     delete h;
+}
+
+extern "C" int rambo_set_query_policy(rambo_t *h, int mode, uint32_t chunk_bytes, uint32_t waves_per_cu)
+{
+    if (!h || mode < RAMBO_QUERY_AUTO || mode > RAMBO_QUERY_QUEUE || chunk_bytes > (1u << 24) ||
+        waves_per_cu > 64)
+        return RAMBO_EINVAL;
+    h->query_mode = mode;
+    h->query_chunk = chunk_bytes ? chunk_bytes : 512;
+    h->query_waves_per_cu = waves_per_cu ? waves_per_cu : 16;
+    return RAMBO_OK;
 }
 
 extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes)
@@ -516,7 +607,21 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
         return RAMBO_OK;
     if (!offsets || !out_masks || (n_chars > 0 && !chars))
         return fail(h, RAMBO_EINVAL, "rambo_query_seqs: NULL array");
-    with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream});
+    if (h->query_mode == RAMBO_QUERY_WAVE_PER_READ) {
+        with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream});
+        return launch_check(h, "rambo_query_seqs");
+    }
+    int rc = ensure_read_queue(h, n_reads);
+    if (rc)
+        return rc;
+    const uint32_t rsw = h->cfg.R * h->SW;
+    hipLaunchKernelGGL(k_rq_setup, dim3((uint32_t)div_up(n_reads, kBlock)), dim3(kBlock), 0, stream, h->rq, offsets,
+                       n_reads, n_chars, h->query_chunk, rsw);
+    hipLaunchKernelGGL(k_rq_scan, dim3(1), dim3(1024), 0, stream, h->rq.items, n_reads);
+    const uint64_t max_items = n_chars / h->query_chunk + n_reads + 1;
+    const uint64_t waves = std::min<uint64_t>(max_items, (uint64_t)h->num_cus * h->query_waves_per_cu);
+    const uint32_t grid = (uint32_t)div_up(waves, kWavesPerBlock);
+    with_row_words(h, QuerySeqsQueueLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream, grid});
     return launch_check(h, "rambo_query_seqs");
 }
 

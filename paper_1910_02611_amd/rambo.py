@@ -23,6 +23,7 @@ EHIP = -1000
 ECODE = -1001
 FLAG_IDENTITY_PARTITION = 1
 INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED = 0, 1, 2
+QUERY_AUTO, QUERY_WAVE_PER_READ, QUERY_QUEUE = 0, 1, 2
 NO_KMER = -1   # UINT64_MAX viewed as int64
 
 MAX_B = 4096
@@ -70,6 +71,7 @@ EXPORTS = {
                                               ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_set_insert_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]),
+    "rambo_set_query_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
     "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rambo_copy_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
@@ -220,6 +222,11 @@ class Rambo:
     def set_insert_policy(self, mode: int = 0, scratch_bytes: int = 0):
         """INSERT_AUTO / INSERT_DIRECT / INSERT_PARTITIONED; same index bits."""
         self._check(lib().rambo_set_insert_policy(self._h, mode, scratch_bytes), "rambo_set_insert_policy")
+
+    def set_query_policy(self, mode: int = 0, chunk_bytes: int = 0, waves_per_cu: int = 0):
+        """QUERY_AUTO / QUERY_WAVE_PER_READ / QUERY_QUEUE; same answers."""
+        self._check(lib().rambo_set_query_policy(self._h, mode, chunk_bytes, waves_per_cu),
+                    "rambo_set_query_policy")
 
     def clear(self, stream=None):
         self._check(lib().rambo_clear(self._h, _stream(stream)), "rambo_clear")

@@ -1,0 +1,69 @@
+"""The work-queue launch of batched sequence queries gives the oracle's answers
+for every tile shape, including chunks far smaller than the reads (many
+chunks per read, early exit across chunks) and grids smaller than the work."""
+import numpy as np
+import pytest
+
+from paper_1910_02611_amd import synth
+from paper_1910_02611_amd import rambo as rb
+from gpu_util import dev, host_u32, make_pair, gpu_insert_seqs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    cfg = synth.INDEX_TINY
+    sets = synth.config_tiny()
+    o, g = make_pair(cfg, seed=2001)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    gpu_insert_seqs(g, sets)
+    rd = synth.config_batched_reads(sets, 2500, seed=3009)
+    want, wn = o.query_seqs(rd.offsets, rd.chars, nthreads=8)
+    return cfg, sets, g, rd, want, wn.astype(np.uint32)
+
+
+@pytest.mark.parametrize("mode,chunk,wpc", [
+    (rb.QUERY_WAVE_PER_READ, 0, 0),
+    (rb.QUERY_QUEUE, 0, 0),
+    (rb.QUERY_QUEUE, 64, 1),
+    (rb.QUERY_QUEUE, 100, 2),
+    (rb.QUERY_QUEUE, 4096, 32),
+    (rb.QUERY_QUEUE, 1 << 20, 4),
+])
+def test_queue_tiles_match_oracle(tiny, mode, chunk, wpc):
+    cfg, sets, g, rd, want, wn = tiny
+    g.set_query_policy(mode, chunk, wpc)
+    try:
+        for _ in range(2):   # the per-read state is reset by every call
+            m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+            assert np.array_equal(host_u32(nk), wn)
+            assert np.array_equal(host_u32(m), want)
+    finally:
+        g.set_query_policy(rb.QUERY_AUTO)
+
+
+def test_queue_grows_its_state(tiny):
+    cfg, sets, g, rd, want, wn = tiny
+    # a first small batch, then the full one: the state is regrown in place
+    few = synth.SeqBatch(rd.chars[: int(rd.offsets[10])].copy(), rd.offsets[:11].copy())
+    m, _ = g.query_seqs(dev(few.offsets, np.int64), dev(few.chars, np.uint8))
+    assert np.array_equal(host_u32(m), want[:10])
+    m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    assert np.array_equal(host_u32(m), want) and np.array_equal(host_u32(nk), wn)
+
+
+def test_queue_mid_shape_reads():
+    """Another row width and shape (B = 50: two-word rows; R = 4)."""
+    cfg = dict(K=200, B=50, R=4, eta=2, k=31, m=1 << 16)
+    sets = synth.genome_sets(4242, K=200, n_ancestors=10, ancestor_len=3000)
+    o, g = make_pair(cfg, seed=77)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    gpu_insert_seqs(g, sets)
+    rd = synth.reads(4243, sets, 800, median_len=400, min_len=1, max_len=3000, substr_frac=0.8)
+    want, wn = o.query_seqs(rd.offsets, rd.chars, nthreads=8)
+    for chunk in (0, 128):
+        g.set_query_policy(rb.QUERY_QUEUE, chunk, 0)
+        m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+        assert np.array_equal(host_u32(nk), wn.astype(np.uint32))
+        assert np.array_equal(host_u32(m), want)
