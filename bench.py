@@ -129,6 +129,55 @@ def cpu_baseline(sets, q, cfg, query_budget_s: float = 12.0):
     }
 
 
+def batched_reads(n_reads: int, plain_prefix: int = 2000):
+    """Batched sequence queries (Sec. 3.2.1) on the tiny index: 64 sets, B=8,
+    R=3, m=2^18; reads of lognormal length (median 1 000, 100-10 000 bp), 70%
+    substrings of a set genome.  One persistent work-queue launch with the
+    autotuned tile, against one wave per read and one launch per read."""
+    import torch
+    from paper_1910_02611_amd import autotune, synth
+    from paper_1910_02611_amd.rambo import Rambo, QUERY_WAVE_PER_READ
+
+    cfg = synth.INDEX_TINY
+    sets = synth.config_tiny()
+    g = Rambo(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed=2001)
+    g.insert_seqs(to_dev(sets.set_ids, np.int32), to_dev(sets.offsets, np.int64), to_dev(sets.chars, np.uint8))
+    t = time.time()
+    rd = synth.config_batched_reads(sets, n_reads)
+    log("batched reads: %d reads, %d bases (%.1f s)" % (rd.n, rd.chars.size, time.time() - t))
+    off, ch = to_dev(rd.offsets, np.int64), to_dev(rd.chars, np.uint8)
+    tune = autotune.tune_query_seqs(g, off, ch, tag="batched-reads", use_cache=False)
+    out = torch.empty((rd.n, g.W), dtype=torch.int32, device="cuda")
+    nk = torch.empty(rd.n, dtype=torch.int32, device="cuda")
+    t_q = autotune.time_query_seqs(g, off, ch, out, nk, reps=5)
+    windows = int(nk.to(torch.int64).sum())
+    g.set_query_policy(QUERY_WAVE_PER_READ)
+    out_w = torch.empty_like(out)
+    t_w = autotune.time_query_seqs(g, off, ch, out_w, nk, reps=5)
+    same_w = bool(torch.equal(out, out_w))
+    # one launch per read on a prefix
+    pre = min(plain_prefix, rd.n)
+    off_p = off[: pre + 1].contiguous()
+    g.query_seqs(off_p, ch, plain=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out_p, _ = g.query_seqs(off_p, ch, plain=True)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    same_p = bool(torch.equal(out_p, out[:pre]))
+    g.close()
+    log("batched reads: queue %.3f ms (%.3g reads/s, %.3g k-mers/s), wave-per-read %.3f ms, plain %.3g reads/s"
+        % (t_q * 1e3, rd.n / t_q, windows / t_q, t_w * 1e3, pre / t_p))
+    return {
+        "workload": "batched reads: tiny index (K=64, B=8, R=3, m=2^18, eta=2); %d reads, lognormal "
+                    "100-10000 bp (median 1000), 70%% set substrings" % rd.n,
+        "reads_per_s": rd.n / t_q, "k_mer_queries_per_s": windows / t_q, "ms": t_q * 1e3, "kmers": windows,
+        "tile": {k: tune[k] for k in ("mode", "chunk", "waves_per_cu")},
+        "wave_per_read": {"reads_per_s": rd.n / t_w, "ms": t_w * 1e3, "identical": same_w},
+        "plain_path": {"reads_per_s": pre / t_p, "prefix": pre, "identical": same_p},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +186,7 @@ def main():
     ap.add_argument("--queries", type=int, default=10_000_000)
     ap.add_argument("--plain-prefix", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reads", type=int, default=100_000, help="batched-read section size (0 = skip)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run one streaming copy of this size (memory-counter calibration)")
     args = ap.parse_args()
@@ -218,6 +268,8 @@ def main():
     g.close()
     del out, codes, dsets
     torch.cuda.empty_cache()
+    if args.reads > 0:
+        res["batched_reads"] = batched_reads(args.reads)
     if not args.no_cpu_baseline:
         t = time.time()
         res["cpu_baseline"] = cpu_baseline(sets, q, cfg)
