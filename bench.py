@@ -68,15 +68,59 @@ def time_steps(g, dsets, codes, out, steps: int, warmup: int):
     for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
+    g.stage_times()        # drop anything recorded so far
+    g.set_timing(True)     # per-kernel HIP events on the same stream, inside the library
     t0 = time.perf_counter()
     for s in range(steps):
         one_step(ev[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    g.set_timing(False)
+    kernels = {k: v / steps for k, v in g.stage_times().items()}
     clear = np.mean([e[0].elapsed_time(e[1]) for e in ev])
     ins = np.mean([e[1].elapsed_time(e[2]) for e in ev])
     qry = np.mean([e[2].elapsed_time(e[3]) for e in ev])
-    return wall, clear, ins, qry
+    return wall, clear, ins, qry, kernels
+
+
+# Integer work of the binning kernel's algorithm, in 32-bit VALU operations
+# (64-bit shift 1, 64-bit xor/add 2, 64x64 multiply 5): extracting one
+# canonical window from the packed streams, and per bit target the seed xor,
+# mix64 (two xorshift-multiply rounds and a final xorshift), the position
+# shift, the bit address and its bucket split.
+ALU_OPS_PER_WINDOW = 30
+ALU_OPS_PER_TARGET = 32
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock: 39.3 T int32 ops/s
+
+
+def kernel_rooflines(kernels, n_ins, n_queries, RE, S, W, index_bytes):
+    """Roofline entry of each timed kernel: algorithmic work per launch over
+    its measured duration."""
+    targets = n_ins * RE
+    work = {
+        "k_bin_windows": ("alu", n_ins * (ALU_OPS_PER_WINDOW + RE * ALU_OPS_PER_TARGET), "TFLOP/s",
+                          "int32 VALU ops: %d per window + %d per target" % (ALU_OPS_PER_WINDOW, ALU_OPS_PER_TARGET)),
+        "k_bin_regions": ("hbm", targets * 8, "GB/s", "4 B read + 4 B written per bit target"),
+        "k_apply_regions": ("hbm", targets * 4 + 2 * index_bytes, "GB/s",
+                            "4 B read per bit target + index read and written once"),
+        "k_insert_seqs": ("hbm", n_ins * RE * 2 * SECTOR, "GB/s", "one 64-B sector read-modify-write per target"),
+        "k_query_kmers": ("hbm", n_queries * (RE * max(SECTOR, S // 8) + 4 * W + 8), "GB/s",
+                          "R*eta row sectors + K-bit answer + code per query"),
+    }
+    out = []
+    for name, ms in kernels.items():
+        if name not in work:
+            continue
+        bound, amount, unit, what = work[name]
+        sec = ms / 1e3
+        if bound == "alu":
+            achieved, peak = amount / sec / 1e12, VALU_PEAK_TOPS
+        else:
+            achieved, peak = amount / sec / 1e9, HBM_PEAK_GBS
+        out.append({"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                    "frac": achieved / peak, "traffic": None, "ms": ms, "work_per_launch": amount, "work": what})
+    out.sort(key=lambda r: -r["ms"])
+    return out
 
 
 def plain_path(g, codes, out_batched, n_prefix: int):
@@ -212,7 +256,7 @@ def main():
     torch.cuda.synchronize()
     log("index: %.2f GiB, row %d bits, %d answer words" % (g.index_bytes / 2**30, g.row_bits, g.W))
 
-    wall, t_clear, t_ins, t_q = time_steps(g, dsets, codes, out, args.steps, args.warmup)
+    wall, t_clear, t_ins, t_q, kernels = time_steps(g, dsets, codes, out, args.steps, args.warmup)
     if g.sync_status() != 0:
         raise SystemExit("device error flag set")
     n_ins = int(np.sum(np.maximum(sets.lengths().astype(np.int64) - cfg["k"] + 1, 0)))
@@ -223,17 +267,10 @@ def main():
         % (ms_per_step, t_clear, t_ins, ins_per_s, t_q, q_per_s))
 
     R, eta, S, W = cfg["R"], cfg["eta"], g.row_bits, g.W
-    ins_bytes = R * eta * 2 * SECTOR                    # RMW of one sector per target
-    q_bytes = R * eta * max(SECTOR, S // 8) + 4 * W + 8  # row sectors + answer + code
-    roof_ins = {"kernel": "k_insert_seqs", "bound": "hbm", "achieved": ins_per_s * ins_bytes / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
-                "bytes_per_unit": ins_bytes, "units_per_launch": n_ins}
-    roof_q = {"kernel": "k_query_kmers", "bound": "hbm", "achieved": q_per_s * q_bytes / 1e9,
-              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
-              "bytes_per_unit": q_bytes, "units_per_launch": q.n}
-    for r in (roof_ins, roof_q):
-        r["frac"] = r["achieved"] / r["peak"]
-    dominant, other = (roof_ins, roof_q) if t_ins >= t_q else (roof_q, roof_ins)
+    roofs = kernel_rooflines(kernels, n_ins, q.n, R * eta, S, W, g.index_bytes)
+    for r in roofs:
+        log("  %-16s %8.3f ms  %-3s %.3g %s (%.1f%% of %.4g)" % (r["kernel"], r["ms"], r["bound"], r["achieved"],
+                                                               r["unit"], 100 * r["frac"], r["peak"]))
 
     if args.calib_copy_gib > 0:
         # a streaming copy of known size: the scale of the memory counters
@@ -261,7 +298,8 @@ def main():
                    "k": cfg["k"], "inserts": n_ins, "queries": q.n},
         "inserts_per_s": ins_per_s,
         "phase_ms": {"clear": t_clear, "insert": t_ins, "query": t_q},
-        "roofline": dominant, "roofline_other": other,
+        "kernel_ms": kernels,
+        "roofline": roofs[0], "roofline_other": roofs[1:],
         "plain_path": {"k_mer_queries_per_s": plain_rate, "prefix": args.plain_prefix,
                        "identical": plain_same, "speedup_batched": q_per_s / plain_rate},
     }

@@ -179,6 +179,17 @@ int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
 #define RAMBO_QUERY_QUEUE 2
 int rambo_set_query_policy(rambo_t *h, int mode, uint32_t chunk_bytes, uint32_t waves_per_cu);
 
+/* Kernel timing.  While enabled, every kernel the handle launches is
+ * bracketed by a pair of HIP events recorded on the caller's stream (do not
+ * enable it under graph capture).  rambo_get_stage_times synchronises those
+ * events and reports, for the kernels launched since the last call to it,
+ * the total milliseconds per kernel name: names receives up to max_stages
+ * NUL-terminated names of at most 47 characters in 48-byte slots, ms their
+ * times; the return value is the number of distinct kernels (or a negative
+ * error). */
+int rambo_set_timing(rambo_t *h, int enable);
+int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max_stages);
+
 /* Zero every Bloom filter (an empty index with the same hashes). */
 int rambo_clear(rambo_t *h, hipStream_t stream);
 

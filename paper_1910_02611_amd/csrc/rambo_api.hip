@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "insert_part.hpp"
 #include "query_queue.hpp"
@@ -44,7 +45,50 @@ struct rambo {
     void *rq_mem = nullptr;
     uint64_t rq_cap = 0;               // reads the queue state holds
     ReadQueue rq{};
+    // kernel timing (rambo_set_timing)
+    bool timing = false;
+    mutable std::vector<hipEvent_t> ev_pool;
+    mutable size_t ev_used = 0;
+    struct Stage {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    mutable std::vector<Stage> stages;
 };
+
+namespace {
+
+// Brackets one kernel launch with two events on its stream when timing is on.
+struct StageScope {
+    const rambo *h;
+    hipStream_t st;
+    hipEvent_t b = nullptr;
+    StageScope(const rambo *h_, const char *name, hipStream_t st_) : h(h_), st(st_)
+    {
+        if (!h->timing || h->stages.size() >= 100000)
+            return;
+        hipEvent_t ev[2];
+        for (hipEvent_t &e : ev) {
+            if (h->ev_used == h->ev_pool.size()) {
+                hipEvent_t n = nullptr;
+                if (hipEventCreate(&n) != hipSuccess)
+                    return;
+                h->ev_pool.push_back(n);
+            }
+            e = h->ev_pool[h->ev_used++];
+        }
+        (void)hipEventRecord(ev[0], st);
+        b = ev[1];
+        h->stages.push_back({name, ev[0], ev[1]});
+    }
+    ~StageScope()
+    {
+        if (b)
+            (void)hipEventRecord(b, st);
+    }
+};
+
+}  // namespace
 
 namespace {
 
@@ -89,6 +133,7 @@ void launch_query_kmers_t(const rambo *h, const uint64_t *codes, uint64_t n, uin
 {
     constexpr int G = SW > 4 ? SW / 4 : 1;
     constexpr uint64_t QPB = kBlock / G;
+    StageScope sc(h, "k_query_kmers", st);
     hipLaunchKernelGGL((k_query_kmers<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n, QPB)), dim3(kBlock), 0, st, h->P,
                        codes, n, out);
 }
@@ -97,6 +142,7 @@ template <int SW, int R_T, int ETA_T>
 void launch_query_seqs_t(const rambo *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
                          uint64_t n_chars, uint32_t *out, uint32_t *nk, hipStream_t st)
 {
+    StageScope sc(h, "k_query_seqs", st);
     hipLaunchKernelGGL((k_query_seqs<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_reads, kWavesPerBlock)),
                        dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk);
 }
@@ -178,6 +224,7 @@ struct QuerySeqsQueueLaunch {
     template <int SW, int R_T, int ETA_T>
     void operator()() const
     {
+        StageScope sc(h, "k_rq_persist", st);
         hipLaunchKernelGGL((k_rq_persist<SW, R_T, ETA_T>), dim3(grid), dim3(kBlock), 0, st, h->P, h->rq, offsets,
                            n_reads, chars, n_chars, h->query_chunk, out, nk);
     }
@@ -392,13 +439,17 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
     const size_t ldsA = lds_bytes_stage_a(G.na), ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     for (uint64_t p = 0; p < n_chars; p += batch_windows) {
         const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
+        { StageScope sc(h, "k_zero_u32", stream);
         hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
-                           (uint64_t)G.na + (uint64_t)G.na * G.nf);
+                           (uint64_t)G.na + (uint64_t)G.na * G.nf); }
         const BinWindowsFn binA = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
+        { StageScope sc(h, "k_bin_windows", stream);
         hipLaunchKernelGGL(binA, dim3((uint32_t)div_up(pe - p, block_windows)), dim3(kBlockP), ldsA, stream, h->P, G,
-                           set_ids, offsets, n_seqs, chars, n_chars, p, pe, steps, rounds);
-        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb);
-        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G);
+                           set_ids, offsets, n_seqs, chars, n_chars, p, pe, steps, rounds); }
+        { StageScope sc(h, "k_bin_regions", stream);
+        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
+        { StageScope sc(h, "k_apply_regions", stream);
+        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G); }
         if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
             return rc;
     }
@@ -523,7 +574,49 @@ extern "C" void rambo_destroy(rambo_t *h)
         (void)hipFree(h->bin_mem);
     if (h->rq_mem)
         (void)hipFree(h->rq_mem);
+    for (hipEvent_t e : h->ev_pool)
+        (void)hipEventDestroy(e);
     delete h;
+}
+
+extern "C" int rambo_set_timing(rambo_t *h, int enable)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    h->timing = enable != 0;
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max_stages)
+{
+    if (!h || max_stages < 0 || (max_stages > 0 && (!names || !ms)))
+        return RAMBO_EINVAL;
+    constexpr int kSlot = 48;
+    std::vector<std::pair<std::string, float>> acc;
+    int rc = RAMBO_OK;
+    for (const auto &s : h->stages) {
+        float t = 0.f;
+        if (rc == RAMBO_OK && (rc = hip_check(h, hipEventSynchronize(s.b), "rambo_get_stage_times")) == RAMBO_OK)
+            rc = hip_check(h, hipEventElapsedTime(&t, s.a, s.b), "rambo_get_stage_times");
+        if (rc)
+            break;
+        auto it = std::find_if(acc.begin(), acc.end(), [&](const auto &e) { return e.first == s.name; });
+        if (it == acc.end())
+            acc.emplace_back(s.name, t);
+        else
+            it->second += t;
+    }
+    h->stages.clear();
+    h->ev_used = 0;
+    if (rc)
+        return rc;
+    const int n = (int)acc.size() < max_stages ? (int)acc.size() : max_stages;
+    for (int i = 0; i < n; ++i) {
+        std::memset(names + (size_t)i * kSlot, 0, kSlot);
+        std::strncpy(names + (size_t)i * kSlot, acc[i].first.c_str(), kSlot - 1);
+        ms[i] = acc[i].second;
+    }
+    return (int)acc.size();
 }
 
 extern "C" int rambo_set_query_policy(rambo_t *h, int mode, uint32_t chunk_bytes, uint32_t waves_per_cu)
@@ -562,6 +655,7 @@ extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uin
         return RAMBO_OK;
     if (!set_ids || !offsets || !codes)
         return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
+    StageScope sc(h, "k_insert_kmers", stream);
     hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,
                        set_ids, offsets, n_sets, codes, n_codes);
     return launch_check(h, "rambo_insert_kmers");
@@ -580,6 +674,7 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
         return insert_seqs_partitioned(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
     const uint64_t waves = div_up(n_chars, kChunk);
     const InsertSeqsFn ins = pick_shape<InsertSeqsFn, InsertSeqsK>(h->cfg.R, h->cfg.eta);
+    StageScope sc(h, "k_insert_seqs", stream);
     hipLaunchKernelGGL(ins, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P, set_ids,
                        offsets, n_seqs, chars, n_chars, kChunk);
     return launch_check(h, "rambo_insert_seqs");
@@ -615,9 +710,11 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
     if (rc)
         return rc;
     const uint32_t rsw = h->cfg.R * h->SW;
+    { StageScope sc(h, "k_rq_setup", stream);
     hipLaunchKernelGGL(k_rq_setup, dim3((uint32_t)div_up(n_reads, kBlock)), dim3(kBlock), 0, stream, h->rq, offsets,
-                       n_reads, n_chars, h->query_chunk, rsw);
-    hipLaunchKernelGGL(k_rq_scan, dim3(1), dim3(1024), 0, stream, h->rq.items, n_reads);
+                       n_reads, n_chars, h->query_chunk, rsw); }
+    { StageScope sc(h, "k_rq_scan", stream);
+    hipLaunchKernelGGL(k_rq_scan, dim3(1), dim3(1024), 0, stream, h->rq.items, n_reads); }
     const uint64_t max_items = n_chars / h->query_chunk + n_reads + 1;
     const uint64_t waves = std::min<uint64_t>(max_items, (uint64_t)h->num_cus * h->query_waves_per_cu);
     const uint32_t grid = (uint32_t)div_up(waves, kWavesPerBlock);
@@ -637,6 +734,7 @@ extern "C" int rambo_extract_kmers(rambo_t *h, const uint64_t *offsets, uint64_t
     if (n_seqs == 0)
         return hip_check(h, hipMemsetAsync(out_codes, 0xFF, n_chars * 8, stream), "rambo_extract_kmers");
     const uint64_t waves = div_up(n_chars, kChunk);
+    StageScope sc(h, "k_extract", stream);
     hipLaunchKernelGGL(k_extract, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->cfg.k,
                        h->P.kmask, offsets, n_seqs, chars, n_chars, kChunk, out_codes);
     return launch_check(h, "rambo_extract_kmers");

@@ -72,6 +72,8 @@ EXPORTS = {
                                               ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_set_insert_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]),
     "rambo_set_query_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
+    "rambo_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "rambo_get_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rambo_copy_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
@@ -227,6 +229,19 @@ class Rambo:
         """QUERY_AUTO / QUERY_WAVE_PER_READ / QUERY_QUEUE; same answers."""
         self._check(lib().rambo_set_query_policy(self._h, mode, chunk_bytes, waves_per_cu),
                     "rambo_set_query_policy")
+
+    def set_timing(self, enable: bool = True):
+        self._check(lib().rambo_set_timing(self._h, int(enable)), "rambo_set_timing")
+
+    def stage_times(self, max_stages: int = 32) -> dict:
+        """Milliseconds per kernel name since the last call (HIP events)."""
+        names = ctypes.create_string_buffer(48 * max_stages)
+        ms = (ctypes.c_float * max_stages)()
+        n = lib().rambo_get_stage_times(self._h, names, ms, max_stages)
+        if n < 0:
+            self._check(n, "rambo_get_stage_times")
+        raw = names.raw
+        return {raw[48 * i:48 * (i + 1)].split(b"\0")[0].decode(): float(ms[i]) for i in range(min(n, max_stages))}
 
     def clear(self, stream=None):
         self._check(lib().rambo_clear(self._h, _stream(stream)), "rambo_clear")
