@@ -222,6 +222,37 @@ def batched_reads(n_reads: int, plain_prefix: int = 2000):
     }
 
 
+def serving(g, sets, n_requests: int, loads, slots: int = 4):
+    """The query server on the resident index: requests of U{1..64} reads,
+    lengths log-uniform in [150, 5000] bp, 70% set substrings; saturated rate
+    (all requests queued at once), then Poisson arrivals at fractions of it.
+    Latency = arrival -> answer in host memory."""
+    from paper_1910_02611_amd import serve, synth
+    from paper_1910_02611_amd.rambo import Server
+
+    t = time.time()
+    reqs = serve.split_requests(synth.served_requests(4004, sets, n_requests))
+    log("serving: %d requests, %d reads (%.1f s)" % (len(reqs), sum(len(o) - 1 for o, _ in reqs), time.time() - t))
+    with Server(g, max_slots=slots, use_graphs=True) as srv:
+        serve.saturated(srv, reqs[: min(200, len(reqs))], g.W)   # warm-up
+        res = serve.sweep(srv, reqs, g.W, loads)
+        res["server"] = srv.stats()
+    sat = res["saturated"]
+    log("serving: saturated %.4g requests/s (%.4g reads/s), p50 %.3f ms p99 %.3f ms"
+        % (sat["qps"], sat["reads_per_s"], sat["p50_ms"], sat["p99_ms"]))
+    for p in res["points"]:
+        log("  load %.2f: offered %.4g/s achieved %.4g/s  p50 %.3f ms  p99 %.3f ms"
+            % (p["load"], p["offered_qps"], p["qps"], p["p50_ms"], p["p99_ms"]))
+    keep = ("load", "offered_qps", "qps", "reads_per_s", "p50_ms", "p99_ms", "mean_ms", "max_submit_lag_ms")
+    return {
+        "workload": "served requests on the resident index: U{1..64} reads of log-uniform 150-5000 bp, "
+                    "70%% set substrings; %d requests per point, %d slots, graph replay" % (len(reqs), slots),
+        "saturated": {k: sat[k] for k in ("qps", "reads_per_s", "p50_ms", "p99_ms")},
+        "points": [{k: p[k] for k in keep} for p in res["points"]],
+        "server": res["server"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +262,8 @@ def main():
     ap.add_argument("--plain-prefix", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reads", type=int, default=100_000, help="batched-read section size (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=3000, help="requests per serving load point (0 = skip)")
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.8,1.0")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run one streaming copy of this size (memory-counter calibration)")
     args = ap.parse_args()
@@ -303,6 +336,11 @@ def main():
         "plain_path": {"k_mer_queries_per_s": plain_rate, "prefix": args.plain_prefix,
                        "identical": plain_same, "speedup_batched": q_per_s / plain_rate},
     }
+    if args.serve_requests > 0:
+        res["serving"] = serving(g, sets, args.serve_requests, [float(x) for x in args.serve_loads.split(",")])
+        half = min(res["serving"]["points"], key=lambda p: abs(p["load"] - 0.5))
+        res["latency"] = {"p50_ms": half["p50_ms"], "p99_ms": half["p99_ms"], "load": half["load"],
+                          "requests_per_s": half["qps"]}
     g.close()
     del out, codes, dsets
     torch.cuda.empty_cache()

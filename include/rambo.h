@@ -135,6 +135,20 @@ int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
                      const uint8_t *chars, uint64_t n_chars, uint32_t *out_masks,
                      uint32_t *out_nkmers, hipStream_t stream);
 
+/* The answers of rambo_query_seqs as ascending set-ID lists (Sec. 3.2.1; the
+ * compacted form of the K-bit mask, for large K where most answers are
+ * short).  id_offsets (n_reads+1 uint64) receives the list boundaries: read
+ * q's IDs are ids[id_offsets[q] .. id_offsets[q+1]), and id_offsets[n_reads]
+ * is the total needed.  ids holds cap uint32 entries (may be NULL when cap is
+ * 0).  id_offsets is always written in full; a read whose list would end
+ * beyond cap gets no IDs written, and the call then raises the sticky
+ * RAMBO_EOVERFLOW status (reported by rambo_sync_status), after which the
+ * caller may call again with cap >= id_offsets[n_reads].  out_nkmers as in
+ * rambo_query_seqs.  Uses the same per-read state as the work-queue form. */
+int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
+                         const uint8_t *chars, uint64_t n_chars, uint64_t *id_offsets,
+                         uint32_t *ids, uint64_t cap, uint32_t *out_nkmers, hipStream_t stream);
+
 /* ---- support ---------------------------------------------------------- */
 
 /* Canonical code of the k-window starting at every byte (the term
@@ -205,8 +219,15 @@ int rambo_copy_index(rambo_t *h, uint64_t word_offset, uint64_t n_words, void *d
  * Synchronous. */
 int rambo_get_partition(rambo_t *h, uint32_t *out);
 
+/* Number of set bits of every Bloom filter: out[r*B + b] (R*B uint64,
+ * device memory) = ones of cell b of repetition r, the n_b of the filter's
+ * fill (Sec. 2.1), as the false-positive expression of Lemma 4.1 uses it.
+ * Asynchronous on `stream`. */
+int rambo_fill_counts(rambo_t *h, uint64_t *out, hipStream_t stream);
+
 /* Synchronise `stream`, then return and clear the sticky device error:
- * RAMBO_OK, RAMBO_ERANGE or RAMBO_ECODE (the first one seen). */
+ * RAMBO_OK, RAMBO_ERANGE, RAMBO_ECODE or RAMBO_EOVERFLOW (in that order of
+ * precedence when several were raised). */
 int rambo_sync_status(rambo_t *h, hipStream_t stream);
 
 /* Text of the last error of the handle (or of the last failed create when

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librambo.so")
 SOURCES = ["rambo_api.hip", "roofline.hip"]
-HEADERS = ["device.hpp", "kernels.hpp", "insert_part.hpp", "query_queue.hpp"]
+HEADERS = ["device.hpp", "kernels.hpp", "insert_part.hpp", "query_queue.hpp", "query_ids.hpp", "serve.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++20", "-fPIC", "-shared", "-Wall",
@@ -20,7 +20,7 @@ HIPCC_FLAGS = [
 
 def sources():
     return [os.path.join(CSRC, s) for s in SOURCES] + [os.path.join(CSRC, h) for h in HEADERS] + \
-        [os.path.join(ROOT, "include", h) for h in ("rambo.h", "rambo_roofline.h")]
+        [os.path.join(ROOT, "include", h) for h in ("rambo.h", "rambo_roofline.h", "rambo_serve.h")]
 
 
 def build(verbose: bool = False) -> str:

@@ -1,0 +1,220 @@
+// Answers of sequence queries as ascending set-ID lists, and per-cell fill
+// counts of the index.
+//
+// The ID form compacts the K-bit answer of Sec. 3.2.1 (Alg. 2's A).  It
+// starts from the per-read group masks that the work-queue launch leaves in
+// its state (run without the mask expansion), then
+//   k_ids_count : wave per read, |A| = sum of popcounts of the expanded words;
+//   k_scan64_*  : exclusive scan of the counts into id_offsets (n+1 entries);
+//   k_ids_write : wave per read, expands again and writes the set bits of
+//                 each word, in word order, at its wave-prefix position.
+// A read whose list would end beyond the caller's capacity is not written and
+// the sticky overflow bit is raised; id_offsets is always complete.
+//
+// k_fill_counts counts the set bits of each cell (r, b): the n_b of the
+// fill 1 - (1 - 1/m)^(eta n) of Sec. 2.1, per BFU.
+#pragma once
+
+#include "query_queue.hpp"
+
+namespace rambo_dev {
+
+constexpr int kErrOverflow = 4;
+constexpr uint32_t kScanTile = 1024;   // elements per block of the u64 scan (256 threads x 4)
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    for (int d = 32; d >= 1; d >>= 1)
+        v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t lane)
+{
+    uint32_t x = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= (uint32_t)d)
+            x += y;
+    }
+    return x - v;
+}
+
+// Loads read q's final group masks (R x SW words) into the wave's LDS G and
+// tells whether its answer is empty (no valid window, or some repetition
+// without a positive cell).
+__device__ __forceinline__ bool load_read_masks(const Params &P, const ReadQueue &Q, uint64_t q, uint32_t SW,
+                                                uint32_t *G, uint32_t lane)
+{
+    const uint32_t rsw = P.R * SW;
+    for (uint32_t i = lane; i < rsw; i += kWave)
+        G[i] = Q.G[q * rsw + i];
+    wave_sync_lds();
+    return Q.nk[q] == 0 || any_rep_empty(G, P.R, SW);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
+                                                      uint64_t *counts)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t lane = lane_id();
+    uint32_t *G = lds + (threadIdx.x / kWave) * (P.R * SW);
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; q < n_reads; q += stride) {
+        const bool empty = load_read_masks(P, Q, q, SW, G, lane);
+        uint32_t c = 0;
+        if (!empty)
+            for (uint32_t w = lane; w < P.W; w += kWave)
+                c += __builtin_popcount(expand_word(P, G, SW, w));
+        c = wave_sum_u32(c);
+        if (lane == 0)
+            counts[q] = c;
+        wave_sync_lds();
+    }
+}
+
+// Tile-local exclusive scan of x[0..n) into y; tile totals into part.
+__global__ __launch_bounds__(256) void k_scan64_tiles(const uint64_t *x, uint64_t n, uint64_t *y, uint64_t *part)
+{
+    __shared__ uint64_t s[256];
+    const uint32_t t = threadIdx.x;
+    const uint64_t i0 = (uint64_t)blockIdx.x * kScanTile + 4 * t;
+    uint64_t v[4], sum = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = i0 + j < n ? x[i0 + j] : 0;
+        sum += v[j];
+    }
+    s[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        const uint64_t a = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += a;
+        __syncthreads();
+    }
+    uint64_t run = s[t] - sum;
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j < n)
+            y[i0 + j] = run;
+        run += v[j];
+    }
+    if (t == 255)
+        part[blockIdx.x] = s[255];
+}
+
+// One workgroup: exclusive scan of the tile totals in place; y[n] = total;
+// overflow bit when the total exceeds cap.
+__global__ __launch_bounds__(1024) void k_scan64_part(uint64_t *part, uint64_t nb, uint64_t *y, uint64_t n,
+                                                      uint64_t cap, int *err)
+{
+    __shared__ uint64_t s[1024];
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (nb + 1023) / 1024;
+    const uint64_t b0 = min((uint64_t)t * per, nb), b1 = min(b0 + per, nb);
+    uint64_t sum = 0;
+    for (uint64_t i = b0; i < b1; ++i)
+        sum += part[i];
+    s[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint64_t a = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += a;
+        __syncthreads();
+    }
+    uint64_t run = s[t] - sum;
+    for (uint64_t i = b0; i < b1; ++i) {
+        const uint64_t c = part[i];
+        part[i] = run;
+        run += c;
+    }
+    if (t == 1023) {
+        y[n] = s[1023];
+        if (s[1023] > cap)
+            atomicOr(err, kErrOverflow);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan64_add(uint64_t *y, uint64_t n, const uint64_t *part)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        y[i] += part[i / kScanTile];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
+                                                      const uint64_t *id_offsets, uint32_t *ids, uint64_t cap)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t lane = lane_id();
+    uint32_t *G = lds + (threadIdx.x / kWave) * (P.R * SW);
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; q < n_reads; q += stride) {
+        const uint64_t o0 = id_offsets[q], o1 = id_offsets[q + 1];
+        if (o0 == o1 || o1 > cap)
+            continue;
+        load_read_masks(P, Q, q, SW, G, lane);
+        uint64_t base = o0;
+        for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
+            const uint32_t w = w0 + lane;
+            uint32_t word = w < P.W ? expand_word(P, G, SW, w) : 0u;
+            const uint32_t c = __builtin_popcount(word);
+            uint64_t pos = base + wave_excl_scan_u32(c, lane);
+            while (word) {
+                const uint32_t b = (uint32_t)__builtin_ctz(word);
+                word &= word - 1;
+                if (pos < o1)
+                    ids[pos] = w * 32 + b;
+                ++pos;
+            }
+            base += wave_sum_u32(c);
+        }
+        wave_sync_lds();
+    }
+}
+
+// Per-cell set-bit counts, out[r * B + b] += ones of column b in repetition
+// r.  Block (x, r) takes kFillTile consecutive words of repetition r; each
+// thread keeps an 8-plane vertical counter for the 32 bit positions of its
+// words (all with the same position inside a row), so a word costs a few
+// bitwise operations, and folds it into an LDS column histogram at the end.
+constexpr uint32_t kFillWordsPerThread = 255;
+constexpr uint64_t kFillTile = (uint64_t)kBlock * kFillWordsPerThread;
+
+__global__ __launch_bounds__(kBlock) void k_fill_counts(const uint32_t *index, uint64_t words_per_rep, uint32_t S,
+                                                        uint32_t B, unsigned long long *out)
+{
+    extern __shared__ uint32_t hist[];   // S counters
+    const uint32_t r = blockIdx.y;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t c = t; c < S; c += kBlock)
+        hist[c] = 0;
+    const uint32_t *rep = index + (uint64_t)r * words_per_rep;
+    const uint64_t w0 = (uint64_t)blockIdx.x * kFillTile + t;
+    uint32_t plane[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t i = 0; i < kFillWordsPerThread; ++i) {
+        const uint64_t w = w0 + (uint64_t)i * kBlock;
+        uint32_t carry = w < words_per_rep ? rep[w] : 0u;
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t nc = plane[k] & carry;
+            plane[k] ^= carry;
+            carry = nc;
+        }
+    }
+    __syncthreads();
+    // every word of this thread starts at bit (w0 * 32) mod S of its row
+    const uint32_t col0 = (uint32_t)((w0 * 32) & (S - 1));
+    for (uint32_t j = 0; j < 32; ++j) {
+        uint32_t c = 0;
+        for (int k = 0; k < 8; ++k)
+            c |= ((plane[k] >> j) & 1u) << k;
+        if (c)
+            atomicAdd(&hist[(col0 + j) & (S - 1)], c);
+    }
+    __syncthreads();
+    for (uint32_t c = t; c < B; c += kBlock)
+        if (hist[c])
+            atomicAdd(out + (uint64_t)r * B + c, (unsigned long long)hist[c]);
+}
+
+}  // namespace rambo_dev

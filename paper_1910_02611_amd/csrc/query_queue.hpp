@@ -12,7 +12,9 @@
 //                 result into the read's state with atomics and raises the
 //                 read's flag once some repetition is empty, so later chunks
 //                 of that read only count windows.  The wave that finishes a
-//                 read's last chunk expands it and writes the answer.
+//                 read's last chunk expands it and writes the answer (unless
+//                 no mask output is given: then the final group masks stay in
+//                 the state for the ID-list kernels).
 #pragma once
 
 #include "kernels.hpp"
@@ -37,9 +39,18 @@ __device__ __forceinline__ void read_span(const uint64_t *offsets, uint64_t q, u
         p0 = pe;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rq_setup(ReadQueue Q, const uint64_t *offsets, uint64_t n_reads,
-                                                     uint64_t n_chars, uint32_t chunk, uint32_t rsw)
+// The number of reads of a batch: n_host, or *n_dev when given (a captured
+// graph replays the same launches for batches of any size up to its grid).
+__device__ __forceinline__ uint64_t batch_reads(uint64_t n_host, const uint64_t *n_dev)
 {
+    return n_dev ? *n_dev : n_host;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rq_setup(ReadQueue Q, const uint64_t *offsets, uint64_t n_host,
+                                                     const uint64_t *n_dev, uint64_t n_chars, uint32_t chunk,
+                                                     uint32_t rsw)
+{
+    const uint64_t n_reads = batch_reads(n_host, n_dev);
     const uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q == 0)
         *Q.counter = 0;
@@ -58,9 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_rq_setup(ReadQueue Q, const uint64_t
 }
 
 // Exclusive scan of items[0..n) in place, items[n] = total; one workgroup.
-__global__ __launch_bounds__(1024) void k_rq_scan(uint32_t *items, uint64_t n)
+__global__ __launch_bounds__(1024) void k_rq_scan(uint32_t *items, uint64_t n_host, const uint64_t *n_dev)
 {
     __shared__ uint32_t part[1024];
+    const uint64_t n = batch_reads(n_host, n_dev);
     const uint32_t t = threadIdx.x;
     const uint64_t per = (n + 1023) / 1024;
     const uint64_t b0 = min((uint64_t)t * per, n), b1 = min(b0 + per, n);
@@ -101,9 +113,11 @@ __device__ __forceinline__ uint64_t read_of_item(const uint32_t *items, uint64_t
 
 template <int SW, int R_T, int ETA_T>
 __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, const uint64_t *offsets,
-                                                       uint64_t n_reads, const uint8_t *chars, uint64_t n_chars,
-                                                       uint32_t chunk, uint32_t *out, uint32_t *out_nk)
+                                                       uint64_t n_host, const uint64_t *n_dev, const uint8_t *chars,
+                                                       uint64_t n_chars, uint32_t chunk, uint32_t *out,
+                                                       uint32_t *out_nk)
 {
+    const uint64_t n_reads = batch_reads(n_host, n_dev);
     constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
     __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
     const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
@@ -153,12 +167,14 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
             continue;
         // last chunk of read q: every other chunk's AND happened before its
         // release-decrement, which our acquire-decrement follows
-        for (uint32_t i = lane; i < rsw; i += kWave)
-            G[i] = __hip_atomic_load(Q.G + q * rsw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t nk_all = __hip_atomic_load(Q.nk + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wave_sync_lds();
         if (out_nk && lane == 0)
             out_nk[q] = nk_all;
+        if (!out)
+            continue;   // the answer stays in the state (ID-list form)
+        for (uint32_t i = lane; i < rsw; i += kWave)
+            G[i] = __hip_atomic_load(Q.G + q * rsw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wave_sync_lds();
         const bool empty = nk_all == 0 || any_rep_empty(G, R, SW);
         uint32_t *o = out + q * P.W;
         for (uint32_t w = lane; w < P.W; w += kWave)

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "insert_part.hpp"
+#include "query_ids.hpp"
 #include "query_queue.hpp"
 #include "kernels.hpp"
 #include "rambo.h"
@@ -45,6 +46,7 @@ struct rambo {
     void *rq_mem = nullptr;
     uint64_t rq_cap = 0;               // reads the queue state holds
     ReadQueue rq{};
+    uint64_t *scan_part = nullptr;     // tile totals of the ID-list scan (in rq_mem)
     // kernel timing (rambo_set_timing)
     bool timing = false;
     mutable std::vector<hipEvent_t> ev_pool;
@@ -213,8 +215,10 @@ struct QuerySeqsLaunch {
 // already set up by k_rq_setup and k_rq_scan.
 struct QuerySeqsQueueLaunch {
     const rambo *h;
+    const ReadQueue &rq;
     const uint64_t *offsets;
     uint64_t n_reads;
+    const uint64_t *n_dev;
     const uint8_t *chars;
     uint64_t n_chars;
     uint32_t *out;
@@ -225,8 +229,8 @@ struct QuerySeqsQueueLaunch {
     void operator()() const
     {
         StageScope sc(h, "k_rq_persist", st);
-        hipLaunchKernelGGL((k_rq_persist<SW, R_T, ETA_T>), dim3(grid), dim3(kBlock), 0, st, h->P, h->rq, offsets,
-                           n_reads, chars, n_chars, h->query_chunk, out, nk);
+        hipLaunchKernelGGL((k_rq_persist<SW, R_T, ETA_T>), dim3(grid), dim3(kBlock), 0, st, h->P, rq, offsets,
+                           n_reads, n_dev, chars, n_chars, h->query_chunk, out, nk);
     }
 };
 
@@ -280,6 +284,32 @@ struct BinWindowsK {
 // ------------------------------------------------ batched read queries
 
 // Per-read state of the work-queue launch, grown to hold n_reads reads.
+uint64_t read_queue_bytes(const rambo *h, uint64_t cap)
+{
+    const uint64_t rsw = (uint64_t)h->cfg.R * h->SW;
+    return 4 * (cap * (rsw + 4) + (cap + 1) + 1);
+}
+
+// Lay out the per-read state of cap reads in mem (read_queue_bytes(h, cap)).
+ReadQueue carve_read_queue(const rambo *h, void *mem, uint64_t cap)
+{
+    const uint64_t rsw = (uint64_t)h->cfg.R * h->SW;
+    ReadQueue q{};
+    uint32_t *p = static_cast<uint32_t *>(mem);
+    q.G = p;
+    p += cap * rsw;
+    q.nk = p;
+    p += cap;
+    q.dead = p;
+    p += cap;
+    q.remaining = p;
+    p += cap;
+    q.items = p;
+    p += cap + 1;
+    q.counter = p;
+    return q;
+}
+
 int ensure_read_queue(rambo *h, uint64_t n_reads)
 {
     if (n_reads <= h->rq_cap && h->rq_mem)
@@ -287,8 +317,6 @@ int ensure_read_queue(rambo *h, uint64_t n_reads)
     uint64_t cap = h->rq_cap ? h->rq_cap : 1024;
     while (cap < n_reads)
         cap *= 2;
-    const uint64_t rsw = (uint64_t)h->cfg.R * h->SW;
-    const uint64_t words = cap * (rsw + 4) + (cap + 1) + 1;
     if (h->rq_mem) {
         const int rc = hip_check(h, hipDeviceSynchronize(), "read queue resize");
         if (rc)
@@ -297,25 +325,39 @@ int ensure_read_queue(rambo *h, uint64_t n_reads)
         h->rq_mem = nullptr;
         h->rq_cap = 0;
     }
-    if (hipMalloc(&h->rq_mem, words * 4) != hipSuccess) {
+    const uint64_t qb = div_up(read_queue_bytes(h, cap), 256) * 256;
+    if (hipMalloc(&h->rq_mem, qb + 8 * (div_up(cap, kScanTile) + 1)) != hipSuccess) {
         (void)hipGetLastError();
         h->rq_mem = nullptr;
         return fail(h, RAMBO_ENOMEM, "read queue allocation failed");
     }
-    uint32_t *p = static_cast<uint32_t *>(h->rq_mem);
-    h->rq.G = p;
-    p += cap * rsw;
-    h->rq.nk = p;
-    p += cap;
-    h->rq.dead = p;
-    p += cap;
-    h->rq.remaining = p;
-    p += cap;
-    h->rq.items = p;
-    p += cap + 1;
-    h->rq.counter = p;
+    h->rq = carve_read_queue(h, h->rq_mem, cap);
+    h->scan_part = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(h->rq_mem) + qb);
     h->rq_cap = cap;
     return RAMBO_OK;
+}
+
+// The three launches of the work-queue read query.  The batch has n_host
+// reads, or *n_dev reads (at most cap_reads) when n_dev is given; n_chars
+// bounds the byte buffer.
+void launch_read_queue(rambo *h, const ReadQueue &rq, const uint64_t *offsets, uint64_t n_host,
+                       const uint64_t *n_dev, uint64_t cap_reads, const uint8_t *chars, uint64_t n_chars,
+                       uint32_t *out, uint32_t *nk, hipStream_t stream)
+{
+    const uint32_t rsw = h->cfg.R * h->SW;
+    {
+        StageScope sc(h, "k_rq_setup", stream);
+        hipLaunchKernelGGL(k_rq_setup, dim3((uint32_t)div_up(cap_reads, kBlock)), dim3(kBlock), 0, stream, rq, offsets,
+                           n_host, n_dev, n_chars, h->query_chunk, rsw);
+    }
+    {
+        StageScope sc(h, "k_rq_scan", stream);
+        hipLaunchKernelGGL(k_rq_scan, dim3(1), dim3(1024), 0, stream, rq.items, n_host, n_dev);
+    }
+    const uint64_t max_items = n_chars / h->query_chunk + cap_reads + 1;
+    const uint64_t waves = std::min<uint64_t>(max_items, (uint64_t)h->num_cus * h->query_waves_per_cu);
+    const uint32_t grid = (uint32_t)div_up(waves, kWavesPerBlock);
+    with_row_words(h, QuerySeqsQueueLaunch{h, rq, offsets, n_host, n_dev, chars, n_chars, out, nk, stream, grid});
 }
 
 // ------------------------------------------------- partitioned insertion
@@ -709,17 +751,64 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
     int rc = ensure_read_queue(h, n_reads);
     if (rc)
         return rc;
-    const uint32_t rsw = h->cfg.R * h->SW;
-    { StageScope sc(h, "k_rq_setup", stream);
-    hipLaunchKernelGGL(k_rq_setup, dim3((uint32_t)div_up(n_reads, kBlock)), dim3(kBlock), 0, stream, h->rq, offsets,
-                       n_reads, n_chars, h->query_chunk, rsw); }
-    { StageScope sc(h, "k_rq_scan", stream);
-    hipLaunchKernelGGL(k_rq_scan, dim3(1), dim3(1024), 0, stream, h->rq.items, n_reads); }
-    const uint64_t max_items = n_chars / h->query_chunk + n_reads + 1;
-    const uint64_t waves = std::min<uint64_t>(max_items, (uint64_t)h->num_cus * h->query_waves_per_cu);
-    const uint32_t grid = (uint32_t)div_up(waves, kWavesPerBlock);
-    with_row_words(h, QuerySeqsQueueLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream, grid});
+    launch_read_queue(h, h->rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, out_masks, out_nkmers, stream);
     return launch_check(h, "rambo_query_seqs");
+}
+
+extern "C" int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
+                                    uint64_t n_chars, uint64_t *id_offsets, uint32_t *ids, uint64_t cap,
+                                    uint32_t *out_nkmers, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (!id_offsets || (n_reads > 0 && !offsets) || (n_chars > 0 && !chars) || (cap > 0 && !ids))
+        return fail(h, RAMBO_EINVAL, "rambo_query_seqs_ids: NULL array");
+    if (n_reads == 0)
+        return hip_check(h, hipMemsetAsync(id_offsets, 0, 8, stream), "rambo_query_seqs_ids");
+    int rc = ensure_read_queue(h, n_reads);
+    if (rc)
+        return rc;
+    // group masks and window counts only: the answers stay in the queue state
+    launch_read_queue(h, h->rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, nullptr, out_nkmers, stream);
+    const uint64_t waves = std::min<uint64_t>(n_reads, (uint64_t)h->num_cus * 16);
+    const dim3 grid((uint32_t)div_up(waves, kWavesPerBlock));
+    const size_t lds = (size_t)kWavesPerBlock * h->cfg.R * h->SW * 4;
+    {
+        StageScope sc(h, "k_ids_count", stream);
+        hipLaunchKernelGGL(k_ids_count, grid, dim3(kBlock), lds, stream, h->P, h->rq, n_reads, h->SW, id_offsets);
+    }
+    const uint64_t nb = div_up(n_reads, kScanTile);
+    {
+        StageScope sc(h, "k_scan64", stream);
+        hipLaunchKernelGGL(k_scan64_tiles, dim3((uint32_t)nb), dim3(256), 0, stream, id_offsets, n_reads, id_offsets,
+                           h->scan_part);
+        hipLaunchKernelGGL(k_scan64_part, dim3(1), dim3(1024), 0, stream, h->scan_part, nb, id_offsets, n_reads, cap,
+                           h->err);
+        hipLaunchKernelGGL(k_scan64_add, dim3((uint32_t)div_up(n_reads, 256)), dim3(256), 0, stream, id_offsets,
+                           n_reads, h->scan_part);
+    }
+    {
+        StageScope sc(h, "k_ids_write", stream);
+        hipLaunchKernelGGL(k_ids_write, grid, dim3(kBlock), lds, stream, h->P, h->rq, n_reads, h->SW, id_offsets, ids,
+                           cap);
+    }
+    return launch_check(h, "rambo_query_seqs_ids");
+}
+
+extern "C" int rambo_fill_counts(rambo_t *h, uint64_t *out, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (!out)
+        return fail(h, RAMBO_EINVAL, "rambo_fill_counts: NULL array");
+    const uint64_t n = (uint64_t)h->cfg.R * h->cfg.B;
+    hipLaunchKernelGGL(k_zero_u32, dim3((uint32_t)div_up(2 * n, kBlock)), dim3(kBlock), 0, stream,
+                       reinterpret_cast<uint32_t *>(out), 2 * n);
+    StageScope sc(h, "k_fill_counts", stream);
+    hipLaunchKernelGGL(k_fill_counts, dim3((uint32_t)div_up(h->words_per_rep, kFillTile), h->cfg.R), dim3(kBlock),
+                       (size_t)h->S * 4, stream, h->index, h->words_per_rep, h->S, h->cfg.B,
+                       reinterpret_cast<unsigned long long *>(out));
+    return launch_check(h, "rambo_fill_counts");
 }
 
 extern "C" int rambo_extract_kmers(rambo_t *h, const uint64_t *offsets, uint64_t n_seqs, const uint8_t *chars,
@@ -834,6 +923,8 @@ extern "C" int rambo_sync_status(rambo_t *h, hipStream_t stream)
         return fail(h, RAMBO_ERANGE, "a set id >= K was seen on the device");
     if (e & kErrCode)
         return fail(h, RAMBO_ECODE, "a k-mer code >= 4^k was seen on the device");
+    if (e & kErrOverflow)
+        return fail(h, RAMBO_EOVERFLOW, "an answer list did not fit the capacity given");
     return RAMBO_OK;
 }
 
@@ -841,3 +932,5 @@ extern "C" const char *rambo_last_error(const rambo_t *h)
 {
     return h ? h->last_error.c_str() : g_create_error.c_str();
 }
+
+#include "serve.hpp"

@@ -1,0 +1,390 @@
+// Continuous-batching query server (include/rambo_serve.h).  Included at the
+// end of rambo_api.hip: it uses the handle's internals.
+//
+// One worker thread owns the index handle while the server runs.  It loops:
+// retire finished batches (event query), then fill every free slot with a
+// batch of queued requests (host pack into pinned staging, one H2D copy of
+// offsets and one of bytes, the three work-queue kernels - replayed from a
+// hipGraph captured per slot when asked - and one D2H copy of masks and
+// counts), then sleeps briefly only when there is nothing to do.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "rambo_serve.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServeRequest {
+    int64_t id = 0;
+    uint64_t n_reads = 0;
+    std::vector<uint64_t> offsets;   // rebased to 0
+    std::vector<uint8_t> chars;
+    Clock::time_point t_submit, t_done;
+    std::vector<uint32_t> masks;     // n_reads * W
+    std::vector<uint32_t> nk;        // n_reads
+    bool done = false;
+};
+
+struct ServeSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    void *dmem = nullptr;            // device: header+offsets, bytes, masks, counts, queue state
+    uint64_t *d_hdr = nullptr;       // [0] = reads, [1..] = offsets
+    uint8_t *d_chars = nullptr;
+    uint32_t *d_masks = nullptr;
+    uint32_t *d_nk = nullptr;
+    ReadQueue rq{};
+    void *hmem = nullptr;            // pinned host: header+offsets, bytes, masks, counts
+    uint64_t *h_hdr = nullptr;
+    uint8_t *h_chars = nullptr;
+    uint32_t *h_masks = nullptr;
+    uint32_t *h_nk = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool busy = false;
+    uint64_t n_reads = 0;
+    std::vector<std::shared_ptr<ServeRequest>> reqs;
+};
+
+}  // namespace
+
+struct rambo_server {
+    rambo *h = nullptr;
+    rambo_serve_config cfg{};
+    std::vector<ServeSlot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<ServeRequest>> queue;
+    std::unordered_map<int64_t, std::shared_ptr<ServeRequest>> live;
+    int64_t next_id = 0;
+    bool stop = false;
+    std::thread worker;
+    uint64_t n_batches = 0, n_requests = 0, n_reads = 0;
+    int device = 0;
+    bool timing_before = false;
+};
+
+namespace {
+
+uint64_t slot_device_bytes(const rambo *h, const rambo_serve_config &c)
+{
+    const uint64_t R = c.max_batch_reads;
+    return div_up(8 * (R + 2), 256) * 256 + div_up(c.max_batch_bytes, 256) * 256 +
+           div_up(4ull * R * h->W, 256) * 256 + div_up(4 * R, 256) * 256 + read_queue_bytes(h, R);
+}
+
+void free_slot(ServeSlot &s)
+{
+    if (s.exec)
+        (void)hipGraphExecDestroy(s.exec);
+    if (s.graph)
+        (void)hipGraphDestroy(s.graph);
+    if (s.done_ev)
+        (void)hipEventDestroy(s.done_ev);
+    if (s.stream)
+        (void)hipStreamDestroy(s.stream);
+    if (s.dmem)
+        (void)hipFree(s.dmem);
+    if (s.hmem)
+        (void)hipHostFree(s.hmem);
+    s = ServeSlot{};
+}
+
+int init_slot(rambo *h, const rambo_serve_config &c, ServeSlot &s)
+{
+    const uint64_t R = c.max_batch_reads;
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s.dmem, slot_device_bytes(h, c)) != hipSuccess) {
+        (void)hipGetLastError();
+        return RAMBO_ENOMEM;
+    }
+    uint8_t *d = static_cast<uint8_t *>(s.dmem);
+    s.d_hdr = reinterpret_cast<uint64_t *>(d);
+    d += div_up(8 * (R + 2), 256) * 256;
+    s.d_chars = d;
+    d += div_up(c.max_batch_bytes, 256) * 256;
+    s.d_masks = reinterpret_cast<uint32_t *>(d);
+    d += div_up(4ull * R * h->W, 256) * 256;
+    s.d_nk = reinterpret_cast<uint32_t *>(d);
+    d += div_up(4 * R, 256) * 256;
+    s.rq = carve_read_queue(h, d, R);
+    const uint64_t hb = 8 * (R + 2) + c.max_batch_bytes + 4ull * R * h->W + 4 * R + 64;
+    if (hipHostMalloc(&s.hmem, hb, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return RAMBO_ENOMEM;
+    }
+    uint8_t *p = static_cast<uint8_t *>(s.hmem);
+    s.h_hdr = reinterpret_cast<uint64_t *>(p);
+    p += 8 * (R + 2);
+    s.h_chars = p;
+    p += c.max_batch_bytes;
+    p = reinterpret_cast<uint8_t *>(div_up(reinterpret_cast<uintptr_t>(p), 16) * 16);
+    s.h_masks = reinterpret_cast<uint32_t *>(p);
+    p += 4ull * R * h->W;
+    s.h_nk = reinterpret_cast<uint32_t *>(p);
+    if (c.use_graphs) {
+        // the three kernels with the read count taken from device memory
+        if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return RAMBO_EHIP;
+        launch_read_queue(h, s.rq, s.d_hdr + 1, 0, s.d_hdr, R, s.d_chars, c.max_batch_bytes, s.d_masks, s.d_nk,
+                          s.stream);
+        if (hipStreamEndCapture(s.stream, &s.graph) != hipSuccess ||
+            hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return RAMBO_EHIP;
+        }
+    }
+    return RAMBO_OK;
+}
+
+// Pack queued requests into slot s and start its batch.  Called by the
+// worker with the lock not held; returns whether a batch was started.
+bool start_batch(rambo_server *sv, ServeSlot &s)
+{
+    const rambo_serve_config &c = sv->cfg;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        uint64_t reads = 0, bytes = 0;
+        while (!sv->queue.empty()) {
+            const auto &r = sv->queue.front();
+            const uint64_t rb = r->offsets.back();
+            if (reads + r->n_reads > c.max_batch_reads || bytes + rb > c.max_batch_bytes)
+                break;
+            reads += r->n_reads;
+            bytes += rb;
+            s.reqs.push_back(r);
+            sv->queue.pop_front();
+        }
+    }
+    if (s.reqs.empty())
+        return false;
+    uint64_t reads = 0, bytes = 0;
+    for (const auto &r : s.reqs) {
+        for (uint64_t i = 0; i < r->n_reads; ++i)
+            s.h_hdr[1 + reads + i] = bytes + r->offsets[i];
+        std::memcpy(s.h_chars + bytes, r->chars.data(), r->chars.size());
+        reads += r->n_reads;
+        bytes += r->chars.size();
+    }
+    s.h_hdr[0] = reads;
+    s.h_hdr[1 + reads] = bytes;
+    s.n_reads = reads;
+    (void)hipMemcpyAsync(s.d_hdr, s.h_hdr, 8 * (reads + 2), hipMemcpyHostToDevice, s.stream);
+    if (bytes)
+        (void)hipMemcpyAsync(s.d_chars, s.h_chars, bytes, hipMemcpyHostToDevice, s.stream);
+    if (s.exec)
+        (void)hipGraphLaunch(s.exec, s.stream);
+    else
+        launch_read_queue(sv->h, s.rq, s.d_hdr + 1, reads, nullptr, reads, s.d_chars, bytes, s.d_masks, s.d_nk,
+                          s.stream);
+    (void)hipMemcpyAsync(s.h_masks, s.d_masks, 4ull * reads * sv->h->W, hipMemcpyDeviceToHost, s.stream);
+    (void)hipMemcpyAsync(s.h_nk, s.d_nk, 4 * reads, hipMemcpyDeviceToHost, s.stream);
+    (void)hipEventRecord(s.done_ev, s.stream);
+    s.busy = true;
+    return true;
+}
+
+void finish_batch(rambo_server *sv, ServeSlot &s)
+{
+    const auto t = Clock::now();
+    const uint32_t W = sv->h->W;
+    uint64_t row = 0;
+    for (const auto &r : s.reqs) {
+        r->masks.assign(s.h_masks + row * W, s.h_masks + (row + r->n_reads) * W);
+        r->nk.assign(s.h_nk + row, s.h_nk + row + r->n_reads);
+        row += r->n_reads;
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (const auto &r : s.reqs) {
+            r->t_done = t;
+            r->done = true;
+        }
+        sv->n_batches += 1;
+        sv->n_requests += s.reqs.size();
+        sv->n_reads += s.n_reads;
+    }
+    sv->cv_done.notify_all();
+    s.reqs.clear();
+    s.busy = false;
+}
+
+void serve_loop(rambo_server *sv)
+{
+    (void)hipSetDevice(sv->device);   // the current device is per thread
+    for (;;) {
+        bool progress = false, any_busy = false;
+        for (ServeSlot &s : sv->slots) {
+            if (s.busy && hipEventQuery(s.done_ev) == hipSuccess) {
+                finish_batch(sv, s);
+                progress = true;
+            }
+        }
+        for (ServeSlot &s : sv->slots) {
+            if (!s.busy && start_batch(sv, s))
+                progress = true;
+            any_busy = any_busy || s.busy;
+        }
+        if (progress)
+            continue;
+        std::unique_lock<std::mutex> lk(sv->mu);
+        if (sv->stop && sv->queue.empty() && !any_busy)
+            return;
+        if (any_busy) {
+            // batches in flight: look again shortly (or as soon as work arrives)
+            sv->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        } else {
+            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int rambo_serve_create(rambo_t *h, const rambo_serve_config *cfg_in, rambo_server_t **out)
+{
+    if (!h || !out)
+        return RAMBO_EINVAL;
+    *out = nullptr;
+    rambo_serve_config c = cfg_in ? *cfg_in : rambo_serve_config{};
+    if (c.mem_budget == 0)
+        c.mem_budget = 1ull << 30;
+    if (c.max_batch_bytes == 0)
+        c.max_batch_bytes = 8ull << 20;
+    if (c.max_slots == 0)
+        c.max_slots = 4;
+    if (c.max_batch_reads == 0)
+        c.max_batch_reads = 8192;
+    if (c.max_slots > 16 || c.max_batch_reads > (1u << 24) || c.max_batch_bytes > (1ull << 34))
+        return fail(h, RAMBO_EINVAL, "rambo_serve_create: configuration out of range");
+    const uint64_t per_slot = slot_device_bytes(h, c);
+    const uint64_t n_slots = std::min<uint64_t>(c.max_slots, c.mem_budget / per_slot);
+    if (n_slots == 0)
+        return fail(h, RAMBO_ENOMEM, "rambo_serve_create: budget holds no slot");
+    auto *sv = new (std::nothrow) rambo_server();
+    if (!sv)
+        return RAMBO_ENOMEM;
+    sv->h = h;
+    sv->cfg = c;
+    sv->slots.resize(n_slots);
+    (void)hipGetDevice(&sv->device);
+    const bool timing = h->timing;
+    sv->timing_before = timing;
+    h->timing = false;   // no timing events inside captured graphs or from the worker
+    for (ServeSlot &s : sv->slots) {
+        const int rc = init_slot(h, c, s);
+        if (rc) {
+            for (ServeSlot &t : sv->slots)
+                free_slot(t);
+            delete sv;
+            h->timing = timing;
+            return fail(h, rc, "rambo_serve_create: slot set-up failed");
+        }
+    }
+    sv->worker = std::thread(serve_loop, sv);
+    *out = sv;
+    return RAMBO_OK;
+}
+
+extern "C" void rambo_serve_destroy(rambo_server_t *sv)
+{
+    if (!sv)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->worker.joinable())
+        sv->worker.join();
+    for (ServeSlot &s : sv->slots) {
+        if (s.stream)
+            (void)hipStreamSynchronize(s.stream);
+        free_slot(s);
+    }
+    sv->h->timing = sv->timing_before;
+    delete sv;
+}
+
+extern "C" int64_t rambo_serve_submit(rambo_server_t *sv, const uint64_t *offsets, uint64_t n_reads,
+                                      const uint8_t *chars)
+{
+    if (!sv || !offsets || n_reads == 0)
+        return RAMBO_EINVAL;
+    const uint64_t b0 = offsets[0], b1 = offsets[n_reads];
+    if (b1 < b0 || n_reads > sv->cfg.max_batch_reads || b1 - b0 > sv->cfg.max_batch_bytes || (b1 > b0 && !chars))
+        return RAMBO_EINVAL;
+    auto r = std::make_shared<ServeRequest>();
+    r->n_reads = n_reads;
+    r->offsets.resize(n_reads + 1);
+    for (uint64_t i = 0; i <= n_reads; ++i) {
+        const uint64_t o = offsets[i] < b0 ? b0 : (offsets[i] > b1 ? b1 : offsets[i]);
+        r->offsets[i] = o - b0;
+    }
+    if (b1 > b0)
+        r->chars.assign(chars + b0, chars + b1);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->id = sv->next_id++;
+        r->t_submit = Clock::now();
+        sv->live[r->id] = r;
+        sv->queue.push_back(r);
+    }
+    sv->cv_work.notify_one();
+    return r->id;
+}
+
+extern "C" int rambo_serve_wait(rambo_server_t *sv, int64_t id, uint32_t *masks, uint32_t *nkmers,
+                                double *latency_ms, int64_t timeout_us)
+{
+    if (!sv)
+        return RAMBO_EINVAL;
+    std::shared_ptr<ServeRequest> r;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        auto it = sv->live.find(id);
+        if (it == sv->live.end())
+            return RAMBO_EINVAL;
+        r = it->second;
+        auto ready = [&] { return r->done; };
+        if (timeout_us < 0)
+            sv->cv_done.wait(lk, ready);
+        else if (!sv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+            return RAMBO_ETIMEDOUT;
+        sv->live.erase(it);
+    }
+    if (masks)
+        std::memcpy(masks, r->masks.data(), r->masks.size() * 4);
+    if (nkmers)
+        std::memcpy(nkmers, r->nk.data(), r->nk.size() * 4);
+    if (latency_ms)
+        *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_serve_stats(rambo_server_t *sv, uint64_t *batches, uint64_t *requests, uint64_t *reads,
+                                 uint32_t *slots)
+{
+    if (!sv)
+        return RAMBO_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (batches)
+        *batches = sv->n_batches;
+    if (requests)
+        *requests = sv->n_requests;
+    if (reads)
+        *reads = sv->n_reads;
+    if (slots)
+        *slots = (uint32_t)sv->slots.size();
+    return RAMBO_OK;
+}

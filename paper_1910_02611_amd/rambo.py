@@ -21,6 +21,7 @@ ERANGE = -34
 EOVERFLOW = -75
 EHIP = -1000
 ECODE = -1001
+ETIMEDOUT = -110
 FLAG_IDENTITY_PARTITION = 1
 INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED = 0, 1, 2
 QUERY_AUTO, QUERY_WAVE_PER_READ, QUERY_QUEUE = 0, 1, 2
@@ -65,6 +66,10 @@ EXPORTS = {
                                         ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_extract_kmers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                            ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_query_seqs_ids": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                            ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_fill_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_query_kmers_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_query_seqs_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
@@ -87,7 +92,22 @@ EXPORTS = {
     "rambo_roofline_atomic_or": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                                 ctypes.c_void_p]),
     "rambo_roofline_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    # include/rambo_serve.h
+    "rambo_serve_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rambo_serve_destroy": (None, [ctypes.c_void_p]),
+    "rambo_serve_submit": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "rambo_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
+    "rambo_serve_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint32)]),
 }
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
+                ("max_slots", ctypes.c_uint32), ("max_batch_reads", ctypes.c_uint32),
+                ("use_graphs", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 def lib_path() -> str:
@@ -211,6 +231,38 @@ class Rambo:
                     "rambo_query_seqs")
         return out, nkmers
 
+    def query_seqs_ids(self, offsets, chars, ids=None, nkmers=None, stream=None):
+        """Answers as ascending set-ID lists: (id_offsets int64 [n+1], ids
+        int32 [total], window counts int32 [n]).  Synchronises `stream`; when
+        the given (or first guessed) capacity is too small, calls again with
+        exactly the capacity needed."""
+        n = offsets.numel() - 1
+        id_off = torch.empty(max(n, 0) + 1, dtype=torch.int64, device=offsets.device)
+        if nkmers is None:
+            nkmers = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+        if ids is None:
+            ids = torch.empty(max(1024, 4 * n), dtype=torch.int32, device=offsets.device)
+        for _ in range(2):
+            rc = lib().rambo_query_seqs_ids(self._h, _dptr(offsets, _U64, "offsets"), n,
+                                            _dptr(chars, (torch.uint8,), "chars"), chars.numel(), id_off.data_ptr(),
+                                            ids.data_ptr(), ids.numel(), _dptr(nkmers, _U32, "nkmers"),
+                                            _stream(stream))
+            self._check(rc, "rambo_query_seqs_ids")
+            st = self.sync_status(stream)
+            need = int(id_off[-1].item())
+            if st == OK:
+                return id_off, ids[:need], nkmers[:n]
+            if st != EOVERFLOW:
+                self._check(st, "rambo_query_seqs_ids")
+            ids = torch.empty(need, dtype=torch.int32, device=offsets.device)
+        raise RamboError(EOVERFLOW, "rambo_query_seqs_ids: capacity")
+
+    def fill_counts(self, stream=None) -> torch.Tensor:
+        """Set bits per cell, int64 [R, B] on the device."""
+        out = torch.empty(self.R * self.B, dtype=torch.int64, device="cuda")
+        self._check(lib().rambo_fill_counts(self._h, out.data_ptr(), _stream(stream)), "rambo_fill_counts")
+        return out.view(self.R, self.B)
+
     def extract_kmers(self, offsets, chars, out=None, stream=None):
         n = chars.numel()
         if out is None:
@@ -266,3 +318,65 @@ class Rambo:
         self._check(lib().rambo_copy_index(self._h, word_offset, n_words, out.data_ptr(), _stream(stream)),
                     "rambo_copy_index")
         return out
+
+
+class Server:
+    """A continuous-batching query server on a resident index
+    (include/rambo_serve.h).  Requests are host numpy arrays; the index
+    handle must not be used for anything else until close()."""
+
+    def __init__(self, index: Rambo, mem_budget: int = 0, max_batch_bytes: int = 0, max_slots: int = 0,
+                 max_batch_reads: int = 0, use_graphs: bool = False):
+        self.index = index
+        cfg = ServeConfig(mem_budget, max_batch_bytes, max_slots, max_batch_reads, int(use_graphs), 0)
+        h = ctypes.c_void_p()
+        index._check(lib().rambo_serve_create(index._h, ctypes.byref(cfg), ctypes.byref(h)), "rambo_serve_create")
+        self._s = h
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().rambo_serve_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, offsets, chars) -> int:
+        """Queue reads chars[offsets[i]:offsets[i+1]] (host uint64 offsets,
+        uint8 bytes); returns the request id."""
+        import numpy as np
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        ch = np.ascontiguousarray(np.frombuffer(chars, np.uint8) if isinstance(chars, (bytes, bytearray)) else chars,
+                                  dtype=np.uint8)
+        n = len(off) - 1
+        rid = lib().rambo_serve_submit(self._s, off.ctypes.data, n, ch.ctypes.data if ch.size else None)
+        if rid < 0:
+            raise RamboError(int(rid), "rambo_serve_submit")
+        return int(rid)
+
+    def wait(self, rid: int, n_reads: int, timeout_us: int = -1):
+        """(masks [n_reads, W] uint32, window counts [n_reads] uint32,
+        latency in ms) of request rid."""
+        import numpy as np
+        masks = np.zeros((n_reads, self.index.W), dtype=np.uint32)
+        nk = np.zeros(n_reads, dtype=np.uint32)
+        lat = ctypes.c_double()
+        rc = lib().rambo_serve_wait(self._s, rid, masks.ctypes.data, nk.ctypes.data, ctypes.byref(lat), timeout_us)
+        if rc != OK:
+            raise RamboError(rc, "rambo_serve_wait")
+        return masks, nk, lat.value
+
+    def stats(self) -> dict:
+        b, q, r = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        sl = ctypes.c_uint32()
+        lib().rambo_serve_stats(self._s, ctypes.byref(b), ctypes.byref(q), ctypes.byref(r), ctypes.byref(sl))
+        return {"batches": b.value, "requests": q.value, "reads": r.value, "slots": sl.value}

@@ -1,0 +1,116 @@
+"""Open-loop load driver for the query server (include/rambo_serve.h).
+
+Requests arrive as a Poisson process; a submitter thread hands each one to
+the server at its arrival time, and the caller's thread collects the answers.
+Latency is arrival -> answer in host memory: the server's own submit ->
+result time plus however late the submitter was.  The server, its batching
+and every kernel are native; this module only paces submissions and reports
+percentiles.
+
+    python -m paper_1910_02611_amd.serve --index tiny --requests 20000
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import threading
+import time
+
+import numpy as np
+
+from . import rambo, synth
+
+
+def split_requests(batch: synth.SeqBatch) -> list[tuple[np.ndarray, np.ndarray]]:
+    ro = batch.meta["request_offsets"]
+    return [synth.request(batch, r) for r in range(len(ro) - 1)]
+
+
+def run_open_loop(server: rambo.Server, reqs, arrivals: np.ndarray, W: int) -> dict:
+    """Submit reqs[i] at arrivals[i] seconds (relative to the start); return
+    latencies (ms), throughput and a checksum of the answers."""
+    n = len(reqs)
+    ids = [None] * n
+    lag = np.zeros(n)
+    ready = [threading.Event() for _ in range(n)]
+    t0 = time.perf_counter() + 0.01
+
+    def submitter():
+        for i, (off, ch) in enumerate(reqs):
+            due = t0 + arrivals[i]
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+                now = time.perf_counter()
+            ids[i] = server.submit(off, ch)
+            lag[i] = max(0.0, now - due)
+            ready[i].set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = np.zeros(n)
+    reads = 0
+    check = 0
+    for i, (off, _) in enumerate(reqs):
+        ready[i].wait()
+        nr = len(off) - 1
+        masks, nk, ms = server.wait(ids[i], nr)
+        lat[i] = ms + 1e3 * lag[i]
+        reads += nr
+        check = (check * 1000003 + int(masks.sum(dtype=np.uint64))) & ((1 << 61) - 1)
+    t_end = time.perf_counter()
+    th.join()
+    span = t_end - t0
+    return dict(requests=n, reads=reads, seconds=span, qps=n / span, reads_per_s=reads / span,
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                mean_ms=float(lat.mean()), max_submit_lag_ms=float(1e3 * lag.max()), checksum=check)
+
+
+def saturated(server: rambo.Server, reqs, W: int) -> dict:
+    """Every request queued at once: the server's peak request rate."""
+    return run_open_loop(server, reqs, np.zeros(len(reqs)), W)
+
+
+def sweep(server: rambo.Server, reqs, W: int, fractions, seed: int = 5004, per_point: int | None = None) -> dict:
+    """Saturated throughput, then Poisson load at the given fractions of it."""
+    sat = saturated(server, reqs, W)
+    points = []
+    for j, f in enumerate(fractions):
+        sub = reqs if per_point is None else reqs[:per_point]
+        rate = f * sat["qps"]
+        arr = synth.poisson_arrivals(seed + j, len(sub), rate)
+        r = run_open_loop(server, sub, arr, W)
+        r["offered_qps"] = rate
+        r["load"] = f
+        points.append(r)
+    return dict(saturated=sat, points=points)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--index", choices=["tiny", "mid", "served"], default="tiny")
+    ap.add_argument("--requests", type=int, default=10_000)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--graphs", action="store_true")
+    ap.add_argument("--loads", default="0.1,0.25,0.4,0.55,0.7,0.85,1.0,1.2")
+    args = ap.parse_args()
+    import torch
+
+    sets = {"tiny": synth.config_tiny, "mid": synth.config_mid, "served": synth.config_served}[args.index]()
+    params = {"tiny": synth.INDEX_TINY, "mid": synth.INDEX_MID, "served": synth.INDEX_SERVED}[args.index]
+    idx = rambo.Rambo(**params, seed={"tiny": 2001, "mid": 2002, "served": 2004}[args.index])
+    dev = torch.device("cuda")
+    idx.insert_seqs(torch.from_numpy(sets.set_ids.view(np.int32)).to(dev),
+                    torch.from_numpy(sets.offsets.view(np.int64)).to(dev),
+                    torch.from_numpy(sets.chars).to(dev))
+    torch.cuda.synchronize()
+    reqs = split_requests(synth.served_requests(4004, sets, args.requests))
+    del sets
+    with rambo.Server(idx, max_slots=args.slots, use_graphs=args.graphs) as srv:
+        res = sweep(srv, reqs, idx.W, [float(x) for x in args.loads.split(",")])
+        res["server"] = srv.stats()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

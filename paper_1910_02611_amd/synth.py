@@ -189,7 +189,55 @@ def config_batched_reads(sets: SeqBatch, n: int = 100_000, seed: int = 3003) -> 
     return reads(seed, sets, n, median_len=1000, min_len=100, max_len=10_000, substr_frac=0.7)
 
 
+def config_served(seed: int = 1004) -> SeqBatch:
+    """10 000 sets: lognormal windows (median 500 kbp, 50 kbp - 5 Mbp) of 500
+    random 5 Mbp ancestors, 1% substitutions (about 6.7e9 bases)."""
+    return genome_sets(seed, K=10_000, n_ancestors=500, ancestor_len=5_000_000,
+                       median_len=500_000, min_len=50_000, max_len=5_000_000)
+
+
+def config_large(seed: int = 1005) -> SeqBatch:
+    """100 000 sets: lognormal windows (median 100 kbp, 10 kbp - 1 Mbp) of
+    5 000 random 1 Mbp ancestors, 1% substitutions (about 1.3e10 bases)."""
+    return genome_sets(seed, K=100_000, n_ancestors=5000, ancestor_len=1_000_000,
+                       median_len=100_000, min_len=10_000, max_len=1_000_000)
+
+
+def served_requests(seed: int, sets: SeqBatch, n_requests: int, *, min_reads: int = 1, max_reads: int = 64,
+                    min_len: int = 150, max_len: int = 5000, substr_frac: float = 0.7) -> SeqBatch:
+    """n_requests requests of U{min_reads..max_reads} reads each, read lengths
+    log-uniform in [min_len, max_len], 70% exact substrings of a set genome
+    and 30% random.  All reads in one batch; meta['request_offsets'] (n+1)
+    delimits the requests' reads."""
+    rng = rng_for(seed)
+    per = rng.integers(min_reads, max_reads + 1, size=n_requests)
+    n = int(per.sum())
+    lengths = np.rint(np.exp(rng.uniform(math.log(min_len), math.log(max_len), size=n))).astype(np.int64)
+    batch = reads(seed + 1, sets, n, median_len=0, min_len=min_len, max_len=max_len,
+                  substr_frac=substr_frac, lengths=lengths)
+    ro = np.zeros(n_requests + 1, dtype=np.int64)
+    np.cumsum(per, out=ro[1:])
+    batch.meta["request_offsets"] = ro
+    return batch
+
+
+def request(batch: SeqBatch, r: int) -> tuple[np.ndarray, np.ndarray]:
+    """(offsets rebased to 0, bytes) of request r of a served_requests batch."""
+    ro = batch.meta["request_offsets"]
+    a, b = int(ro[r]), int(ro[r + 1])
+    off = batch.offsets[a:b + 1]
+    return (off - off[0]).astype(np.uint64), batch.chars[int(off[0]):int(off[-1])]
+
+
+def poisson_arrivals(seed: int, n: int, rate: float) -> np.ndarray:
+    """n arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = rng_for(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
 # Index parameters of the workloads: K sets, B cells, R repetitions, m bits per
 # cell, eta hashes, k-mer length.
 INDEX_TINY = dict(K=64, B=8, R=3, m=1 << 18, eta=2, k=31)
 INDEX_MID = dict(K=1000, B=50, R=4, m=1 << 28, eta=2, k=31)
+INDEX_SERVED = dict(K=10_000, B=200, R=5, m=1 << 29, eta=2, k=31)
+INDEX_LARGE = dict(K=100_000, B=1000, R=6, m=1 << 27, eta=2, k=31)

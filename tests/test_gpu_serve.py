@@ -1,0 +1,129 @@
+"""The query server (include/rambo_serve.h): every request's answer is the
+oracle's, and the same whether the request ran alone or packed into a batch
+with others, with or without captured graphs, over one or several slots."""
+import threading
+
+import numpy as np
+import pytest
+
+from paper_1910_02611_amd import rambo as rb
+from paper_1910_02611_amd import serve, synth
+from gpu_util import make_pair, gpu_insert_seqs
+
+pytestmark = pytest.mark.gpu
+TIMEOUT_US = 30_000_000   # a lost request fails the test instead of hanging it
+
+
+@pytest.fixture(scope="module")
+def served():
+    cfg = synth.INDEX_TINY
+    sets = synth.config_tiny()
+    o, g = make_pair(cfg, seed=2001)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    gpu_insert_seqs(g, sets)
+    batch = synth.served_requests(4010, sets, 80, max_len=1500)
+    reqs = serve.split_requests(batch)
+    # edge requests: empty read, reads shorter than k, a break in every window
+    edge_chars = np.frombuffer(b"ACG" + b"A" * 31 + b"ACGTNACGTACGTACGTACGTACGTACGTACGTAC", np.uint8)
+    edge_off = np.array([0, 0, 3, 34, 34 + 35], np.uint64)
+    reqs.insert(5, (edge_off, edge_chars))
+    want = []
+    for off, ch in reqs:
+        m, nk = o.query_seqs(off, ch, nthreads=8)
+        want.append((m, nk.astype(np.uint32)))
+    return g, reqs, want
+
+
+def check(got, want):
+    for i, ((m, nk), (wm, wn)) in enumerate(zip(got, want)):
+        assert np.array_equal(nk, wn), i
+        assert np.array_equal(m, wm), i
+
+
+def alone(srv, reqs):
+    out = []
+    for off, ch in reqs:
+        rid = srv.submit(off, ch)
+        m, nk, _ = srv.wait(rid, len(off) - 1, timeout_us=TIMEOUT_US)
+        out.append((m, nk))
+    return out
+
+
+def mixed(srv, reqs, lead=None):
+    """Submit everything before waiting for anything (after an optional
+    large leading request that keeps the first slot busy meanwhile)."""
+    lead_id = srv.submit(*lead) if lead is not None else None
+    ids = [srv.submit(off, ch) for off, ch in reqs]
+    out = [srv.wait(rid, len(off) - 1, timeout_us=TIMEOUT_US)[:2] for rid, (off, _) in zip(ids, reqs)]
+    if lead_id is not None:
+        srv.wait(lead_id, len(lead[0]) - 1, timeout_us=TIMEOUT_US)
+    return out
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+@pytest.mark.parametrize("slots", [1, 4])
+def test_alone_and_mixed_match_oracle(served, graphs, slots):
+    g, reqs, want = served
+    with rb.Server(g, max_slots=slots, use_graphs=graphs, max_batch_reads=256, max_batch_bytes=1 << 20) as srv:
+        a = alone(srv, reqs)
+        check(a, want)
+        m = mixed(srv, reqs)
+        check(m, want)
+        st = srv.stats()
+    assert st["requests"] == 2 * len(reqs)
+    assert st["reads"] == 2 * sum(len(off) - 1 for off, _ in reqs)
+
+
+def test_requests_share_batches(served):
+    g, reqs, want = served
+    # a large first request keeps the only slot busy while the rest queue up
+    rng = np.random.default_rng(7)
+    big_chars = rng.choice(np.frombuffer(b"ACGT", np.uint8), size=4000 * 2000)
+    big_off = np.arange(0, 4000 * 2000 + 1, 2000, dtype=np.uint64)
+    with rb.Server(g, max_slots=1, max_batch_reads=4096, max_batch_bytes=16 << 20) as srv:
+        m = mixed(srv, reqs, lead=(big_off, big_chars))
+        st = srv.stats()
+    check(m, want)
+    assert st["requests"] == len(reqs) + 1
+    assert st["batches"] < st["requests"]   # some batch held several requests
+
+
+def test_concurrent_clients(served):
+    g, reqs, want = served
+    got = [None] * len(reqs)
+
+    def client(c):
+        for i in range(c, len(reqs), 4):
+            off, ch = reqs[i]
+            rid = srv.submit(off, ch)
+            got[i] = srv.wait(rid, len(off) - 1, timeout_us=TIMEOUT_US)[:2]
+
+    with rb.Server(g, max_slots=3, use_graphs=True, max_batch_reads=512) as srv:
+        ts = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+    check(got, want)
+
+
+def test_open_loop_driver(served):
+    g, reqs, want = served
+    with rb.Server(g, max_slots=2) as srv:
+        r = serve.run_open_loop(srv, reqs, synth.poisson_arrivals(9, len(reqs), 2000.0), g.W)
+    assert r["requests"] == len(reqs)
+    assert 0 < r["p50_ms"] <= r["p99_ms"]
+
+
+def test_errors(served):
+    g, reqs, _ = served
+    with rb.Server(g, max_slots=1, max_batch_reads=16, max_batch_bytes=4096) as srv:
+        off = np.arange(0, 17 * 10 + 1, 10, dtype=np.uint64)   # 17 reads
+        with pytest.raises(rb.RamboError):   # more reads than a batch holds
+            srv.submit(off, np.zeros(170, np.uint8))
+        with pytest.raises(rb.RamboError):   # more bytes than a batch holds
+            srv.submit(np.array([0, 5000], np.uint64), np.zeros(5000, np.uint8))
+        with pytest.raises(rb.RamboError):   # unknown id
+            srv.wait(12345, 1, timeout_us=0)
+    with pytest.raises(rb.RamboError):        # budget too small for one slot
+        rb.Server(g, mem_budget=1024)
