@@ -224,6 +224,102 @@ __global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, co
     }
 }
 
+// Stage A for compile-time shapes: the targets of a round stay in registers
+// instead of an unsorted LDS copy.  Each target takes its rank inside its
+// bucket from the counting atomic itself, so after the scan it goes straight
+// to its sorted slot: LDS holds only the sorted tile (6 bytes per target) and
+// two workgroups fit a CU.
+__host__ __device__ constexpr uint32_t hold_steps(uint32_t re)
+{
+    return 10240u / (kBlockP * re) > 0 ? 10240u / (kBlockP * re) : 1u;
+}
+__host__ __device__ constexpr uint32_t hold_tile(uint32_t re) { return hold_steps(re) * kBlockP * re; }
+__host__ __device__ constexpr size_t lds_bytes_stage_a_hold(uint32_t re, uint32_t na)
+{
+    return hold_tile(re) * 6ull + na * 12ull + 64;
+}
+
+template <int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlockP) __attribute__((amdgpu_waves_per_eu(4)))
+void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
+                        const uint8_t *chars, uint64_t n_chars, uint64_t p_begin, uint64_t p_end, uint32_t rounds)
+{
+    constexpr uint32_t RE = R_T * ETA_T;
+    constexpr uint32_t ST = hold_steps(RE);
+    constexpr uint32_t TILE = hold_tile(RE);
+    constexpr uint32_t NT = ST * RE;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    extern __shared__ uint32_t lds[];
+    uint32_t *srt = lds;                                          // TILE: low bits of each target, sorted
+    uint16_t *sbk = reinterpret_cast<uint16_t *>(srt + TILE);     // TILE: its bucket
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(sbk + TILE);     // na: counts (reset by the reservation)
+    uint32_t *lbase = cnt + G.na;                                 // na: first sorted slot of each bucket
+    uint32_t *gbase = lbase + G.na;                               // na: first slab entry of each run
+    uint32_t *wsum = gbase + G.na;                                // kWavesP
+    const uint32_t shA = G.rb + G.fb;
+    const uint64_t maskA = (1ull << shA) - 1;
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t span = (uint64_t)rounds * ST * kWave;
+    const uint64_t w0 = p_begin + ((uint64_t)blockIdx.x * kWavesP + wv) * span;
+    const uint64_t w1 = min(w0 + span, p_end);
+    const bool busy = w0 < p_end;
+    WindowWalker walker;
+    if (busy)
+        walker.init(offsets, n_seqs, chars, n_chars, w0, w1, P.k, P.kmask);
+    SetCache cache;
+    cache.init_seeds(P);
+    for (uint32_t b = threadIdx.x; b < G.na; b += kBlockP)
+        cnt[b] = 0;
+    __syncthreads();
+
+    for (uint32_t round = 0; round < rounds; ++round) {
+        // bucket | rank << 16 (kNone: no target) and low bits of each held target
+        uint32_t hbr[NT], he[NT];
+#pragma unroll
+        for (uint32_t st = 0; st < ST; ++st) {
+            bool valid = false;
+            uint64_t x = 0, s = 0;
+            if (busy && walker.p < w1)
+                walker.step(valid, x, s);
+            uint64_t gb[RE];
+            const bool ok = window_targets<R_T, ETA_T>(P, set_ids, cache, valid, x, s, gb);
+#pragma unroll
+            for (uint32_t t = 0; t < RE; ++t) {
+                const uint32_t b = (uint32_t)(gb[t] >> shA);
+                he[st * RE + t] = (uint32_t)(gb[t] & maskA);
+                hbr[st * RE + t] = ok ? (b | (atomicAdd(&cnt[b], 1u) << 16)) : kNone;
+            }
+        }
+        __syncthreads();
+        const uint32_t total = block_exclusive_scan(cnt, lbase, G.na, wsum);
+        RunReservation res;
+        res.issue(cnt, G.na, G.fillA);
+#pragma unroll
+        for (uint32_t i = 0; i < NT; ++i) {
+            if (hbr[i] == kNone)
+                continue;
+            const uint32_t b = hbr[i] & 0xFFFFu;
+            const uint32_t pos = lbase[b] + (hbr[i] >> 16);
+            srt[pos] = he[i];
+            sbk[pos] = (uint16_t)b;
+        }
+        res.finish(gbase, G.na, G.slabA, G.capA);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < total; i += kBlockP) {
+            const uint32_t b = sbk[i];
+            const uint32_t e = srt[i];
+            const uint32_t g = gbase[b];
+            if (g == kFail)
+                direct_or(P, ((uint64_t)b << shA) | e);
+            else
+                G.slabA[(uint64_t)b * G.capA + g + (i - lbase[b])] = e;
+        }
+        // no barrier here: the next round's first barrier (after its
+        // counting) is reached only when every wave has finished this loop,
+        // and the counting touches only cnt, which this loop does not read
+    }
+}
+
 // Stage B: block = (coarse bucket, tile of its slab).
 __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
 {

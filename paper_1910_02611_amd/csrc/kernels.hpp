@@ -225,58 +225,67 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l)
            (uint32_t)__builtin_amdgcn_readlane((uint32_t)v, l);
 }
 
-// Alg. 1 for the windows the wave holds: each lane with a valid window (term
-// x of sequence s) gets on_target(gb) for each of its R*eta bit targets, gb
-// being the global bit address in the bit-sliced index of (repetition r,
-// row pos_{r,j}(x), column phi_r(set)).  When every valid lane is in the same
-// sequence - the common case - the set and its columns come from the cache.
-// With compile-time R_T and ETA_T all R*eta hashes of a window are computed
-// as independent chains before the first target is emitted (instruction-level
-// parallelism for the 64-bit multiplies); R_T == 0 is the run-time path.
+// The R*eta bit targets of the window a lane holds (term x of sequence s):
+// gb[t] is the global bit address in the bit-sliced index of (repetition
+// t / eta, row pos_{r,j}(x), column phi_r(set)).  Returns whether this lane
+// has targets (a valid window of a valid set).  When every valid lane is in
+// the same sequence - the common case - the set and its columns come from the
+// cache.  All R*eta hashes are independent chains (instruction-level
+// parallelism for the 64-bit multiplies).  Call on every lane of the wave.
+template <int R_T, int ETA_T>
+__device__ __forceinline__ bool window_targets(const Params &P, const uint32_t *set_ids, SetCache &cache, bool valid,
+                                               uint64_t x, uint64_t s, uint64_t (&gb)[R_T * ETA_T])
+{
+    const uint64_t live = __ballot(valid);
+    if (!live)
+        return false;
+    const uint64_t rep_bits = P.words_per_rep * 32;
+    const int first = __builtin_ctzll(live);
+    const uint64_t s0 = readfirstlane64(__shfl(s, first, kWave));
+    const bool uniform = __ballot(valid && s != s0) == 0;
+    uint32_t cols[R_T];
+    bool ok = valid;
+    if (uniform) {
+        if (s0 != cache.s) {
+            cache.s = s0;
+            cache.set = __builtin_amdgcn_readfirstlane(set_ids[s0]);
+            const uint32_t lane = lane_id();
+            cache.cols = (cache.set < P.K && lane < P.R) ? P.phi[(uint64_t)lane * P.K + cache.set] : 0u;
+        }
+        if (cache.set >= P.K) {
+            if ((int)lane_id() == first)
+                atomicOr(P.err, kErrSetId);
+            return false;
+        }
+#pragma unroll
+        for (int r = 0; r < R_T; ++r)
+            cols[r] = (uint32_t)__builtin_amdgcn_readlane(cache.cols, r);
+    } else {
+        const uint32_t set = valid ? set_ids[s] : 0u;
+        if (valid && set >= P.K)
+            atomicOr(P.err, kErrSetId);
+        ok = valid && set < P.K;
+#pragma unroll
+        for (int r = 0; r < R_T; ++r)
+            cols[r] = ok ? P.phi[(uint64_t)r * P.K + set] : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < R_T * ETA_T; ++t)
+        gb[t] = (uint64_t)(t / ETA_T) * rep_bits + cols[t / ETA_T] +
+                (bf_position(x, readlane64(cache.seed, t), P) << P.S_log2);
+    return ok;
+}
+
+// Alg. 1 for the windows the wave holds: each lane with a valid window gets
+// on_target(gb) for each of its R*eta bit targets (see window_targets).
+// R_T == 0 is the run-time shape path.
 template <int R_T, int ETA_T, class F>
 __device__ __forceinline__ void wave_targets(const Params &P, const uint32_t *set_ids, SetCache &cache, bool valid,
                                              uint64_t x, uint64_t s, F &&on_target)
 {
     if constexpr (R_T > 0) {
-        const uint64_t live = __ballot(valid);
-        if (!live)
-            return;
-        const uint64_t rep_bits = P.words_per_rep * 32;
-        const int first = __builtin_ctzll(live);
-        const uint64_t s0 = readfirstlane64(__shfl(s, first, kWave));
-        const bool uniform = __ballot(valid && s != s0) == 0;
-        uint32_t cols[R_T];
-        bool ok = valid;
-        if (uniform) {
-            if (s0 != cache.s) {
-                cache.s = s0;
-                cache.set = __builtin_amdgcn_readfirstlane(set_ids[s0]);
-                const uint32_t lane = lane_id();
-                cache.cols = (cache.set < P.K && lane < P.R) ? P.phi[(uint64_t)lane * P.K + cache.set] : 0u;
-            }
-            if (cache.set >= P.K) {
-                if ((int)lane_id() == first)
-                    atomicOr(P.err, kErrSetId);
-                return;
-            }
-#pragma unroll
-            for (int r = 0; r < R_T; ++r)
-                cols[r] = (uint32_t)__builtin_amdgcn_readlane(cache.cols, r);
-        } else {
-            const uint32_t set = valid ? set_ids[s] : 0u;
-            if (valid && set >= P.K)
-                atomicOr(P.err, kErrSetId);
-            ok = valid && set < P.K;
-#pragma unroll
-            for (int r = 0; r < R_T; ++r)
-                cols[r] = ok ? P.phi[(uint64_t)r * P.K + set] : 0u;
-        }
         uint64_t gb[R_T * ETA_T];
-#pragma unroll
-        for (int t = 0; t < R_T * ETA_T; ++t)
-            gb[t] = (uint64_t)(t / ETA_T) * rep_bits + cols[t / ETA_T] +
-                    (bf_position(x, readlane64(cache.seed, t), P) << P.S_log2);
-        if (ok) {
+        if (window_targets<R_T, ETA_T>(P, set_ids, cache, valid, x, s, gb)) {
 #pragma unroll
             for (int t = 0; t < R_T * ETA_T; ++t)
                 on_target(gb[t]);

@@ -281,6 +281,48 @@ struct BinWindowsK {
     static constexpr BinWindowsFn fn = k_bin_windows<R_T, ETA_T>;
 };
 
+using BinHoldFn = void (*)(Params, BinGeom, const uint32_t *, const uint64_t *, uint64_t, const uint8_t *, uint64_t,
+                           uint64_t, uint64_t, uint32_t);
+
+// Stage A with the targets held in registers, for the compile-time shapes.
+BinHoldFn pick_bin_hold(uint32_t R, uint32_t eta)
+{
+    if (eta == 2) {
+        switch (R) {
+        case 3: return k_bin_windows_hold<3, 2>;
+        case 4: return k_bin_windows_hold<4, 2>;
+        case 5: return k_bin_windows_hold<5, 2>;
+        case 6: return k_bin_windows_hold<6, 2>;
+        default: break;
+        }
+    }
+    return nullptr;
+}
+
+// The stage-A kernel of a shape, its steps per round and its LDS bytes.
+struct StageA {
+    BinWindowsFn generic = nullptr;
+    BinHoldFn hold = nullptr;
+    uint32_t steps = 0;
+    size_t lds = 0;
+};
+
+StageA stage_a(const rambo *h)
+{
+    const uint32_t RE = h->cfg.R * h->cfg.eta;
+    StageA a;
+    a.hold = pick_bin_hold(h->cfg.R, h->cfg.eta);
+    if (a.hold) {
+        a.steps = hold_steps(RE);
+        a.lds = lds_bytes_stage_a_hold(RE, h->bin.na);
+    } else {
+        a.generic = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
+        a.steps = kTileA / (kBlockP * RE);
+        a.lds = lds_bytes_stage_a(h->bin.na);
+    }
+    return a;
+}
+
 // ------------------------------------------------ batched read queries
 
 // Per-read state of the work-queue launch, grown to hold n_reads reads.
@@ -427,9 +469,9 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     }
     BinGeom &G = h->bin;
     // stages A and B use more than the default 64 KiB of dynamic LDS
-    const BinWindowsFn binA = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(binA),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_a(G.na)) != hipSuccess ||
+    const StageA A = stage_a(h);
+    const void *binA = A.hold ? reinterpret_cast<const void *>(A.hold) : reinterpret_cast<const void *>(A.generic);
+    if (hipFuncSetAttribute(binA, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void *>(k_bin_regions),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_b(G.nf)) != hipSuccess) {
         (void)hipFree(h->bin_mem);
@@ -473,21 +515,26 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
         return rc;
     BinGeom &G = h->bin;
     const uint64_t batch_windows = h->bin_targets / RE;
-    // stage A: each round takes `steps` steps of every wave (at most kTileA targets)
-    const uint32_t steps = (uint32_t)(kTileA / (kBlockP * RE));
+    // stage A: each round takes `steps` steps of every wave
+    const StageA A = stage_a(h);
+    const uint32_t steps = A.steps;
     const uint32_t rounds = (uint32_t)div_up(kStageAWindowsPerWave, (uint64_t)steps * kWave);
     const uint64_t block_windows = (uint64_t)kWavesP * rounds * steps * kWave;
     const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
-    const size_t ldsA = lds_bytes_stage_a(G.na), ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
+    const size_t ldsA = A.lds, ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     for (uint64_t p = 0; p < n_chars; p += batch_windows) {
         const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
         { StageScope sc(h, "k_zero_u32", stream);
         hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
                            (uint64_t)G.na + (uint64_t)G.na * G.nf); }
-        const BinWindowsFn binA = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
         { StageScope sc(h, "k_bin_windows", stream);
-        hipLaunchKernelGGL(binA, dim3((uint32_t)div_up(pe - p, block_windows)), dim3(kBlockP), ldsA, stream, h->P, G,
-                           set_ids, offsets, n_seqs, chars, n_chars, p, pe, steps, rounds); }
+        const dim3 grid((uint32_t)div_up(pe - p, block_windows));
+        if (A.hold)
+            hipLaunchKernelGGL(A.hold, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_seqs, chars,
+                               n_chars, p, pe, rounds);
+        else
+            hipLaunchKernelGGL(A.generic, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_seqs,
+                               chars, n_chars, p, pe, steps, rounds); }
         { StageScope sc(h, "k_bin_regions", stream);
         hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
         { StageScope sc(h, "k_apply_regions", stream);
