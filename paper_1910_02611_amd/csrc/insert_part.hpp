@@ -14,6 +14,9 @@
 //  B  k_bin_regions : each tile of a coarse bucket's slab is split the same
 //                     way into the bucket's fine buckets (index regions of
 //                     2^rb bits).
+// Stages A and B keep a tile's targets in registers while they are counted:
+// the counting atomic returns each target's rank inside its bucket, so after
+// the scan every target goes straight to its slot in the sorted LDS tile.
 //  C  k_apply_regions: one workgroup per region loads the region into LDS,
 //                     ORs in its targets with LDS atomics and writes it back.
 //
@@ -51,7 +54,7 @@ struct BinGeom {
 };
 
 __host__ __device__ constexpr size_t lds_bytes_stage_a(uint32_t na) { return kTileA * 12ull + na * 12ull + 64; }
-__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 8ull + nf * 12ull + 64; }
+__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 4ull + nf * 12ull + 64; }
 
 // Exclusive prefix sum of cnt[0..n) into start[0..n) by the whole
 // workgroup; returns the total.  wsum holds kWavesP words of LDS.
@@ -92,21 +95,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(const uint32_t *cnt, ui
 
 // Reserving one run per bucket takes a global atomicAdd round trip.  The
 // reservation is split so that the LDS scatter runs while the atomics are in
-// flight: issue() starts them (cnt[b] entries for bucket b, at most
-// kMaxBucketsPerThread buckets per thread) and resets cnt[b] to 0, the run
-// cursor; finish() stores gbase[b], the run's first slab entry, or kFail for
-// a run that does not fit - whose slab tail, if it starts inside the slab, is
-// filled with sentinels so readers skip it.
+// flight: issue() starts them (cnt[b] entries for bucket b, at most kSlots
+// buckets per thread) and resets cnt[b] to 0; finish() stores gbase[b], the
+// run's first slab entry, or kFail for a run that does not fit - whose slab
+// tail, if it starts inside the slab, is filled with sentinels so readers
+// skip it.
 constexpr uint32_t kMaxBucketsPerThread = 8;   // 4096 buckets / 512 threads
 
-struct RunReservation {
-    uint32_t pos[kMaxBucketsPerThread];
-    uint32_t c[kMaxBucketsPerThread];
+template <uint32_t kSlots>
+struct RunReservationT {
+    uint32_t pos[kSlots];
+    uint32_t c[kSlots];
 
     __device__ __forceinline__ void issue(uint32_t *cnt, uint32_t nb, uint32_t *fill)
     {
 #pragma unroll
-        for (uint32_t i = 0; i < kMaxBucketsPerThread; ++i) {
+        for (uint32_t i = 0; i < kSlots; ++i) {
             const uint32_t b = threadIdx.x + i * kBlockP;
             c[i] = 0;
             pos[i] = 0;
@@ -122,7 +126,7 @@ struct RunReservation {
     __device__ __forceinline__ void finish(uint32_t *gbase, uint32_t nb, uint32_t *slab, uint64_t cap)
     {
 #pragma unroll
-        for (uint32_t i = 0; i < kMaxBucketsPerThread; ++i) {
+        for (uint32_t i = 0; i < kSlots; ++i) {
             const uint32_t b = threadIdx.x + i * kBlockP;
             if (b >= nb)
                 continue;
@@ -138,6 +142,7 @@ struct RunReservation {
         }
     }
 };
+using RunReservation = RunReservationT<kMaxBucketsPerThread>;
 
 // Stage A over the windows starting in [p_begin, p_end).  Wave w of block g
 // walks `rounds * steps * 64` consecutive windows; each round the workgroup
@@ -229,6 +234,8 @@ __global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, co
 // bucket from the counting atomic itself, so after the scan it goes straight
 // to its sorted slot: LDS holds only the sorted tile (6 bytes per target) and
 // two workgroups fit a CU.
+constexpr uint32_t kHoldBucketsPerThread = 4;   // the held-target kernel takes at most 2048 coarse buckets
+
 __host__ __device__ constexpr uint32_t hold_steps(uint32_t re)
 {
     return 10240u / (kBlockP * re) > 0 ? 10240u / (kBlockP * re) : 1u;
@@ -292,7 +299,7 @@ void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint
         }
         __syncthreads();
         const uint32_t total = block_exclusive_scan(cnt, lbase, G.na, wsum);
-        RunReservation res;
+        RunReservationT<kHoldBucketsPerThread> res;
         res.issue(cnt, G.na, G.fillA);
 #pragma unroll
         for (uint32_t i = 0; i < NT; ++i) {
@@ -320,16 +327,19 @@ void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint
     }
 }
 
-// Stage B: block = (coarse bucket, tile of its slab).
+// Stage B: block = (coarse bucket, tile of its slab).  The tile's entries
+// stay in registers; the counting atomic gives each its rank inside its
+// region, so after the scan it goes straight to its sorted LDS slot (4 bytes
+// of LDS per entry).
 __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
 {
     extern __shared__ uint32_t lds[];
-    uint32_t *ent = lds;                // kTileB entries as read
-    uint32_t *srt = ent + kTileB;       // kTileB entries sorted by region
-    uint32_t *cnt = srt + kTileB;       // nf counts, then run cursors
+    uint32_t *srt = lds;                // kTileB entries sorted by region
+    uint32_t *cnt = srt + kTileB;       // nf counts (reset by the reservation)
     uint32_t *lbase = cnt + G.nf;       // nf first sorted slots
     uint32_t *gbase = lbase + G.nf;     // nf first slab entries of the runs
     uint32_t *wsum = gbase + G.nf;      // kWavesP
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
     const uint32_t c = blockIdx.x / tiles_per_bucket;
     const uint32_t tile = blockIdx.x % tiles_per_bucket;
     const uint64_t n_c = min((uint64_t)G.fillA[c], G.capA);
@@ -340,28 +350,26 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     const uint32_t *src = G.slabA + (uint64_t)c * G.capA + t0;   // 16-byte aligned: capA, t0 are multiples of 4
     for (uint32_t b = threadIdx.x; b < G.nf; b += kBlockP)
         cnt[b] = 0;
-    {
-        // unconditional loads (clamped to the last vector) so none waits for
-        // another; only ent[0..n) is used below
-        constexpr int kV = kTileB / 4 / kBlockP;
-        u32x4 v[kV];
-        const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
-        const uint32_t n4 = (n + 3) / 4;
+    // unconditional loads (clamped to the last vector) so none waits for
+    // another; entries past n are not counted
+    constexpr int kV = kTileB / 4 / kBlockP;
+    u32x4 v[kV];
+    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+    const uint32_t n4 = (n + 3) / 4;
 #pragma unroll
-        for (int i = 0; i < kV; ++i)
-            v[i] = s4[min((uint32_t)(i * kBlockP) + threadIdx.x, n4 - 1)];
-#pragma unroll
-        for (int i = 0; i < kV; ++i) {
-            const uint32_t j = i * kBlockP + threadIdx.x;
-            if (j < n4)
-                reinterpret_cast<u32x4 *>(ent)[j] = v[i];
-        }
-    }
+    for (int i = 0; i < kV; ++i)
+        v[i] = s4[min((uint32_t)(i * kBlockP) + threadIdx.x, n4 - 1)];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kBlockP) {
-        const uint32_t e = ent[i];
-        if (e != kSentinel)
-            atomicAdd(&cnt[e >> G.rb], 1u);
+    uint32_t rk[kV * 4];
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+        const uint32_t j = (uint32_t)(i * kBlockP) + threadIdx.x;
+        const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool ok = j * 4 + q < n && e[q] != kSentinel;
+            rk[i * 4 + q] = ok ? atomicAdd(&cnt[e[q] >> G.rb], 1u) : kNone;
+        }
     }
     __syncthreads();
     const uint32_t total = block_exclusive_scan(cnt, lbase, G.nf, wsum);
@@ -369,13 +377,13 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     uint32_t *slab = G.slabB + (uint64_t)c * G.nf * G.capB;
     RunReservation res;
     res.issue(cnt, G.nf, fill);
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kBlockP) {
-        const uint32_t e = ent[i];
-        if (e == kSentinel)
-            continue;
-        const uint32_t f = e >> G.rb;
-        srt[lbase[f] + atomicAdd(&cnt[f], 1u)] = e;
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+        const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (rk[i * 4 + q] != kNone)
+                srt[lbase[e[q] >> G.rb] + rk[i * 4 + q]] = e[q];
     }
     res.finish(gbase, G.nf, slab, G.capB);
     __syncthreads();

@@ -311,7 +311,7 @@ StageA stage_a(const rambo *h)
 {
     const uint32_t RE = h->cfg.R * h->cfg.eta;
     StageA a;
-    a.hold = pick_bin_hold(h->cfg.R, h->cfg.eta);
+    a.hold = h->bin.na <= kHoldBucketsPerThread * kBlockP ? pick_bin_hold(h->cfg.R, h->cfg.eta) : nullptr;
     if (a.hold) {
         a.steps = hold_steps(RE);
         a.lds = lds_bytes_stage_a_hold(RE, h->bin.na);
