@@ -48,13 +48,23 @@ struct BinGeom {
     uint64_t capB;        // slab entries per region
     uint32_t *slabA;      // na * capA
     uint32_t *fillA;      // na
-    uint32_t *slabB;      // na * nf * capB
+    uint32_t *slabB;      // n_regions * capB
     uint32_t *fillB;      // na * nf
+    uint32_t *dirty;      // na * nf: a fallback atomic wrote into this region
     uint64_t total_words; // words of the index (all repetitions)
 };
 
 __host__ __device__ constexpr size_t lds_bytes_stage_a(uint32_t na) { return kTileA * 12ull + na * 12ull + 64; }
 __host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 4ull + nf * 12ull + 64; }
+
+// A target whose run did not fit its slab is set with a global atomic right
+// away; its region is marked so that stage C reads the region back even into
+// an index known to have been all zero.
+__device__ __forceinline__ void fallback_or(const Params &P, const BinGeom &G, uint64_t gb)
+{
+    direct_or(P, gb);
+    G.dirty[gb >> G.rb] = 1u;
+}
 
 // Exclusive prefix sum of cnt[0..n) into start[0..n) by the whole
 // workgroup; returns the total.  wsum holds kWavesP words of LDS.
@@ -221,7 +231,7 @@ __global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, co
             const uint32_t e = srt[i];
             const uint32_t g = gbase[b];
             if (g == kFail)
-                direct_or(P, ((uint64_t)b << shA) | e);
+                fallback_or(P, G, ((uint64_t)b << shA) | e);
             else
                 G.slabA[(uint64_t)b * G.capA + g + (i - lbase[b])] = e;
         }
@@ -317,7 +327,7 @@ void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint
             const uint32_t e = srt[i];
             const uint32_t g = gbase[b];
             if (g == kFail)
-                direct_or(P, ((uint64_t)b << shA) | e);
+                fallback_or(P, G, ((uint64_t)b << shA) | e);
             else
                 G.slabA[(uint64_t)b * G.capA + g + (i - lbase[b])] = e;
         }
@@ -394,14 +404,17 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
         const uint32_t f = e >> G.rb;
         const uint32_t g = gbase[f];
         if (g == kFail)
-            direct_or(P, cbit + e);
+            fallback_or(P, G, cbit + e);
         else
             slab[(uint64_t)f * G.capB + g + (i - lbase[f])] = e & maskB;
     }
 }
 
 // Stage C: block = region.  Regions no target reached are left untouched.
-__global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G)
+// With `fresh` the index is known to have been all zero before this batch
+// (nothing inserted since it was created or cleared): a region that no
+// fallback atomic touched starts from zero in LDS instead of being read.
+__global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, uint32_t fresh)
 {
     extern __shared__ uint32_t lds[];   // 2^rb / 32 words
     const uint64_t g = blockIdx.x;
@@ -424,7 +437,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G)
     // every load is unconditional (clamped to an in-bounds vector) so all of
     // them are in flight before the first use.
     u32x4 ev[kBatch];
-    {
+    if (fresh && !G.dirty[g]) {
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            ev[i] = s4[min((uint64_t)i * kBlock + threadIdx.x, n4 - 1)];
+        const u32x4 zero = {0u, 0u, 0u, 0u};
+        for (uint32_t j = threadIdx.x; j < nw4; j += kBlock)
+            l4[j] = zero;
+    } else {
         u32x4 rv[kRegion4PerThread];
 #pragma unroll
         for (int i = 0; i < kRegion4PerThread; ++i)

@@ -30,6 +30,7 @@ struct rambo {
     uint16_t *phi = nullptr;
     uint32_t *cellmask = nullptr;
     int *err = nullptr;
+    bool index_zero = true;          // nothing inserted since create or clear
     std::string last_error;
     // partitioned insertion
     int insert_mode = RAMBO_INSERT_AUTO;
@@ -411,6 +412,9 @@ constexpr double kAtomicRate = 1.7e10;      // measured random atomicOr/s over a
 constexpr double kStreamRate = 4.0e12;      // streaming bytes/s the partitioned path sustains
 constexpr uint32_t kStageAWindowsPerWave = 2048;
 
+// Regions of 2^rb bits that hold index bits (the last may be partial).
+uint64_t n_regions(const BinGeom &G) { return div_up(G.total_words * 32, 1ull << G.rb); }
+
 void plan_partition(rambo *h)
 {
     const uint64_t total_words = (uint64_t)h->cfg.R * h->words_per_rep;
@@ -429,13 +433,19 @@ void plan_partition(rambo *h)
                  lds_bytes_stage_a(G.na) <= kMaxLds && lds_bytes_stage_b(G.nf) <= kMaxLds;
 }
 
+// Slab capacities for T targets per batch spread evenly over the index (the
+// index may hold fewer bits than na coarse buckets of nf regions), with
+// margins for the statistical spread; skewed inputs overflow into the
+// fallback atomics.
 uint64_t scratch_bytes_for(const BinGeom &G, uint64_t T, uint64_t &capA, uint64_t &capB)
 {
-    capA = (uint64_t)((double)T / G.na * 1.04) + 4096;
-    capB = (uint64_t)((double)T / ((double)G.na * G.nf) * 1.08) + 512;
+    const double bits = (double)G.total_words * 32.0;
+    const double coarse = bits / (double)(1ull << (G.rb + G.fb)), regions = bits / (double)(1ull << G.rb);
+    capA = (uint64_t)((double)T / (coarse < 1.0 ? 1.0 : coarse) * 1.04) + 4096;
+    capB = (uint64_t)((double)T / (regions < 1.0 ? 1.0 : regions) * 1.08) + 512;
     capA = div_up(capA, 4) * 4;
     capB = div_up(capB, 4) * 4;
-    return 4 * ((uint64_t)G.na * capA + (uint64_t)G.na * G.nf * capB + G.na + (uint64_t)G.na * G.nf);
+    return 4 * ((uint64_t)G.na * capA + n_regions(G) * capB + G.na + 2ull * G.na * G.nf);
 }
 
 // Allocate the scratch of the partitioned path once: as many targets per
@@ -484,10 +494,12 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     G.slabA = p;
     p += (uint64_t)G.na * capA;
     G.slabB = p;
-    p += (uint64_t)G.na * G.nf * capB;
+    p += n_regions(G) * capB;
     G.fillA = p;
     p += G.na;
     G.fillB = p;
+    p += (uint64_t)G.na * G.nf;
+    G.dirty = p;
     h->bin_targets = T;
     return RAMBO_OK;
 }
@@ -522,11 +534,14 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
     const uint64_t block_windows = (uint64_t)kWavesP * rounds * steps * kWave;
     const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
     const size_t ldsA = A.lds, ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
-    for (uint64_t p = 0; p < n_chars; p += batch_windows) {
+    // the first batch into an all-zero index need not read the regions back
+    uint32_t fresh = h->index_zero ? 1u : 0u;
+    h->index_zero = false;
+    for (uint64_t p = 0; p < n_chars; p += batch_windows, fresh = 0) {
         const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
         { StageScope sc(h, "k_zero_u32", stream);
         hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
-                           (uint64_t)G.na + (uint64_t)G.na * G.nf); }
+                           (uint64_t)G.na + 2ull * G.na * G.nf); }   // fillA, fillB, dirty
         { StageScope sc(h, "k_bin_windows", stream);
         const dim3 grid((uint32_t)div_up(pe - p, block_windows));
         if (A.hold)
@@ -538,7 +553,7 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
         { StageScope sc(h, "k_bin_regions", stream);
         hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
         { StageScope sc(h, "k_apply_regions", stream);
-        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G); }
+        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G, fresh); }
         if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
             return rc;
     }
@@ -744,6 +759,7 @@ extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uin
         return RAMBO_OK;
     if (!set_ids || !offsets || !codes)
         return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
+    h->index_zero = false;
     StageScope sc(h, "k_insert_kmers", stream);
     hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,
                        set_ids, offsets, n_sets, codes, n_codes);
@@ -761,6 +777,7 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
         return fail(h, RAMBO_EINVAL, "rambo_insert_seqs: NULL array");
     if (use_partitioned(h, n_chars))
         return insert_seqs_partitioned(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
+    h->index_zero = false;
     const uint64_t waves = div_up(n_chars, kChunk);
     const InsertSeqsFn ins = pick_shape<InsertSeqsFn, InsertSeqsK>(h->cfg.R, h->cfg.eta);
     StageScope sc(h, "k_insert_seqs", stream);
@@ -910,7 +927,10 @@ extern "C" int rambo_clear(rambo_t *h, hipStream_t stream)
 {
     if (!h)
         return RAMBO_EINVAL;
-    return hip_check(h, hipMemsetAsync(h->index, 0, h->index_bytes, stream), "rambo_clear");
+    const int rc = hip_check(h, hipMemsetAsync(h->index, 0, h->index_bytes, stream), "rambo_clear");
+    if (rc == RAMBO_OK)
+        h->index_zero = true;
+    return rc;
 }
 
 extern "C" int rambo_get_info(const rambo_t *h, rambo_info *out)

@@ -279,6 +279,32 @@ def test_partitioned_insert_in_many_batches(tiny):
     assert torch.equal(g.index_words(), g_direct.index_words())
 
 
+def test_partitioned_insert_reads_back_earlier_bits(tiny):
+    # bits set by a direct k-mer insert, and by an earlier partitioned call,
+    # survive a later partitioned insert (only the first insert into an
+    # all-zero index skips reading the regions back); a clear makes the next
+    # insert start from zero again
+    cfg, sets, o, g_direct = tiny
+    _, g = _partitioned_pair(cfg, 2001)
+    half = sets.n // 2
+    first = synth.SeqBatch(sets.chars, sets.offsets[:half + 1], sets.set_ids[:half])
+    rest_off = sets.offsets[half:]
+    rest = synth.SeqBatch(sets.chars, rest_off, sets.set_ids[half:])
+    codes = oracle.extract(sets.offsets, sets.chars, cfg["k"])
+    seg = np.searchsorted(sets.offsets[1:], np.arange(codes.size), side="right")
+    keep = (codes != oracle.NO_KMER) & (seg < half)
+    offs = np.zeros(half + 1, np.uint64)
+    offs[1:] = np.cumsum(np.bincount(seg[keep], minlength=half))
+    g.insert_kmers(dev(first.set_ids, np.int32), dev(offs, np.int64), dev(codes[keep].copy(), np.int64))
+    gpu_insert_seqs(g, rest)
+    assert torch.equal(g.index_words(), g_direct.index_words())
+    g.clear()
+    gpu_insert_seqs(g, first)
+    gpu_insert_seqs(g, rest)
+    assert g.sync_status() == 0
+    assert torch.equal(g.index_words(), g_direct.index_words())
+
+
 def test_partitioned_insert_overflow_falls_back():
     # one k-mer repeated thousands of times crowds one region past its slab
     cfg = dict(K=8, B=4, R=3, eta=2, k=21, m=1 << 16)
