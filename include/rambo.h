@@ -21,8 +21,10 @@
  *   draw a_r = 1 + u mod (2^61-2), b_r = u mod (2^61-1); then for r, j draw
  *   s_{r,j}.  phi_r(i) = ((a_r i + b_r) mod (2^61-1)) mod B (Carter-Wegman,
  *   the 2-universal family of Sec. 3.1).  Position j of term x in repetition
- *   r: floor(mix64(x XOR s_{r,j}) * m / 2^64), mix64 = splitmix64's output
- *   function; the B cells of one repetition share these positions.
+ *   r: multiply-shift (Dietzfelbinger et al. 1997) with the odd multiplier
+ *   a_{r,j} = s_{r,j} | 1 over mix64(x), splitmix64's output function (a
+ *   bijection): floor(((a_{r,j} * mix64(x)) mod 2^64) * m / 2^64); the B
+ *   cells of one repetition share these positions.
  *
  * Index layout in device memory (bit-sliced): repetition r is a block of
  * words_per_rep 32-bit words; inside it, row p (a Bloom-filter position)

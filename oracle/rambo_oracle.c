@@ -24,11 +24,18 @@
  *  - Partition hash phi_r (Alg. 1, Sec. 3.1), applied to the set identity:
  *    phi_r(i) = ((a_r * i + b_r) mod P) mod B with P = 2^61 - 1, the
  *    Carter-Wegman 2-universal family the paper cites; repetitions 0..R-1.
- *  - Bloom-filter hash h_{r,j} (Sec. 2): pos = floor(mix64(x XOR s_{r,j}) * m
- *    / 2^64), where mix64 is the output function of splitmix64 (Steele, Lea
- *    and Flood, OOPSLA 2014) and the floor-of-product range reduction is
- *    Lemire's (2019).  The eta seeds of a repetition are shared by the B
- *    cells of that repetition and differ between repetitions.
+ *  - Bloom-filter hashes h_{r,j} (Sec. 2, Alg. 1: eta universal hash
+ *    functions per filter): the multiply-shift family of Dietzfelbinger,
+ *    Hagerup, Katajainen and Penttonen (J. Algorithms 1997) over a fixed
+ *    bijective mix of the code, pos = floor(((a_{r,j} * mix64(x)) mod 2^64)
+ *    * m / 2^64) with a_{r,j} = s_{r,j} OR 1 (odd).  mix64 is the output
+ *    function of splitmix64 (Steele, Lea and Flood, OOPSLA 2014); being a
+ *    bijection it keeps distinct codes distinct, and for distinct keys a
+ *    random odd multiplier collides with probability at most 2/m.  For a
+ *    power-of-two m this is the top log2(m) bits of the product; otherwise
+ *    the floor-of-product range reduction is Lemire's (2019).  The eta
+ *    multipliers of a repetition are shared by the B cells of that
+ *    repetition and differ between repetitions.
  *  - Seeds: one splitmix64 stream from the master seed yields, in order,
  *    (a_r, b_r) for r = 0..R-1 with a_r = 1 + u mod (P-1), b_r = u mod P,
  *    then s_{r,j} for r = 0..R-1, j = 0..eta-1.
@@ -77,11 +84,14 @@ uint32_t orc_partition_value(uint64_t a, uint64_t b, uint64_t i, uint32_t B)
     return (uint32_t)(modp % B);
 }
 
-/* Bloom-filter position (Sec. 2): floor(mix64(x ^ s) * m / 2^64). */
+/* Bloom-filter position (Sec. 2): multiply-shift with the odd multiplier
+ * seed|1 over mix64(x), reduced to [0, m): floor((((seed|1) * mix64(x)) mod
+ * 2^64) * m / 2^64). */
 uint64_t orc_position(uint64_t x, uint64_t seed, uint64_t m)
 {
-    uint64_t h = orc_mix64(x ^ seed);
-    return (uint64_t)(((unsigned __int128)h * m) >> 64);
+    uint64_t h = orc_mix64(x);
+    uint64_t v = (seed | 1ULL) * h; /* mod 2^64 */
+    return (uint64_t)(((unsigned __int128)v * m) >> 64);
 }
 
 /* ------------------------------------------------------------- k-mer code */

@@ -39,7 +39,7 @@ struct Params {
     uint32_t rep_first;         // bit t: probe t is the first of its repetition
     uint32_t rep_last;          // bit t: probe t is the last of its repetition
     uint8_t rep_of[RAMBO_MAX_RETA];    // repetition of probe t = r*eta + j
-    uint64_t seeds[RAMBO_MAX_RETA];    // s_{r,j} at t = r*eta + j
+    uint64_t seeds[RAMBO_MAX_RETA];    // odd multipliers s_{r,j} | 1 at t = r*eta + j
 };
 
 __device__ __forceinline__ uint32_t lane_id()
@@ -55,12 +55,15 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// Bloom-filter position: floor(mix64(x ^ s) * m / 2^64); a shift when m is a
-// power of two.
-__device__ __forceinline__ uint64_t bf_position(uint64_t x, uint64_t seed, const Params &P)
+// Bloom-filter position (Sec. 2, eta universal hashes per filter): the
+// multiply-shift family over hx = mix64(x), the term's bijective mix computed
+// once per term.  mult is the odd multiplier of (repetition, hash):
+// floor(((mult * hx) mod 2^64) * m / 2^64), the top log2(m) bits of the
+// product when m is a power of two.
+__device__ __forceinline__ uint64_t bf_position(uint64_t hx, uint64_t mult, const Params &P)
 {
-    const uint64_t h = mix64(x ^ seed);
-    return P.m_log2 ? (h >> (64u - P.m_log2)) : __umul64hi(h, P.m);
+    const uint64_t v = mult * hx;
+    return P.m_log2 ? (v >> (64u - P.m_log2)) : __umul64hi(v, P.m);
 }
 
 // Base value of one byte: A/a 0, C/c 1, G/g 2, T/t 3, anything else 4.

@@ -269,10 +269,11 @@ __device__ __forceinline__ bool window_targets(const Params &P, const uint32_t *
         for (int r = 0; r < R_T; ++r)
             cols[r] = ok ? P.phi[(uint64_t)r * P.K + set] : 0u;
     }
+    const uint64_t hx = mix64(x);
 #pragma unroll
     for (int t = 0; t < R_T * ETA_T; ++t)
         gb[t] = (uint64_t)(t / ETA_T) * rep_bits + cols[t / ETA_T] +
-                (bf_position(x, readlane64(cache.seed, t), P) << P.S_log2);
+                (bf_position(hx, readlane64(cache.seed, t), P) << P.S_log2);
     return ok;
 }
 
@@ -296,6 +297,7 @@ __device__ __forceinline__ void wave_targets(const Params &P, const uint32_t *se
     if (!live)
         return;
     const uint64_t rep_bits = P.words_per_rep * 32;
+    const uint64_t hx = mix64(x);
     const int first = __builtin_ctzll(live);
     const uint64_t s0 = readfirstlane64(__shfl(s, first, kWave));
     if (__ballot(valid && s != s0) == 0) {
@@ -315,7 +317,7 @@ __device__ __forceinline__ void wave_targets(const Params &P, const uint32_t *se
             for (uint32_t j = 0; j < P.eta; ++j, ++t) {
                 const uint64_t seed = readlane64(cache.seed, t);
                 if (valid)
-                    on_target(base + (bf_position(x, seed, P) << P.S_log2));
+                    on_target(base + (bf_position(hx, seed, P) << P.S_log2));
             }
         }
         return;
@@ -329,7 +331,7 @@ __device__ __forceinline__ void wave_targets(const Params &P, const uint32_t *se
         for (uint32_t j = 0; j < P.eta; ++j, ++t) {
             const uint64_t seed = readlane64(cache.seed, t);
             if (ok)
-                on_target(base + (bf_position(x, seed, P) << P.S_log2));
+                on_target(base + (bf_position(hx, seed, P) << P.S_log2));
         }
     }
 }
@@ -386,32 +388,32 @@ __global__ __launch_bounds__(kBlock) void k_insert_kmers(Params P, const uint32_
         atomicOr(P.err, kErrCode);
         return;
     }
-    const uint64_t x = canonical(code, P.k);
+    const uint64_t hx = mix64(canonical(code, P.k));
     for (uint32_t r = 0; r < P.R; ++r) {
         const uint32_t col = P.phi[(uint64_t)r * P.K + set];
         for (uint32_t j = 0; j < P.eta; ++j)
-            set_cell_bit(P, r, bf_position(x, P.seeds[r * P.eta + j], P), col);
+            set_cell_bit(P, r, bf_position(hx, P.seeds[r * P.eta + j], P), col);
     }
 }
 
 // ------------------------------------------------------------------ probe
 
-// Group masks of term x for row words [w0, w0+L): g[r][.] = AND over j of
-// row pos_{r,j}(x) of repetition r (Alg. 2, "Q in BF(M[b,r])" for all b of
-// repetition r at once).  Compile-time R_T/ETA_T issue all R*eta loads
+// Group masks of the term with mix hx = mix64(x) for row words [w0, w0+L):
+// g[r][.] = AND over j of row pos_{r,j}(x) of repetition r (Alg. 2, the
+// filter test of every cell b of repetition r at once).  Compile-time R_T/ETA_T issue all R*eta loads
 // before the first use; R_T == 0 is the run-time-sized path.
 template <int SW, int L, int R_T, int ETA_T>
 struct Probe {
     static constexpr int RN = R_T > 0 ? R_T : 1;
     // Fixed-size path: every load in flight at once.
-    __device__ __forceinline__ static void run(const Params &P, uint64_t x, int w0, bool ok, uint32_t (&g)[RN][L])
+    __device__ __forceinline__ static void run(const Params &P, uint64_t hx, int w0, bool ok, uint32_t (&g)[RN][L])
     {
         static_assert(R_T > 0 && ETA_T > 0, "fixed path");
         uint32_t rows[R_T * ETA_T][L];
 #pragma unroll
         for (int t = 0; t < R_T * ETA_T; ++t) {
             if (ok) {
-                load_row<SW, L>(P, t / ETA_T, bf_position(x, P.seeds[t], P), w0, rows[t]);
+                load_row<SW, L>(P, t / ETA_T, bf_position(hx, P.seeds[t], P), w0, rows[t]);
             } else {
 #pragma unroll
                 for (int w = 0; w < L; ++w)
@@ -434,7 +436,7 @@ struct Probe {
 
 // Run-time R and eta: one repetition at a time.
 template <int SW, int L>
-__device__ __forceinline__ void probe_rep(const Params &P, uint64_t x, uint32_t r, int w0, bool ok, uint32_t (&acc)[L])
+__device__ __forceinline__ void probe_rep(const Params &P, uint64_t hx, uint32_t r, int w0, bool ok, uint32_t (&acc)[L])
 {
 #pragma unroll
     for (int w = 0; w < L; ++w)
@@ -443,7 +445,7 @@ __device__ __forceinline__ void probe_rep(const Params &P, uint64_t x, uint32_t 
         return;
     for (uint32_t j = 0; j < P.eta; ++j) {
         uint32_t row[L];
-        load_row<SW, L>(P, r, bf_position(x, P.seeds[r * P.eta + j], P), w0, row);
+        load_row<SW, L>(P, r, bf_position(hx, P.seeds[r * P.eta + j], P), w0, row);
 #pragma unroll
         for (int w = 0; w < L; ++w)
             acc[w] &= row[w];
@@ -511,11 +513,11 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
     const bool ok = live && code <= P.kmask;
     if (live && !ok && part == 0)
         atomicOr(P.err, kErrCode);
-    const uint64_t x = canonical(code & P.kmask, P.k);
+    const uint64_t hx = mix64(canonical(code & P.kmask, P.k));
 
     if constexpr (R_T > 0) {
         uint32_t g[R_T][L];
-        Probe<SW, L, R_T, ETA_T>::run(P, x, part * L, ok, g);
+        Probe<SW, L, R_T, ETA_T>::run(P, hx, part * L, ok, g);
 #pragma unroll
         for (int r = 0; r < R_T; ++r)
 #pragma unroll
@@ -524,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
     } else {
         for (uint32_t r = 0; r < R; ++r) {
             uint32_t acc[L];
-            probe_rep<SW, L>(P, x, r, part * L, ok, acc);
+            probe_rep<SW, L>(P, hx, r, part * L, ok, acc);
 #pragma unroll
             for (int w = 0; w < L; ++w)
                 gq[r * SW + part * L + w] = acc[w];
@@ -590,12 +592,13 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
         uint64_t x = 0;
         const bool valid = (p + lane < p_stop) && window_code(A, Bg, lane, P.k, kmask, x);
         nk += (uint32_t)__popcll(__ballot(valid));
+        const uint64_t hx = mix64(x);
         if (!dead) {
 #pragma unroll 1
             for (int sl = 0; sl < NSL; ++sl) {
                 if constexpr (R_T > 0) {
                     uint32_t g[R_T][L];
-                    Probe<SW, L, R_T, ETA_T>::run(P, x, sl * L, valid, g);
+                    Probe<SW, L, R_T, ETA_T>::run(P, hx, sl * L, valid, g);
 #pragma unroll
                     for (int r = 0; r < R_T; ++r)
 #pragma unroll
@@ -607,7 +610,7 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
                 } else {
                     for (uint32_t r = 0; r < R; ++r) {
                         uint32_t acc[L];
-                        probe_rep<SW, L>(P, x, r, sl * L, valid, acc);
+                        probe_rep<SW, L>(P, hx, r, sl * L, valid, acc);
 #pragma unroll
                         for (int w = 0; w < L; ++w) {
                             const uint32_t a = wave_and(valid ? acc[w] : ~0u);

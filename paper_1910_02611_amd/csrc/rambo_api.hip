@@ -607,7 +607,7 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
     for (uint32_t r = 0; r < c.R; ++r)
         for (uint32_t j = 0; j < c.eta; ++j) {
             const uint32_t t = r * c.eta + j;
-            P.seeds[t] = splitmix64_next(st);
+            P.seeds[t] = splitmix64_next(st) | 1u;   // odd multiplier of the multiply-shift hash
             P.rep_of[t] = (uint8_t)r;
             if (j == 0)
                 P.rep_first |= 1u << t;

@@ -6,8 +6,10 @@
 * partition hash: hand-worked closed forms of (a i + b) mod (2^61 - 1) mod B,
   the partition invariant and the 1/B collision rate of a 2-universal family
   (Sec. 3.1; Sec. 5.2 and the appendix state the 1/B collision probability).
-* Bloom-filter positions: range, the power-of-two special case and a
-  chi-square uniformity test.
+* Bloom-filter positions: range, the power-of-two special case, a
+  chi-square uniformity test, and the pairwise collision bound of the
+  multiply-shift family (at most 2/m over random odd multipliers,
+  Dietzfelbinger et al. 1997).
 """
 import os
 
@@ -145,9 +147,9 @@ def test_position_range_and_power_of_two_case():
     for x in rng.integers(0, 1 << 62, size=200, dtype=np.uint64):
         x = int(x)
         for s in (0, 12345, (1 << 64) - 1):
-            h = oracle.mix64(x ^ s)
+            v = ((s | 1) * oracle.mix64(x)) % (1 << 64)
             for t in (6, 18, 28, 40):
-                assert oracle.position(x, s, 1 << t) == h >> (64 - t)
+                assert oracle.position(x, s, 1 << t) == v >> (64 - t)
             for m in (64, 1000, 3 * (1 << 20) + 7):
                 assert 0 <= oracle.position(x, s, m) < m
 
@@ -162,6 +164,24 @@ def test_position_uniformity_chi2():
         counts[oracle.position(x, 0x1234ABCD, m)] += 1
     chi2 = ((counts - n / m) ** 2 / (n / m)).sum()
     assert stats.chi2.sf(chi2, m - 1) > 1e-4
+
+
+def test_position_pair_collision_rate():
+    # multiply-shift is 2-universal up to a factor 2: for fixed distinct keys
+    # and a random odd multiplier, P[pos(x) = pos(y)] <= 2/m; averaged over
+    # key pairs it is close to 1/m.  Codes one apart are the hardest pairs.
+    m = 1 << 8
+    rng = np.random.default_rng(11)
+    seeds = [int(v) for v in rng.integers(0, 1 << 63, size=4000, dtype=np.uint64)]
+    total, hits = 0, 0
+    for x in [0, 1, 12345, (1 << 61) + 3, 4 ** 31 - 2]:
+        for y in (x + 1, x + 2, x ^ (1 << 40)):
+            c = sum(oracle.position(x, s, m) == oracle.position(y, s, m) for s in seeds)
+            assert c / len(seeds) <= 2.0 / m + 4 * np.sqrt(2.0 / m / len(seeds))
+            hits += c
+            total += len(seeds)
+    p = hits / total
+    assert abs(p - 1.0 / m) <= 4 * np.sqrt(1.0 / m / total) + 0.25 / m
 
 
 def test_mask_bit_order_and_padding():
