@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -85,28 +86,39 @@ def time_steps(g, dsets, codes, out, steps: int, warmup: int):
 
 # Integer work of the binning kernel's algorithm, in 32-bit VALU operations
 # (64-bit shift 1, 64-bit xor/add 2, 64x64 multiply 5): extracting one
-# canonical window from the packed streams, and per bit target the seed xor,
-# mix64 (two xorshift-multiply rounds and a final xorshift), the position
-# shift, the bit address and its bucket split.
-ALU_OPS_PER_WINDOW = 30
-ALU_OPS_PER_TARGET = 32
+# canonical window from the packed streams and mixing it once (two
+# xorshift-multiply rounds and a final xorshift: 19), and per bit target the
+# multiply-shift position (5 + 1), the bit address (4) and its bucket split
+# (2).
+ALU_OPS_PER_WINDOW = 30 + 19
+ALU_OPS_PER_TARGET = 12
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock: 39.3 T int32 ops/s
+TRAFFIC_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_mid.json")
 
 
-def kernel_rooflines(kernels, n_ins, n_queries, RE, S, W, index_bytes):
+def kernel_rooflines(kernels, n_ins, n_queries, RE, S, W, index_bytes, fresh=True):
     """Roofline entry of each timed kernel: algorithmic work per launch over
-    its measured duration."""
+    its measured duration.  fresh: the insert went into an all-zero index,
+    so stage C writes the index without reading it."""
+    from paper_1910_02611_amd.profsum import load_traffic
     targets = n_ins * RE
     work = {
-        "k_bin_windows": ("alu", n_ins * (ALU_OPS_PER_WINDOW + RE * ALU_OPS_PER_TARGET), "TFLOP/s",
+        "k_bin_windows": ("alu", n_ins * (ALU_OPS_PER_WINDOW + RE * ALU_OPS_PER_TARGET), "TOP/s",
                           "int32 VALU ops: %d per window + %d per target" % (ALU_OPS_PER_WINDOW, ALU_OPS_PER_TARGET)),
         "k_bin_regions": ("hbm", targets * 8, "GB/s", "4 B read + 4 B written per bit target"),
-        "k_apply_regions": ("hbm", targets * 4 + 2 * index_bytes, "GB/s",
-                            "4 B read per bit target + index read and written once"),
+        "k_apply_regions": ("hbm", targets * 4 + (1 if fresh else 2) * index_bytes, "GB/s",
+                            "4 B read per bit target + index written once (and read once unless the index "
+                            "was all zero)"),
         "k_insert_seqs": ("hbm", n_ins * RE * 2 * SECTOR, "GB/s", "one 64-B sector read-modify-write per target"),
         "k_query_kmers": ("hbm", n_queries * (RE * max(SECTOR, S // 8) + 4 * W + 8), "GB/s",
                           "R*eta row sectors + K-bit answer + code per query"),
     }
+    measured = load_traffic(TRAFFIC_JSON)
+    launch_bytes = {}
+    if measured is not None:
+        for name, v in measured["kernels"].items():
+            base = re.sub(r"<.*", "", name).replace("_hold", "")
+            launch_bytes[base] = v["bytes"]
     out = []
     for name, ms in kernels.items():
         if name not in work:
@@ -118,7 +130,8 @@ def kernel_rooflines(kernels, n_ins, n_queries, RE, S, W, index_bytes):
         else:
             achieved, peak = amount / sec / 1e9, HBM_PEAK_GBS
         out.append({"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                    "frac": achieved / peak, "traffic": None, "ms": ms, "work_per_launch": amount, "work": what})
+                    "frac": achieved / peak, "traffic": launch_bytes.get(name), "ms": ms,
+                    "work_per_launch": amount, "work": what})
     out.sort(key=lambda r: -r["ms"])
     return out
 

@@ -405,15 +405,17 @@ __global__ __launch_bounds__(kBlock) void k_insert_kmers(Params P, const uint32_
 template <int SW, int L, int R_T, int ETA_T>
 struct Probe {
     static constexpr int RN = R_T > 0 ? R_T : 1;
-    // Fixed-size path: every load in flight at once.
-    __device__ __forceinline__ static void run(const Params &P, uint64_t hx, int w0, bool ok, uint32_t (&g)[RN][L])
+    // Fixed-size path: every load in flight at once.  Repetitions r0 ..
+    // r0 + R_T - 1 go to g[0 .. R_T - 1].
+    __device__ __forceinline__ static void run(const Params &P, uint64_t hx, int w0, bool ok, uint32_t (&g)[RN][L],
+                                               int r0 = 0)
     {
         static_assert(R_T > 0 && ETA_T > 0, "fixed path");
         uint32_t rows[R_T * ETA_T][L];
 #pragma unroll
         for (int t = 0; t < R_T * ETA_T; ++t) {
             if (ok) {
-                load_row<SW, L>(P, t / ETA_T, bf_position(hx, P.seeds[t], P), w0, rows[t]);
+                load_row<SW, L>(P, r0 + t / ETA_T, bf_position(hx, P.seeds[r0 * ETA_T + t], P), w0, rows[t]);
             } else {
 #pragma unroll
                 for (int w = 0; w < L; ++w)
@@ -516,13 +518,31 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
     const uint64_t hx = mix64(canonical(code & P.kmask, P.k));
 
     if constexpr (R_T > 0) {
-        uint32_t g[R_T][L];
-        Probe<SW, L, R_T, ETA_T>::run(P, hx, part * L, ok, g);
+        // Repetition 0 first: a term with no positive cell there has an empty
+        // answer whatever the other repetitions hold (the intersection of
+        // Alg. 2 is empty), so it reads no further rows.  Most absent terms
+        // stop here; present terms go on with all other rows in flight.
+        uint32_t g0[1][L];
+        Probe<SW, L, 1, ETA_T>::run(P, hx, part * L, ok, g0);
+        uint32_t any = 0;
 #pragma unroll
-        for (int r = 0; r < R_T; ++r)
+        for (int w = 0; w < L; ++w)
+            any |= g0[0][w];
 #pragma unroll
-            for (int w = 0; w < L; ++w)
-                gq[r * SW + part * L + w] = g[r][w];
+        for (int off = 1; off < G; off <<= 1)
+            any |= __shfl_xor(any, off, kWave);
+#pragma unroll
+        for (int w = 0; w < L; ++w)
+            gq[part * L + w] = g0[0][w];
+        if constexpr (R_T > 1) {
+            uint32_t g[R_T - 1][L];
+            Probe<SW, L, R_T - 1, ETA_T>::run(P, hx, part * L, ok && any != 0, g, 1);
+#pragma unroll
+            for (int r = 1; r < R_T; ++r)
+#pragma unroll
+                for (int w = 0; w < L; ++w)
+                    gq[r * SW + part * L + w] = g[r - 1][w];
+        }
     } else {
         for (uint32_t r = 0; r < R; ++r) {
             uint32_t acc[L];

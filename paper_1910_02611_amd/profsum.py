@@ -1,0 +1,141 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics and memory counters).
+
+    python -m paper_1910_02611_amd.profsum trace DIR/NAME_kernel_stats.csv --title T --cmd C > OUT.md
+    python -m paper_1910_02611_amd.profsum traffic --fetch DIR/F_counter_collection.csv \
+        --write DIR/W_counter_collection.csv --copy-bytes N --title T --cmd C --json OUT.json > OUT.md
+
+The traffic summary turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, each
+from its own run) into bytes per launch, each scaled by what the counter
+reads for the streaming copy kernel of known size (N bytes read and N bytes
+written) that the same run launches.  The JSON form carries a hash of the
+kernel sources, so a reader can tell whether the kernels changed since.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources and headers of the library."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def short_name(full: str) -> str:
+    """rambo_dev::k_bin_windows_hold<4, 2>(...) -> k_bin_windows_hold<4, 2>"""
+    s = re.sub(r"^void ", "", full)
+    s = s.split("(")[0]
+    return s.replace("rambo_dev::", "")
+
+
+def trace_md(path: str, title: str, cmd: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["# %s" % title, "", "Command (from the repository root on the MI355X host):", "", "```", cmd, "```", "",
+           "| kernel | calls | total ns | avg ns | % | min ns | max ns |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append("| %s | %s | %d | %d | %.2f | %d | %d |" % (
+            short_name(r["Name"]), r["Calls"], int(float(r["TotalDurationNs"])), int(float(r["AverageNs"])),
+            float(r["Percentage"]), int(float(r["MinNs"])), int(float(r["MaxNs"]))))
+    return "\n".join(out) + "\n"
+
+
+def per_dispatch(path: str, counter: str) -> dict[str, list[float]]:
+    """kernel -> [counter value of each dispatch] (values of one dispatch summed)."""
+    acc: dict[tuple[str, str], float] = collections.defaultdict(float)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        acc[(short_name(r["Kernel_Name"]), r["Dispatch_Id"])] += float(r["Counter_Value"])
+    out: dict[str, list[float]] = collections.defaultdict(list)
+    for (k, _), v in acc.items():
+        out[k].append(v)
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, copy_bytes: int) -> dict:
+    fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(write_csv, "WRITE_SIZE")
+    copy = [k for k in fetch if k.startswith("k_copy")]
+    if not copy:
+        raise SystemExit("no k_copy dispatch in %s: run with --calib-copy-gib" % fetch_csv)
+    f_copy = max(fetch[copy[0]]) * 1024.0
+    w_copy = max(write[copy[0]]) * 1024.0
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    kernels = {}
+    for k in sorted(set(fetch) | set(write)):
+        fv, wv = fetch.get(k, []), write.get(k, [])
+        fb = (sum(fv) / len(fv)) * 1024.0 * f_scale if fv else 0.0
+        wb = (sum(wv) / len(wv)) * 1024.0 * w_scale if wv else 0.0
+        kernels[k] = {"dispatches": max(len(fv), len(wv)), "fetch_bytes": fb, "write_bytes": wb,
+                      "bytes": fb + wb}
+    return {"copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
+            "kernel_source_sha256": kernel_source_hash(), "kernels": kernels}
+
+
+def traffic_md(t: dict, title: str, cmd: str) -> str:
+    out = ["# %s" % title, "", "Commands (from the repository root on the MI355X host):", "", "```", cmd, "```", "",
+           "Calibration: a streaming copy of %d bytes (read once, written once) reads FETCH_SIZE x %.3f and "
+           "WRITE_SIZE x %.3f of its true bytes; every figure below is scaled by those factors." % (
+               t["copy_bytes"], 1 / t["fetch_scale"], 1 / t["write_scale"]), "",
+           "Kernel source hash: `%s`" % t["kernel_source_sha256"], "",
+           "| kernel | dispatches | HBM read / launch | HBM written / launch | total / launch |",
+           "|---|---:|---:|---:|---:|"]
+    for k, v in t["kernels"].items():
+        out.append("| %s | %d | %.4g B | %.4g B | %.4g B |" % (k, v["dispatches"], v["fetch_bytes"],
+                                                            v["write_bytes"], v["bytes"]))
+    return "\n".join(out) + "\n"
+
+
+def load_traffic(path: str) -> dict | None:
+    """The traffic summary at path, or None when missing or when the kernel
+    sources changed since it was taken."""
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("trace")
+    a.add_argument("stats_csv")
+    a.add_argument("--title", required=True)
+    a.add_argument("--cmd", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--title", required=True)
+    b.add_argument("--cmd", required=True)
+    b.add_argument("--json")
+    args = ap.parse_args()
+    if args.what == "trace":
+        sys.stdout.write(trace_md(args.stats_csv, args.title, args.cmd))
+    else:
+        t = traffic(args.fetch, args.write, args.copy_bytes)
+        if args.json:
+            with open(args.json, "w") as f:
+                json.dump(t, f, indent=1)
+        sys.stdout.write(traffic_md(t, args.title, args.cmd))
+
+
+if __name__ == "__main__":
+    main()
