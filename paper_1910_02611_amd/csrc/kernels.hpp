@@ -556,6 +556,41 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    if ((P.W & 3u) == 0) {
+        // The wave's answers are QPW * W consecutive words: each lane takes 4
+        // of them (one 16-byte store) per step.  Empty answers are zeros;
+        // the others OR 16-byte slices of the cell masks.
+        const uint32_t ql2 = lane < (uint32_t)QPW ? lane : 0u;
+        const bool nonempty = lane < (uint32_t)QPW && qbase + lane < n &&
+                              !any_rep_empty(gs + (wv * QPW + ql2) * RMAX * SW, R, SW);
+        const uint64_t ne = __ballot(nonempty);
+        const uint32_t W4 = P.W / 4;
+        const uint64_t n_here = min((uint64_t)QPW, n - qbase);
+        const uint32_t total4 = (uint32_t)n_here * W4;
+        u32x4 *o4 = reinterpret_cast<u32x4 *>(out + qbase * P.W);
+        for (uint32_t i = lane; i < total4; i += kWave) {
+            const uint32_t qi = i / W4, w = (i - qi * W4) * 4;
+            u32x4 acc = {0u, 0u, 0u, 0u};
+            if ((ne >> qi) & 1) {
+                const uint32_t *g2 = gs + (wv * QPW + qi) * RMAX * SW;
+                acc = ~acc;
+                for (uint32_t r = 0; r < R; ++r) {
+                    u32x4 u = {0u, 0u, 0u, 0u};
+                    for (uint32_t sw = 0; sw < (uint32_t)SW; ++sw) {
+                        uint32_t bits = g2[r * SW + sw];
+                        while (bits) {
+                            const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
+                            bits &= bits - 1;
+                            u |= *reinterpret_cast<const u32x4 *>(P.cellmask + ((uint64_t)r * P.B + b) * P.W + w);
+                        }
+                    }
+                    acc &= u;
+                }
+            }
+            o4[i] = acc;
+        }
+        return;
+    }
     // Expansion: sub-groups of WG lanes, one query per sub-group at a time.
     uint32_t WG = 1;
     while (WG < P.W && WG < (uint32_t)kWave)

@@ -220,6 +220,8 @@ SHAPES = [
     dict(K=4100, B=4096, R=2, eta=1, k=31, m=256),
     dict(K=64, B=8, R=7, eta=2, k=31, m=1 << 12),
     dict(K=64, B=8, R=3, eta=1, k=31, m=1 << 12),
+    dict(K=4096, B=256, R=3, eta=2, k=31, m=1 << 11),   # answer words a multiple of 4, 2 lanes per query
+    dict(K=1024, B=64, R=5, eta=2, k=31, m=1 << 12),    # answer words a multiple of 4, one lane per query
 ]
 
 
