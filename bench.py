@@ -327,7 +327,7 @@ def main():
                                          torch.cuda.current_stream().cuda_stream) == 0
         torch.cuda.synchronize()
         del buf
-    plain_rate, plain_same = float("nan"), None
+    plain_rate, plain_same = None, None
     if args.plain_prefix > 0:
         plain_rate, plain_same = plain_path(g, codes, out, min(args.plain_prefix, q.n))
         log("plain one-launch-per-query path: %.3g queries/s on %d, identical=%s"
@@ -347,7 +347,7 @@ def main():
         "kernel_ms": kernels,
         "roofline": roofs[0], "roofline_other": roofs[1:],
         "plain_path": {"k_mer_queries_per_s": plain_rate, "prefix": args.plain_prefix,
-                       "identical": plain_same, "speedup_batched": q_per_s / plain_rate},
+                       "identical": plain_same, "speedup_batched": q_per_s / plain_rate if plain_rate else None},
     }
     if args.serve_requests > 0:
         res["serving"] = serving(g, sets, args.serve_requests, [float(x) for x in args.serve_loads.split(",")])

@@ -3,6 +3,7 @@
     python -m paper_1910_02611_amd.profsum trace DIR/NAME_kernel_stats.csv --title T --cmd C > OUT.md
     python -m paper_1910_02611_amd.profsum traffic --fetch DIR/F_counter_collection.csv \
         --write DIR/W_counter_collection.csv --copy-bytes N --title T --cmd C --json OUT.json > OUT.md
+    python -m paper_1910_02611_amd.profsum counters DIR/X_counter_collection.csv --title T --cmd C > OUT.md
 
 The traffic summary turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, each
 from its own run) into bytes per launch, each scaled by what the counter
@@ -99,6 +100,23 @@ def traffic_md(t: dict, title: str, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def counters_md(path: str, title: str, cmd: str) -> str:
+    """Per-kernel averages of every counter in a counter-collection CSV."""
+    names = sorted({r["Counter_Name"] for r in csv.DictReader(open(path))})
+    vals = {n: per_dispatch(path, n) for n in names}
+    kernels = sorted({k for v in vals.values() for k in v})
+    out = ["# %s" % title, "", "Command (from the repository root on the MI355X host):", "", "```", cmd, "```", "",
+           "Values are per dispatch, averaged over the dispatches of each kernel.", "",
+           "| kernel | " + " | ".join(names) + " |", "|---|" + "---:|" * len(names)]
+    for k in kernels:
+        cells = []
+        for n in names:
+            v = vals[n].get(k)
+            cells.append("%.4g" % (sum(v) / len(v)) if v else "")
+        out.append("| %s | %s |" % (k, " | ".join(cells)))
+    return "\n".join(out) + "\n"
+
+
 def load_traffic(path: str) -> dict | None:
     """The traffic summary at path, or None when missing or when the kernel
     sources changed since it was taken."""
@@ -126,9 +144,15 @@ def main():
     b.add_argument("--title", required=True)
     b.add_argument("--cmd", required=True)
     b.add_argument("--json")
+    c = sub.add_parser("counters")
+    c.add_argument("counter_csv")
+    c.add_argument("--title", required=True)
+    c.add_argument("--cmd", required=True)
     args = ap.parse_args()
     if args.what == "trace":
         sys.stdout.write(trace_md(args.stats_csv, args.title, args.cmd))
+    elif args.what == "counters":
+        sys.stdout.write(counters_md(args.counter_csv, args.title, args.cmd))
     else:
         t = traffic(args.fetch, args.write, args.copy_bytes)
         if args.json:

@@ -98,13 +98,15 @@ def genome_sets(seed: int, K: int, n_ancestors: int, ancestor_len: int, *,
         lens = np.full(K, ancestor_len, dtype=np.int64)
     else:
         lens = lognormal_lengths(rng, K, median_len, min_len, min(max_len, ancestor_len))
-    parts = []
+    offsets = np.zeros(K + 1, dtype=np.uint64)
+    np.cumsum(lens.astype(np.uint64), out=offsets[1:])
+    chars = np.empty(int(offsets[-1]), dtype=np.uint8)   # filled in place: no second copy of the genomes
     for i in range(K):
         a = anc[i % n_ancestors]
         L = int(lens[i])
         start = int(rng.integers(0, ancestor_len - L + 1))
-        parts.append(to_bytes(substitute(rng, a[start:start + L], sub_rate)))
-    chars, offsets = _csr(parts)
+        o = int(offsets[i])
+        chars[o:o + L] = _LUT[substitute(rng, a[start:start + L], sub_rate)]
     return SeqBatch(chars, offsets, np.arange(K, dtype=np.uint32),
                     meta=dict(K=K, n_ancestors=n_ancestors, ancestor_len=ancestor_len,
                               sub_rate=sub_rate, median_len=median_len))
