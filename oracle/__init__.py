@@ -22,6 +22,7 @@ _SRC = os.path.join(_HERE, "rambo_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FLAG_IDENTITY_PARTITION = 1
+FLAG_NO_FILTERS = 2   # parameters only, for the row scans of indexes larger than host memory
 NO_KMER = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -75,6 +76,9 @@ def lib():
             "orc_copy_bfu": (None, [vp, u32, u32, vp]),
             "orc_bits_at": (None, [vp, u32, vp, u64, vp]),
             "orc_max_threads": (i32, []),
+            "orc_scan_rows": (i32, [vp, vp, vp, vp, u64, u64, vp, vp, u64, vp, i32, i32]),
+            "orc_window_keys": (u64, [vp, vp, vp, u64, vp, u64]),
+            "orc_query_seqs_rows": (i32, [vp, vp, vp, u64, vp, u64, vp, vp, vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -256,6 +260,56 @@ class OracleIndex:
         out = np.zeros((rows.size, self.B), np.uint8)
         lib().orc_bits_at(self._h, r, _ptr(rows), rows.size, _ptr(out))
         return out
+
+    # rows of indexes too large for host memory (works with FLAG_NO_FILTERS)
+    @property
+    def row_words(self) -> int:
+        return (self.B + 63) // 64
+
+    def window_keys(self, offsets, chars) -> np.ndarray:
+        """Row keys r*m + pos_{r,j}(x) of every valid window of every read."""
+        offsets = np.ascontiguousarray(offsets, np.uint64)
+        chars = np.ascontiguousarray(chars, np.uint8)
+        n = offsets.size - 1
+        cnt = int(lib().orc_window_keys(self._h, _ptr(offsets), _ptr(chars), n, None, 0))
+        out = np.zeros(max(cnt, 1), np.uint64)
+        lib().orc_window_keys(self._h, _ptr(offsets), _ptr(chars), n, _ptr(out), cnt)
+        return out[:cnt]
+
+    def scan_rows(self, set_ids, offsets, chars, D: int = 0, keys=None, nthreads=0, progress=False):
+        """One pass over the inserted sets: (rows p % D == 0 of every
+        repetition as [R, m/D, BW] uint64 or None, rows of the given
+        ascending distinct keys as [n_keys, BW] uint64 or None)."""
+        set_ids = np.ascontiguousarray(set_ids, np.uint32)
+        offsets = np.ascontiguousarray(offsets, np.uint64)
+        chars = np.ascontiguousarray(chars, np.uint8)
+        BW = self.row_words
+        sampled = np.zeros((self.R, self.m // D, BW), np.uint64) if D else None
+        keys = None if keys is None else np.ascontiguousarray(keys, np.uint64)
+        rows = np.zeros((keys.size, BW), np.uint64) if keys is not None else None
+        rc = lib().orc_scan_rows(self._h, _ptr(set_ids), _ptr(offsets), _ptr(chars), set_ids.size, D,
+                                 _ptr(sampled) if sampled is not None else None,
+                                 _ptr(keys) if keys is not None else None, 0 if keys is None else keys.size,
+                                 _ptr(rows) if rows is not None else None, nthreads, int(progress))
+        if rc != 0:
+            raise ValueError("orc_scan_rows failed (%d)" % rc)
+        return sampled, rows
+
+    def query_seqs_rows(self, offsets, chars, keys, rows, nthreads=0):
+        """Sec. 3.2.1 answers of reads with the filter bits read from rows
+        (as scan_rows returns them): (masks [n, W], window counts [n])."""
+        offsets = np.ascontiguousarray(offsets, np.uint64)
+        chars = np.ascontiguousarray(chars, np.uint8)
+        keys = np.ascontiguousarray(keys, np.uint64)
+        rows = np.ascontiguousarray(rows, np.uint64)
+        n = offsets.size - 1
+        out = np.zeros((n, self.W), np.uint32)
+        nk = np.zeros(n, np.uint64)
+        rc = lib().orc_query_seqs_rows(self._h, _ptr(offsets), _ptr(chars), n, _ptr(keys), keys.size, _ptr(rows),
+                                       _ptr(out), _ptr(nk), nthreads)
+        if rc != 0:
+            raise ValueError("orc_query_seqs_rows failed (%d): a needed row is missing" % rc)
+        return out, nk
 
 
 def max_threads() -> int:

@@ -43,6 +43,7 @@
  *  - A sequence query with no valid k-mer answers the empty set.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -55,6 +56,7 @@
 #define ORC_ERANGE (-34)
 
 #define ORC_FLAG_IDENTITY_PARTITION 1u
+#define ORC_FLAG_NO_FILTERS 2u          /* parameters only: for the row scans of large indexes */
 #define ORC_NO_KMER UINT64_MAX
 
 static const uint64_t ORC_P61 = (1ULL << 61) - 1;
@@ -187,7 +189,7 @@ void orc_destroy(orc_index *h)
         return;
     if (h->bfu) {
         for (uint64_t c = 0; c < (uint64_t)h->R * h->B; c++)
-            free(h->bfu[c]);
+            free(h->bfu[c]);   /* NULL without filters */
         free(h->bfu);
     }
     free(h->pa); free(h->pb); free(h->ps); free(h->phi);
@@ -249,7 +251,7 @@ int orc_create(uint32_t K, uint32_t B, uint32_t R, uint32_t eta, uint32_t k, uin
     h->member_off[(size_t)R * B] = pos;
 
     /* B x R array of Bloom filters, all bits 0 (Alg. 1, Sec. 2). */
-    for (uint64_t c = 0; c < (uint64_t)R * B; c++) {
+    for (uint64_t c = 0; c < (uint64_t)R * B && !(flags & ORC_FLAG_NO_FILTERS); c++) {
         h->bfu[c] = calloc(h->words, sizeof(uint64_t));
         if (!h->bfu[c]) {
             orc_destroy(h);
@@ -289,6 +291,8 @@ static int orc_bf_query(const orc_index *h, uint32_t r, uint32_t cell, uint64_t 
  * repetition. */
 int orc_insert_kmer(orc_index *h, uint32_t set_id, uint64_t code)
 {
+    if (h->flags & ORC_FLAG_NO_FILTERS)
+        return ORC_EINVAL;
     if (set_id >= h->K)
         return ORC_ERANGE;
     if (!orc_code_in_range(code, h->k))
@@ -318,6 +322,8 @@ int orc_insert_seq(orc_index *h, uint32_t set_id, const unsigned char *chars, ui
 int orc_insert_seqs(orc_index *h, const uint32_t *set_ids, const uint64_t *offsets,
                     const unsigned char *chars, uint64_t n_seqs, int nthreads)
 {
+    if (h->flags & ORC_FLAG_NO_FILTERS)
+        return ORC_EINVAL;
     for (uint64_t s = 0; s < n_seqs; s++)
         if (set_ids[s] >= h->K)
             return ORC_ERANGE;
@@ -347,6 +353,8 @@ int orc_insert_seqs(orc_index *h, const uint32_t *set_ids, const uint64_t *offse
 int orc_insert_kmers(orc_index *h, const uint32_t *set_ids, const uint64_t *offsets,
                      const uint64_t *codes, uint64_t n_sets, int nthreads)
 {
+    if (h->flags & ORC_FLAG_NO_FILTERS)
+        return ORC_EINVAL;
     for (uint64_t s = 0; s < n_sets; s++) {
         if (set_ids[s] >= h->K)
             return ORC_ERANGE;
@@ -389,6 +397,8 @@ static void orc_mask_set(uint32_t *mask, uint32_t i) { mask[i >> 5] |= 1u << (i 
  * A code outside [0, 4^k) is not a term and answers the empty set. */
 int orc_query_kmer(const orc_index *h, uint64_t code, uint32_t *mask)
 {
+    if (h->flags & ORC_FLAG_NO_FILTERS)
+        return ORC_EINVAL;
     uint32_t W = (h->K + 31) / 32;
     memset(mask, 0, W * sizeof(uint32_t));
     if (!orc_code_in_range(code, h->k))
@@ -477,6 +487,228 @@ void orc_query_seqs(const orc_index *h, const uint64_t *offsets, const unsigned 
         if (nkmers)
             nkmers[q] = n;
     }
+}
+
+/* ------------------------------------------------- rows of large indexes */
+
+/* Index sizes beyond host memory are checked through rows: row p of
+ * repetition r is the B-bit vector whose bit b is bit p of BFU(r,b).  A row is
+ * computed from its definition (Alg. 1): bit b is set iff some term x of some
+ * set i with phi_r(i) = b has pos_{r,j}(x) = p for some j.  Rows are stored
+ * as BW = ceil(B/64) words, bit b at word b/64, bit b%64.  A row key is
+ * r*m + p. */
+
+static uint64_t orc_row_words(const orc_index *h) { return (h->B + 63) / 64; }
+
+static void orc_atomic_or64(uint64_t *w, uint64_t v)
+{
+    __atomic_fetch_or(w, v, __ATOMIC_RELAXED);
+}
+
+/* Index of key in the ascending array keys[0..n), or n if absent. */
+static uint64_t orc_find_key(const uint64_t *keys, uint64_t n, uint64_t key)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < n && keys[lo] == key ? lo : n;
+}
+
+/* One pass over every window of every sequence (sequence s belongs to set
+ * set_ids[s]).  Keeps (a) with D > 0, every row p with p % D == 0:
+ * sampled[((r*(m/D)) + p/D) * BW ...]; (b) the rows whose keys are listed
+ * in keys[0..n_keys) (ascending, distinct): rows[t*BW ...].  Threads take
+ * whole sequences and OR bits with atomic ORs (OR is order-free).  The
+ * arrays must be zeroed by the caller.  m must be a multiple of D. */
+int orc_scan_rows(const orc_index *h, const uint32_t *set_ids, const uint64_t *offsets,
+                  const unsigned char *chars, uint64_t n_seqs, uint64_t D, uint64_t *sampled,
+                  const uint64_t *keys, uint64_t n_keys, uint64_t *rows, int nthreads, int progress)
+{
+    uint64_t done = 0;   /* sequences finished, for the progress lines */
+    if (D > 0 && h->m % D != 0)
+        return ORC_EINVAL;
+    for (uint64_t s = 0; s < n_seqs; s++)
+        if (set_ids[s] >= h->K)
+            return ORC_ERANGE;
+    const uint64_t BW = orc_row_words(h);
+    /* which positions are asked for: one bit per (r, p), behind a small
+     * cache-resident bitmap of the keys' low bits that turns most misses
+     * away before the large one is touched */
+    const uint64_t small_bits = 1ULL << 26;
+    uint64_t *want = NULL, *want_small = NULL;
+    if (n_keys > 0) {
+        want = calloc(((uint64_t)h->R * h->m + 63) / 64, sizeof(uint64_t));
+        want_small = calloc(small_bits / 64, sizeof(uint64_t));
+        if (!want || !want_small) {
+            free(want);
+            free(want_small);
+            return ORC_ENOMEM;
+        }
+        for (uint64_t t = 0; t < n_keys; t++) {
+            orc_bit_set(want, keys[t]);
+            orc_bit_set(want_small, keys[t] & (small_bits - 1));
+        }
+    }
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t s = 0; s < (int64_t)n_seqs; s++) {
+        uint32_t set = set_ids[s];
+        for (uint64_t p = offsets[s]; p + h->k <= offsets[s + 1]; p++) {
+            uint64_t code;
+            if (!orc_encode_kmer(chars + p, h->k, &code))
+                continue;
+            uint64_t x = orc_canonical(code, h->k);
+            for (uint32_t r = 0; r < h->R; r++) {
+                uint32_t b = h->phi[(size_t)r * h->K + set];
+                uint64_t bit = 1ULL << (b & 63);
+                for (uint32_t j = 0; j < h->eta; j++) {
+                    uint64_t pos = orc_position(x, h->ps[(size_t)r * h->eta + j], h->m);
+                    if (D > 0 && pos % D == 0)
+                        orc_atomic_or64(&sampled[((uint64_t)r * (h->m / D) + pos / D) * BW + b / 64], bit);
+                    uint64_t key = (uint64_t)r * h->m + pos;
+                    if (want && orc_bit_get(want_small, key & (small_bits - 1)) && orc_bit_get(want, key)) {
+                        uint64_t t = orc_find_key(keys, n_keys, key);
+                        orc_atomic_or64(&rows[t * BW + b / 64], bit);
+                    }
+                }
+            }
+        }
+        if (progress) {
+            uint64_t d = __atomic_add_fetch(&done, 1, __ATOMIC_RELAXED);
+            if (d * 20 / n_seqs != (d - 1) * 20 / n_seqs) {
+                fprintf(stderr, "orc_scan_rows: %llu of %llu sequences\n", (unsigned long long)d,
+                        (unsigned long long)n_seqs);
+                fflush(stderr);
+            }
+        }
+    }
+    free(want);
+    free(want_small);
+    return ORC_OK;
+}
+
+/* Keys r*m + pos_{r,j}(x) of every valid window of every read, in window
+ * order (R*eta per window); returns how many there are (at most cap are
+ * written). */
+uint64_t orc_window_keys(const orc_index *h, const uint64_t *offsets, const unsigned char *chars,
+                         uint64_t n_reads, uint64_t *out, uint64_t cap)
+{
+    uint64_t n = 0;
+    for (uint64_t q = 0; q < n_reads; q++)
+        for (uint64_t p = offsets[q]; p + h->k <= offsets[q + 1]; p++) {
+            uint64_t code;
+            if (!orc_encode_kmer(chars + p, h->k, &code))
+                continue;
+            uint64_t x = orc_canonical(code, h->k);
+            for (uint32_t r = 0; r < h->R; r++)
+                for (uint32_t j = 0; j < h->eta; j++) {
+                    if (n < cap)
+                        out[n] = (uint64_t)r * h->m + orc_position(x, h->ps[(size_t)r * h->eta + j], h->m);
+                    n++;
+                }
+        }
+    return n;
+}
+
+/* Alg. 2 for one term with its Bloom-filter bits read from rows (keys and
+ * rows as orc_scan_rows leaves them): cell (r,b) passes iff bit b of every
+ * row r*m + pos_{r,j}(x) is set; A = intersection over r of the union of
+ * SetIDs(M[b,r]) over the passing cells.  mask: ceil(K/32) words.  inG and
+ * A are K-byte work arrays. */
+static int orc_query_kmer_rows(const orc_index *h, uint64_t x, const uint64_t *keys, uint64_t n_keys,
+                               const uint64_t *rows, uint32_t *mask, unsigned char *inG, unsigned char *A)
+{
+    const uint64_t BW = orc_row_words(h);
+    uint32_t W = (h->K + 31) / 32;
+    memset(mask, 0, W * sizeof(uint32_t));
+    for (uint32_t i = 0; i < h->K; i++)
+        A[i] = 1;
+    for (uint32_t r = 0; r < h->R; r++) {
+        /* the eta rows of x in repetition r (each holds bit pos_{r,j}(x) of
+         * every cell) */
+        const uint64_t *row[64];
+        if (h->eta > 64)
+            return ORC_EINVAL;
+        for (uint32_t j = 0; j < h->eta; j++) {
+            uint64_t key = (uint64_t)r * h->m + orc_position(x, h->ps[(size_t)r * h->eta + j], h->m);
+            uint64_t t = orc_find_key(keys, n_keys, key);
+            if (t == n_keys)
+                return ORC_EINVAL;
+            row[j] = rows + t * BW;
+        }
+        memset(inG, 0, h->K);
+        for (uint32_t b = 0; b < h->B; b++) {
+            int pass = 1;
+            for (uint32_t j = 0; j < h->eta && pass; j++)
+                pass = (int)((row[j][b / 64] >> (b & 63)) & 1);
+            if (!pass)
+                continue;
+            for (uint64_t p = h->member_off[(size_t)r * h->B + b]; p < h->member_off[(size_t)r * h->B + b + 1]; p++)
+                inG[h->member_ids[p]] = 1;
+        }
+        for (uint32_t i = 0; i < h->K; i++)
+            A[i] = A[i] & inG[i];
+    }
+    for (uint32_t i = 0; i < h->K; i++)
+        if (A[i])
+            orc_mask_set(mask, i);
+    return ORC_OK;
+}
+
+/* Sec. 3.2.1 for reads, from rows: the conjunction of the answers of all
+ * valid windows, literally as orc_query_seq; empty when a read has none.
+ * Returns ORC_EINVAL if some needed row was not provided. */
+int orc_query_seqs_rows(const orc_index *h, const uint64_t *offsets, const unsigned char *chars,
+                        uint64_t n_reads, const uint64_t *keys, uint64_t n_keys, const uint64_t *rows,
+                        uint32_t *out, uint64_t *nkmers, int nthreads)
+{
+    uint32_t W = (h->K + 31) / 32;
+    int rc = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < (int64_t)n_reads; q++) {
+        uint32_t *mask = out + (size_t)q * W;
+        uint32_t *one = malloc(W * sizeof(uint32_t));
+        unsigned char *inG = malloc(h->K), *A = malloc(h->K);
+        uint64_t n = 0;
+        if (!one || !inG || !A) {
+            __atomic_store_n(&rc, ORC_ENOMEM, __ATOMIC_RELAXED);
+        } else {
+            for (uint32_t w = 0; w < W; w++)
+                mask[w] = 0;
+            for (uint32_t i = 0; i < h->K; i++)
+                orc_mask_set(mask, i);
+            for (uint64_t p = offsets[q]; p + h->k <= offsets[q + 1]; p++) {
+                uint64_t code;
+                if (!orc_encode_kmer(chars + p, h->k, &code))
+                    continue;
+                n++;
+                if (orc_query_kmer_rows(h, orc_canonical(code, h->k), keys, n_keys, rows, one, inG, A) != ORC_OK) {
+                    __atomic_store_n(&rc, ORC_EINVAL, __ATOMIC_RELAXED);
+                    break;
+                }
+                for (uint32_t w = 0; w < W; w++)
+                    mask[w] &= one[w];
+            }
+            if (n == 0)
+                memset(mask, 0, W * sizeof(uint32_t));
+        }
+        if (nkmers)
+            nkmers[q] = n;
+        free(one); free(inG); free(A);
+    }
+    return rc;
 }
 
 /* ------------------------------------------------------------ inspection */

@@ -1,0 +1,167 @@
+"""Parity at the full size of the served and large workloads (10 000 sets,
+B = 200, R = 5, m = 2^29: an 80 GiB index; 100 000 sets, B = 1 000, R = 6,
+m = 2^27: a 96 GiB index), in the launch configuration the library uses for
+them.  The oracle cannot hold these indexes, so it computes rows from the
+inserted sets directly (one pass over every window, Alg. 1):
+  - every row p = 0 mod 64 of every repetition, compared bit for bit with
+    the device index;
+  - every row that a sample of reads and k-mer queries needs, from which it
+    answers them (Sec. 3.2.1, Alg. 2), compared with the device answers
+    (K-bit masks, and for the large workload ID lists);
+and, on many more reads, the device answers contain every read's source set
+(no false negatives).  Each workload takes minutes of host time, so the
+tests run only when RAMBO_SCALE names them (served, large)."""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_02611_amd import rambo as rb
+from paper_1910_02611_amd import serve, synth
+from gpu_util import dev, host_u32
+
+SCALE = [s for s in os.environ.get("RAMBO_SCALE", "").split(",") if s]
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not SCALE, reason="full-size runs take minutes; set RAMBO_SCALE=served or large")]
+D = 64   # every 64th row of every repetition is compared
+OUT = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
+
+WORKLOADS = {
+    # a small stand-in with the served row width, to try the path in seconds
+    "mini": dict(sets=lambda: synth.genome_sets(1099, K=2000, n_ancestors=20, ancestor_len=20000, median_len=5000,
+                                                min_len=500, max_len=20000),
+                 index=dict(K=2000, B=200, R=5, m=1 << 22, eta=2, k=31), seed=2099),
+    "served": dict(sets=synth.config_served, index=synth.INDEX_SERVED, seed=2004),
+    "large": dict(sets=synth.config_large, index=synth.INDEX_LARGE, seed=2005),
+}
+
+
+def log(rec, **kw):
+    rec.update(kw)
+    print(json.dumps(kw), flush=True)
+
+
+def device_sampled_rows(g, r, D, chunk_rows=1 << 22):
+    """Rows p = 0 mod D of repetition r as [m/D, S/32] uint32 (copied in chunks)."""
+    spw = g.row_bits // 32
+    out = []
+    for p0 in range(0, g.m, chunk_rows):
+        n = min(chunk_rows, g.m - p0)
+        w = g.index_words(r * g.words_per_rep + p0 * spw, n * spw).view(n, spw)
+        out.append(host_u32(w[::D].contiguous()))
+        del w
+    return np.concatenate(out)
+
+
+def rows_equal(dev_words, oracle_words, B):
+    """Device rows (S/32 uint32 words) against oracle rows (ceil(B/64) uint64
+    words): the first B bits equal, the rest of the device row zero."""
+    db = np.unpackbits(np.ascontiguousarray(dev_words).view(np.uint8), axis=-1, bitorder="little")
+    ob = np.unpackbits(np.ascontiguousarray(oracle_words).view(np.uint8), axis=-1, bitorder="little")
+    return np.array_equal(db[..., :B], ob[..., :B]) and not db[..., B:].any()
+
+
+@pytest.fixture(scope="module", params=SCALE)
+def workload(request):
+    name = request.param
+    w = WORKLOADS[name]
+    cfg = w["index"]
+    rec = {"workload": name}
+    t = time.time()
+    sets = w["sets"]()
+    log(rec, sets=int(sets.n), bases=int(sets.chars.size), gen_s=round(time.time() - t, 1))
+    g = rb.Rambo(**cfg, seed=w["seed"])
+    t = time.time()
+    d = (dev(sets.set_ids, np.int32), dev(sets.offsets, np.int64), dev(sets.chars, np.uint8))
+    torch.cuda.synchronize()
+    h2d = time.time() - t
+    n_ins = int(np.maximum(sets.lengths().astype(np.int64) - cfg["k"] + 1, 0).sum())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.insert_seqs(*d)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert g.sync_status() == rb.OK
+    log(rec, index_gib=g.index_bytes / 2**30, inserts=n_ins, insert_ms=ms, inserts_per_s=n_ins / ms * 1e3,
+        h2d_s=round(h2d, 1))
+    del d
+    torch.cuda.empty_cache()
+    o = oracle.OracleIndex(**cfg, seed=w["seed"], flags=oracle.FLAG_NO_FILTERS)
+    yield name, cfg, sets, g, o, rec
+    with open(os.path.join(OUT, "scale_%s.json" % name), "w") as f:
+        json.dump(rec, f, indent=1)
+    g.close()
+
+
+def test_scale_rows_and_sampled_answers(workload):
+    name, cfg, sets, g, o, rec = workload
+    if name in ("served", "mini"):
+        reads = synth.served_requests(4104, sets, 40)      # about 1 300 reads of 150-5 000 bp
+        rd = synth.SeqBatch(reads.chars, reads.offsets)
+    else:
+        rd = synth.reads(3105, sets, 600, median_len=150, min_len=150, max_len=150, substr_frac=0.8,
+                         read_sub_rate=0.01)
+    q = synth.kmer_queries(3106, sets, 3000, cfg["k"])
+    keys = np.unique(np.concatenate([o.window_keys(rd.offsets, rd.chars), o.window_keys(q.offsets, q.chars)]))
+    nthreads = min(os.cpu_count() or 1, 16)
+    t = time.time()
+    sampled, rows = o.scan_rows(sets.set_ids, sets.offsets, sets.chars, D=D, keys=keys, nthreads=nthreads,
+                                progress=True)
+    log(rec, oracle_scan_s=round(time.time() - t, 1), oracle_threads=nthreads, sampled_rows=int(sampled.shape[1]),
+        needed_rows=int(keys.size))
+    for r in range(cfg["R"]):
+        assert rows_equal(device_sampled_rows(g, r, D), sampled[r], cfg["B"]), "repetition %d" % r
+    log(rec, sampled_rows_equal=True, rows_compared=int(cfg["R"] * sampled.shape[1]))
+    # reads: masks (and ID lists) against the oracle's answers from rows
+    want, wk = o.query_seqs_rows(rd.offsets, rd.chars, keys, rows, nthreads=nthreads)
+    m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    assert np.array_equal(host_u32(nk), wk.astype(np.uint32))
+    assert np.array_equal(host_u32(m), want)
+    id_off, ids, _ = g.query_seqs_ids(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    id_off = id_off.cpu().numpy()
+    ids = ids.cpu().numpy()
+    for i in range(rd.n):
+        assert ids[id_off[i]:id_off[i + 1]].tolist() == oracle.mask_to_ids(want[i], cfg["K"])
+    # single k-mers
+    qw, _ = o.query_seqs_rows(q.offsets, q.chars, keys, rows, nthreads=nthreads)
+    qm, _ = g.query_seqs(dev(q.offsets, np.int64), dev(q.chars, np.uint8))
+    assert np.array_equal(host_u32(qm), qw)
+    log(rec, reads_equal=int(rd.n), kmer_queries_equal=int(q.n),
+        mean_answer_sets=float(np.mean([len(oracle.mask_to_ids(x, cfg["K"])) for x in want[:200]])))
+
+
+def test_scale_no_false_negatives(workload):
+    name, cfg, sets, g, o, rec = workload
+    rd = synth.reads(3107, sets, 20000, median_len=300, min_len=31, max_len=5000, substr_frac=1.0)
+    src = rd.meta["source_set"]
+    m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    m = host_u32(m)
+    has = (m[np.arange(rd.n), src // 32] >> (src % 32).astype(np.uint32)) & 1
+    assert has[host_u32(nk) > 0].all()
+    log(rec, no_false_negatives_reads=int((host_u32(nk) > 0).sum()))
+
+
+def test_scale_serving(workload):
+    name, cfg, sets, g, o, rec = workload
+    if name not in ("served", "mini"):
+        pytest.skip("serving is measured on the served workload")
+    reqs = serve.split_requests(synth.served_requests(4004, sets, 4000))
+    with rb.Server(g, max_slots=4, use_graphs=True) as srv:
+        serve.saturated(srv, reqs[:200], g.W)
+        res = serve.sweep(srv, reqs, g.W, [0.25, 0.5, 0.8, 1.0])
+        res["server"] = srv.stats()
+    keep = ("load", "offered_qps", "qps", "reads_per_s", "p50_ms", "p99_ms")
+    log(rec, serving_saturated={k: res["saturated"][k] for k in ("qps", "reads_per_s", "p50_ms", "p99_ms")},
+        serving_points=[{k: p[k] for k in keep} for p in res["points"]], serving_slots=res["server"]["slots"])
+    # requests answered in the mix equal the same requests answered alone
+    with rb.Server(g, max_slots=4, use_graphs=True) as srv:
+        ids = [srv.submit(off, ch) for off, ch in reqs[:300]]
+        mixed = [srv.wait(i, len(off) - 1, timeout_us=60_000_000)[0] for i, (off, _) in zip(ids, reqs[:300])]
+    for (off, ch), got in zip(reqs[:300], mixed):
+        alone, _ = g.query_seqs(dev(off, np.int64), dev(ch, np.uint8))
+        assert np.array_equal(host_u32(alone), got)

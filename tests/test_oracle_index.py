@@ -330,3 +330,59 @@ def test_out_of_range_inputs(tiny):
     assert not o.query_kmer(1 << 62).any()
     bad = np.array([cfg["K"]], np.uint32)
     assert o.insert_seqs(bad, np.array([0, 40], np.uint64), np.frombuffer(b"A" * 40, np.uint8)) != 0
+
+
+# ----------------------------------------------- rows of large indexes
+
+def _rows_from_filters(o, D=1):
+    """[R, m/D, B] bits of the full oracle's filters at positions p % D == 0."""
+    out = np.zeros((o.R, o.m // D, o.B), np.uint8)
+    for r in range(o.R):
+        for b in range(o.B):
+            out[r, :, b] = o.bfu_bits(r, b)[::D]
+    return out
+
+
+def _unpack_rows(words, B):
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little").reshape(words.shape[:-1] + (-1,))
+    return bits[..., :B]
+
+
+@pytest.mark.parametrize("cfg", [dict(K=64, B=8, R=3, eta=2, k=31, m=1 << 12),
+                                 dict(K=300, B=130, R=2, eta=3, k=21, m=1 << 10)])
+def test_row_scan_equals_filters(cfg):
+    # the row view computed from Alg. 1's definition in one pass equals the
+    # transposed filters of the full oracle, for sampled rows and listed keys
+    sets = synth.genome_sets(77, K=cfg["K"], n_ancestors=4, ancestor_len=300, sub_rate=0.02)
+    full = oracle.OracleIndex(**cfg, seed=91)
+    full.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 4)
+    lean = oracle.OracleIndex(**cfg, seed=91, flags=oracle.FLAG_NO_FILTERS)
+    assert lean.insert_seqs(sets.set_ids, sets.offsets, sets.chars) != 0   # no filters to insert into
+    want = _rows_from_filters(full)
+    for D in (1, 8):
+        sampled, _ = lean.scan_rows(sets.set_ids, sets.offsets, sets.chars, D=D, nthreads=4)
+        assert np.array_equal(_unpack_rows(sampled, cfg["B"]), want[:, ::D, :])
+    rng = np.random.default_rng(5)
+    keys = np.unique(rng.integers(0, cfg["R"] * cfg["m"], size=300).astype(np.uint64))
+    _, rows = lean.scan_rows(sets.set_ids, sets.offsets, sets.chars, keys=keys, nthreads=4)
+    got = _unpack_rows(rows, cfg["B"])
+    for t, key in enumerate(keys):
+        r, p = divmod(int(key), cfg["m"])
+        assert np.array_equal(got[t], want[r, p])
+
+
+def test_read_answers_from_rows_equal_full_oracle():
+    cfg = synth.INDEX_TINY
+    sets = synth.config_tiny()
+    full = oracle.OracleIndex(**cfg, seed=2001)
+    full.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    lean = oracle.OracleIndex(**cfg, seed=2001, flags=oracle.FLAG_NO_FILTERS)
+    rd = synth.reads(3021, sets, 150, median_len=150, min_len=20, max_len=400, substr_frac=0.8, read_sub_rate=0.01)
+    keys = np.unique(lean.window_keys(rd.offsets, rd.chars))
+    _, rows = lean.scan_rows(sets.set_ids, sets.offsets, sets.chars, keys=keys, nthreads=8)
+    got, gk = lean.query_seqs_rows(rd.offsets, rd.chars, keys, rows, nthreads=8)
+    want, wk = full.query_seqs(rd.offsets, rd.chars, nthreads=8)
+    assert np.array_equal(gk, wk)
+    assert np.array_equal(got, want)
+    with pytest.raises(ValueError):   # a row it was not given
+        lean.query_seqs_rows(rd.offsets, rd.chars, keys[1:], rows[1:])
