@@ -215,13 +215,22 @@ __device__ __forceinline__ void load_row(const Params &P, uint32_t r, uint64_t r
     }
 }
 
-// AND of v over the 64 lanes of the wave (every lane gets the result).
+// AND of v over the 64 lanes of the wave (every lane gets the result); call
+// with the whole wave active.  DPP moves inside rows of 16 lanes (no LDS
+// crossbar): the two quad swaps, then the 8- and 16-lane mirrors leave every
+// lane with the AND of its row; one lane of each of the four rows finishes.
 __device__ __forceinline__ uint32_t wave_and(uint32_t v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v &= __shfl_xor(v, off, kWave);
-    return v;
+    constexpr int kQuadSwap1 = 0xB1;     // quad_perm [1,0,3,2]
+    constexpr int kQuadSwap2 = 0x4E;     // quad_perm [2,3,0,1]
+    constexpr int kHalfMirror = 0x141;   // row_half_mirror
+    constexpr int kMirror = 0x140;       // row_mirror
+    v &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, kQuadSwap1, 0xF, 0xF, false);
+    v &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, kQuadSwap2, 0xF, 0xF, false);
+    v &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, kHalfMirror, 0xF, 0xF, false);
+    v &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, kMirror, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) & (uint32_t)__builtin_amdgcn_readlane((int)v, 16) &
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) & (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
 }  // namespace rambo_dev

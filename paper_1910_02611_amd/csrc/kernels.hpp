@@ -649,20 +649,49 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
         nk += (uint32_t)__popcll(__ballot(valid));
         const uint64_t hx = mix64(x);
         if (!dead) {
+            if constexpr (R_T > 0) {
+                // Repetition 0 first: once its running AND has no cell left the
+                // read's answer is empty (the intersection of Alg. 2), so the
+                // rows of the other repetitions are read only while it has one.
+#pragma unroll 1
+                for (int sl = 0; sl < NSL; ++sl) {
+                    uint32_t g0[1][L];
+                    Probe<SW, L, 1, ETA_T>::run(P, hx, sl * L, valid, g0);
+#pragma unroll
+                    for (int w = 0; w < L; ++w) {
+                        const uint32_t a = wave_and(valid ? g0[0][w] : ~0u);
+                        if (lane == 0)
+                            G[sl * L + w] &= a;
+                    }
+                }
+                wave_sync_lds();
+                uint32_t left = 0;
+                for (int w = 0; w < SW; ++w)
+                    left |= G[w];
+                if (left == 0) {
+                    dead = true;
+                    A = Bg;
+                    continue;
+                }
+                if constexpr (R_T > 1) {
+#pragma unroll 1
+                    for (int sl = 0; sl < NSL; ++sl) {
+                        uint32_t g[R_T - 1][L];
+                        Probe<SW, L, R_T - 1, ETA_T>::run(P, hx, sl * L, valid, g, 1);
+#pragma unroll
+                        for (int r = 1; r < R_T; ++r)
+#pragma unroll
+                            for (int w = 0; w < L; ++w) {
+                                const uint32_t a = wave_and(valid ? g[r - 1][w] : ~0u);
+                                if (lane == 0)
+                                    G[r * SW + sl * L + w] &= a;
+                            }
+                    }
+                }
+            } else {
 #pragma unroll 1
             for (int sl = 0; sl < NSL; ++sl) {
-                if constexpr (R_T > 0) {
-                    uint32_t g[R_T][L];
-                    Probe<SW, L, R_T, ETA_T>::run(P, hx, sl * L, valid, g);
-#pragma unroll
-                    for (int r = 0; r < R_T; ++r)
-#pragma unroll
-                        for (int w = 0; w < L; ++w) {
-                            const uint32_t a = wave_and(valid ? g[r][w] : ~0u);
-                            if (lane == 0)
-                                G[r * SW + sl * L + w] &= a;
-                        }
-                } else {
+                {
                     for (uint32_t r = 0; r < R; ++r) {
                         uint32_t acc[L];
                         probe_rep<SW, L>(P, hx, r, sl * L, valid, acc);
@@ -674,6 +703,7 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
                         }
                     }
                 }
+            }
             }
             wave_sync_lds();
             dead = any_rep_empty(G, R, SW);

@@ -165,3 +165,39 @@ def test_scale_serving(workload):
     for (off, ch), got in zip(reqs[:300], mixed):
         alone, _ = g.query_seqs(dev(off, np.int64), dev(ch, np.uint8))
         assert np.array_equal(host_u32(alone), got)
+
+
+def test_scale_batched_ids(workload):
+    """The large workload's query batch: 1e6 reads of 150 bp (80% set
+    substrings with 1% further substitutions, 20% random), answered as ID
+    lists in one call; throughput and the answer-size histogram."""
+    name, cfg, sets, g, o, rec = workload
+    if name not in ("large", "mini"):
+        pytest.skip("the ID-list batch is the large workload's")
+    n = 1_000_000 if name == "large" else 20_000
+    rd = synth.reads(3205, sets, n, median_len=150, min_len=150, max_len=150, substr_frac=0.8, read_sub_rate=0.01)
+    off, ch = dev(rd.offsets, np.int64), dev(rd.chars, np.uint8)
+    ids_buf = torch.empty(8 << 20, dtype=torch.int32, device="cuda")
+    g.query_seqs_ids(off, ch, ids=ids_buf)            # warm-up (and state growth)
+    g.set_timing(True)
+    g.stage_times()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    id_off, ids, nk = g.query_seqs_ids(off, ch, ids=ids_buf)
+    e1.record()
+    torch.cuda.synchronize()
+    stages = g.stage_times()
+    g.set_timing(False)
+    ms = e0.elapsed_time(e1)
+    sizes = np.diff(id_off.cpu().numpy())
+    hist = np.bincount(np.minimum(sizes, 10), minlength=11)
+    # the answers agree with the mask form
+    m, _ = g.query_seqs(off, ch)
+    m = host_u32(m)
+    ids = ids.cpu().numpy()
+    io = id_off.cpu().numpy()
+    for i in np.random.default_rng(1).choice(rd.n, size=min(rd.n, 2000), replace=False):
+        assert ids[io[i]:io[i + 1]].tolist() == oracle.mask_to_ids(m[i], cfg["K"])
+    log(rec, ids_reads=int(rd.n), ids_ms=ms, ids_reads_per_s=rd.n / ms * 1e3,
+        ids_kmers_per_s=float(nk.to(torch.int64).sum()) / ms * 1e3, ids_stage_ms=stages,
+        ids_total=int(sizes.sum()), answer_size_hist_0_to_10plus=hist.tolist())
