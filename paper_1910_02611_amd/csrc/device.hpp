@@ -29,6 +29,8 @@ struct Params {
     uint32_t *index;            // R blocks of words_per_rep words
     const uint16_t *phi;        // phi_r(i) at [r*K + i]
     const uint32_t *cellmask;   // SetIDs(M[b,r]) as K-bit masks at [(r*B + b)*W + w]
+    const uint32_t *member_off; // SetIDs(M[b,r]) as ascending lists: members[member_off[r*(B+1) + b] ..
+    const uint32_t *members;    //   member_off[r*(B+1) + b + 1]) of repetition r's block (K entries)
     int *err;                   // sticky error bits
     uint64_t m;                 // Bloom-filter positions per repetition
     uint64_t words_per_rep;

@@ -4,10 +4,12 @@
 // The ID form compacts the K-bit answer of Sec. 3.2.1 (Alg. 2's A).  It
 // starts from the per-read group masks that the work-queue launch leaves in
 // its state (run without the mask expansion), then
-//   k_ids_count : wave per read, |A| = sum of popcounts of the expanded words;
+//   k_ids_count : wave per read, |A|: either the candidate members of one
+//                 repetition's positive cells tested against the others, or
+//                 the popcounts of the expanded K-bit words;
 //   k_scan64_*  : exclusive scan of the counts into id_offsets (n+1 entries);
-//   k_ids_write : wave per read, expands again and writes the set bits of
-//                 each word, in word order, at its wave-prefix position.
+//   k_ids_write : wave per read, the same enumeration again, writing the IDs
+//                 in ascending order at their wave-prefix positions.
 // A read whose list would end beyond the caller's capacity is not written and
 // the sticky overflow bit is raised; id_offsets is always complete.
 //
@@ -53,6 +55,81 @@ __device__ __forceinline__ bool load_read_masks(const Params &P, const ReadQueue
     return Q.nk[q] == 0 || any_rep_empty(G, P.R, SW);
 }
 
+// How a read's answer is enumerated.  By the partition identity, A is the
+// set of members i of the positive cells of any one repetition r* with
+// phi_r(i) positive in every other repetition.  When r*'s candidates times
+// the other repetitions cost less than expanding all W words over every
+// positive cell, the candidates are tested one by one (a few hundred for a
+// large K); otherwise the K-bit words are expanded.
+struct Enum {
+    bool by_members;
+    uint32_t rstar;      // repetition whose members are enumerated
+    uint32_t cells;      // positive cells of rstar
+};
+
+__device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, uint32_t SW)
+{
+    Enum e{false, 0, 0};
+    uint32_t best = 0xFFFFFFFFu, all_cells = 0;
+    for (uint32_t r = 0; r < P.R; ++r) {
+        const uint32_t *off = P.member_off + (uint64_t)r * (P.B + 1);
+        uint32_t cand = 0, cells = 0;
+        for (uint32_t sw = 0; sw < SW; ++sw) {
+            uint32_t bits = G[r * SW + sw];
+            cells += __builtin_popcount(bits);
+            while (bits) {
+                const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1;
+                cand += off[b + 1] - off[b];
+            }
+        }
+        all_cells += cells;
+        if (cand < best) {
+            best = cand;
+            e.rstar = r;
+            e.cells = cells;
+        }
+    }
+    e.by_members = (uint64_t)best * (P.R - 1) <= (uint64_t)P.W * all_cells;
+    return e;
+}
+
+// Whether set i is in every repetition's positive cells other than rstar.
+__device__ __forceinline__ bool member_passes(const Params &P, const uint32_t *G, uint32_t SW, uint32_t rstar,
+                                              uint32_t i)
+{
+    for (uint32_t r = 0; r < P.R; ++r) {
+        if (r == rstar)
+            continue;
+        const uint32_t b = P.phi[(uint64_t)r * P.K + i];
+        if (!((G[r * SW + (b >> 5)] >> (b & 31)) & 1u))
+            return false;
+    }
+    return true;
+}
+
+// Calls f(i, pass) for the candidates of rstar, 64 at a time on the wave's
+// lanes (lanes past the end get pass = false), cell by cell in ascending b.
+template <class F>
+__device__ __forceinline__ void for_candidates(const Params &P, const uint32_t *G, uint32_t SW, uint32_t rstar,
+                                               uint32_t lane, F &&f)
+{
+    const uint32_t *off = P.member_off + (uint64_t)rstar * (P.B + 1);
+    const uint32_t *mem = P.members + (uint64_t)rstar * P.K;
+    for (uint32_t sw = 0; sw < SW; ++sw) {
+        uint32_t bits = G[rstar * SW + sw];
+        while (bits) {
+            const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1;
+            for (uint32_t k0 = off[b]; k0 < off[b + 1]; k0 += kWave) {
+                const uint32_t k = k0 + lane;
+                const uint32_t i = k < off[b + 1] ? mem[k] : 0u;
+                f(i, k < off[b + 1] && member_passes(P, G, SW, rstar, i));
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
                                                       uint64_t *counts)
 {
@@ -63,9 +140,14 @@ __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uin
     for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; q < n_reads; q += stride) {
         const bool empty = load_read_masks(P, Q, q, SW, G, lane);
         uint32_t c = 0;
-        if (!empty)
-            for (uint32_t w = lane; w < P.W; w += kWave)
-                c += __builtin_popcount(expand_word(P, G, SW, w));
+        if (!empty) {
+            const Enum e = plan_enum(P, G, SW);
+            if (e.by_members)
+                for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t, bool pass) { c += pass ? 1u : 0u; });
+            else
+                for (uint32_t w = lane; w < P.W; w += kWave)
+                    c += __builtin_popcount(expand_word(P, G, SW, w));
+        }
         c = wave_sum_u32(c);
         if (lane == 0)
             counts[q] = c;
@@ -142,32 +224,88 @@ __global__ __launch_bounds__(256) void k_scan64_add(uint64_t *y, uint64_t n, con
         y[i] += part[i / kScanTile];
 }
 
+// Largest list a wave sorts in LDS when the candidates come from several
+// cells (their lists interleave); longer lists take the word expansion.
+constexpr uint32_t kSortCap = 1024;
+
+__device__ __forceinline__ void wave_bitonic_sort(uint32_t *a, uint32_t n_pad, uint32_t lane)
+{
+    for (uint32_t k = 2; k <= n_pad; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = lane; i < n_pad; i += kWave) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            wave_sync_lds();
+        }
+}
+
 __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
                                                       const uint64_t *id_offsets, uint32_t *ids, uint64_t cap)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
-    uint32_t *G = lds + (threadIdx.x / kWave) * (P.R * SW);
+    const uint32_t wv = threadIdx.x / kWave;
+    uint32_t *G = lds + wv * (P.R * SW);
+    uint32_t *buf = lds + kWavesPerBlock * (P.R * SW) + wv * kSortCap;
     const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
-    for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; q < n_reads; q += stride) {
+    for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv; q < n_reads; q += stride) {
         const uint64_t o0 = id_offsets[q], o1 = id_offsets[q + 1];
         if (o0 == o1 || o1 > cap)
             continue;
         load_read_masks(P, Q, q, SW, G, lane);
-        uint64_t base = o0;
-        for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
-            const uint32_t w = w0 + lane;
-            uint32_t word = w < P.W ? expand_word(P, G, SW, w) : 0u;
-            const uint32_t c = __builtin_popcount(word);
-            uint64_t pos = base + wave_excl_scan_u32(c, lane);
-            while (word) {
-                const uint32_t b = (uint32_t)__builtin_ctz(word);
-                word &= word - 1;
-                if (pos < o1)
-                    ids[pos] = w * 32 + b;
-                ++pos;
+        const Enum e = plan_enum(P, G, SW);
+        const uint32_t n = (uint32_t)(o1 - o0);
+        if (e.by_members && e.cells == 1) {
+            // one member list, ascending: passing members in list order
+            uint64_t base = o0;
+            for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
+                const uint64_t bal = __ballot(pass);
+                if (pass)
+                    ids[base + __popcll(bal & ((1ull << lane) - 1))] = i;
+                base += __popcll(bal);
+            });
+        } else if (e.by_members && n <= kSortCap) {
+            // several lists: gather in LDS, sort, write
+            uint32_t fill = 0;
+            for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
+                const uint64_t bal = __ballot(pass);
+                if (pass)
+                    buf[fill + __popcll(bal & ((1ull << lane) - 1))] = i;
+                fill += __popcll(bal);
+            });
+            uint32_t n_pad = 1;
+            while (n_pad < n)
+                n_pad <<= 1;
+            for (uint32_t t = n + lane; t < n_pad; t += kWave)
+                buf[t] = 0xFFFFFFFFu;
+            wave_sync_lds();
+            wave_bitonic_sort(buf, n_pad, lane);
+            for (uint32_t t = lane; t < n; t += kWave)
+                ids[o0 + t] = buf[t];
+        } else {
+            uint64_t base = o0;
+            for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
+                const uint32_t w = w0 + lane;
+                uint32_t word = w < P.W ? expand_word(P, G, SW, w) : 0u;
+                const uint32_t c = __builtin_popcount(word);
+                uint64_t pos = base + wave_excl_scan_u32(c, lane);
+                while (word) {
+                    const uint32_t b = (uint32_t)__builtin_ctz(word);
+                    word &= word - 1;
+                    if (pos < o1)
+                        ids[pos] = w * 32 + b;
+                    ++pos;
+                }
+                base += wave_sum_u32(c);
             }
-            base += wave_sum_u32(c);
         }
         wave_sync_lds();
     }

@@ -29,6 +29,8 @@ struct rambo {
     uint32_t *index = nullptr;
     uint16_t *phi = nullptr;
     uint32_t *cellmask = nullptr;
+    uint32_t *member_off = nullptr;   // R x (B+1)
+    uint32_t *members = nullptr;      // R x K
     int *err = nullptr;
     bool index_zero = true;          // nothing inserted since create or clear
     std::string last_error;
@@ -560,6 +562,40 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
     return RAMBO_OK;
 }
 
+// SetIDs(M[b,r]) as ascending member lists (a counting sort of phi_r per
+// repetition, on the host, once): the ID-list kernels enumerate candidate
+// sets from them.
+int build_member_lists(rambo *h)
+{
+    const uint32_t K = h->cfg.K, B = h->cfg.B, R = h->cfg.R;
+    std::vector<uint16_t> phi((size_t)R * K);
+    std::vector<uint32_t> off((size_t)R * (B + 1)), mem((size_t)R * K);
+    int rc = hip_check(h, hipMemcpy(phi.data(), h->phi, phi.size() * 2, hipMemcpyDeviceToHost), "member lists");
+    if (rc)
+        return rc;
+    for (uint32_t r = 0; r < R; ++r) {
+        uint32_t *o = off.data() + (size_t)r * (B + 1);
+        const uint16_t *f = phi.data() + (size_t)r * K;
+        for (uint32_t i = 0; i < K; ++i)
+            ++o[f[i] + 1];
+        for (uint32_t b = 0; b < B; ++b)
+            o[b + 1] += o[b];
+        std::vector<uint32_t> cur(o, o + B);
+        for (uint32_t i = 0; i < K; ++i)   // ascending i: each list comes out sorted
+            mem[(size_t)r * K + cur[f[i]]++] = i;
+    }
+    if (hipMalloc(&h->member_off, off.size() * 4) != hipSuccess || hipMalloc(&h->members, mem.size() * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, RAMBO_ENOMEM, "member lists: device allocation failed");
+    }
+    if ((rc = hip_check(h, hipMemcpy(h->member_off, off.data(), off.size() * 4, hipMemcpyHostToDevice), "member lists")) ||
+        (rc = hip_check(h, hipMemcpy(h->members, mem.data(), mem.size() * 4, hipMemcpyHostToDevice), "member lists")))
+        return rc;
+    h->P.member_off = h->member_off;
+    h->P.members = h->members;
+    return RAMBO_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -652,7 +688,8 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
     const uint64_t ncm = (uint64_t)c.R * h->W;
     hipLaunchKernelGGL(k_build_cellmask, dim3((uint32_t)div_up(ncm, kBlock)), dim3(kBlock), 0, 0, h->phi, c.K, c.B,
                        c.R, h->W, h->cellmask);
-    if ((rc = launch_check(h, "build tables")) || (rc = hip_check(h, hipDeviceSynchronize(), "build tables"))) {
+    if ((rc = launch_check(h, "build tables")) || (rc = hip_check(h, hipDeviceSynchronize(), "build tables")) ||
+        (rc = build_member_lists(h))) {
         g_create_error = h->last_error;
         rambo_destroy(h);
         return rc;
@@ -672,6 +709,10 @@ extern "C" void rambo_destroy(rambo_t *h)
         (void)hipFree(h->phi);
     if (h->cellmask)
         (void)hipFree(h->cellmask);
+    if (h->member_off)
+        (void)hipFree(h->member_off);
+    if (h->members)
+        (void)hipFree(h->members);
     if (h->err)
         (void)hipFree(h->err);
     if (h->bin_mem)
@@ -853,7 +894,7 @@ extern "C" int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_
     }
     {
         StageScope sc(h, "k_ids_write", stream);
-        hipLaunchKernelGGL(k_ids_write, grid, dim3(kBlock), lds, stream, h->P, h->rq, n_reads, h->SW, id_offsets, ids,
+        hipLaunchKernelGGL(k_ids_write, grid, dim3(kBlock), lds + (size_t)kWavesPerBlock * kSortCap * 4, stream, h->P, h->rq, n_reads, h->SW, id_offsets, ids,
                            cap);
     }
     return launch_check(h, "rambo_query_seqs_ids");
