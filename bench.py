@@ -208,6 +208,20 @@ def batched_reads(n_reads: int, plain_prefix: int = 2000):
     nk = torch.empty(rd.n, dtype=torch.int32, device="cuda")
     t_q = autotune.time_query_seqs(g, off, ch, out, nk, reps=5)
     windows = int(nk.to(torch.int64).sum())
+    # the same batch as one captured graph, replayed with eager calls in
+    # between; every replay must give the eager answers
+    out_g = torch.empty_like(out)
+    nk_g = torch.empty_like(nk)
+    graph = autotune.capture_query_seqs(g, off, ch, out_g, nk_g)
+    same_g = True
+    for _ in range(3):
+        out_g.zero_()
+        graph.replay()
+        g.query_seqs(off, ch, out=out, nkmers=nk)
+        torch.cuda.synchronize()
+        same_g = same_g and bool(torch.equal(out_g, out)) and bool(torch.equal(nk_g, nk))
+    t_g = autotune.time_graph(graph, reps=5)
+    del graph
     g.set_query_policy(QUERY_WAVE_PER_READ)
     out_w = torch.empty_like(out)
     t_w = autotune.time_query_seqs(g, off, ch, out_w, nk, reps=5)
@@ -223,14 +237,16 @@ def batched_reads(n_reads: int, plain_prefix: int = 2000):
     t_p = time.perf_counter() - t0
     same_p = bool(torch.equal(out_p, out[:pre]))
     g.close()
-    log("batched reads: queue %.3f ms (%.3g reads/s, %.3g k-mers/s), wave-per-read %.3f ms, plain %.3g reads/s"
-        % (t_q * 1e3, rd.n / t_q, windows / t_q, t_w * 1e3, pre / t_p))
+    log("batched reads: tuned %.3f ms (%.3g reads/s, %.3g k-mers/s), graph replay %.3f ms (identical %s), "
+        "wave-per-read %.3f ms, plain %.3g reads/s"
+        % (t_q * 1e3, rd.n / t_q, windows / t_q, t_g * 1e3, same_g, t_w * 1e3, pre / t_p))
     return {
         "workload": "batched reads: tiny index (K=64, B=8, R=3, m=2^18, eta=2); %d reads, lognormal "
                     "100-10000 bp (median 1000), 70%% set substrings" % rd.n,
         "reads_per_s": rd.n / t_q, "k_mer_queries_per_s": windows / t_q, "ms": t_q * 1e3, "kmers": windows,
         "tile": {k: tune[k] for k in ("mode", "chunk", "waves_per_cu")},
         "wave_per_read": {"reads_per_s": rd.n / t_w, "ms": t_w * 1e3, "identical": same_w},
+        "graph_replay": {"reads_per_s": rd.n / t_g, "ms": t_g * 1e3, "identical": same_g},
         "plain_path": {"reads_per_s": pre / t_p, "prefix": pre, "identical": same_p},
     }
 

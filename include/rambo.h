@@ -181,15 +181,18 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
 #define RAMBO_INSERT_PARTITIONED 2
 int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
 
-/* How rambo_query_seqs schedules a batch of reads (the answers are the same
- * either way): WAVE_PER_READ runs one wavefront per read; QUEUE (and AUTO)
- * splits the reads into work items of chunk_bytes bytes that a persistent
+/* How rambo_query_seqs and rambo_query_seqs_ids schedule a batch of reads
+ * (the answers are the same either way): WAVE_PER_READ runs one wavefront
+ * per read; QUEUE splits the reads into work items of chunk_bytes bytes that
+ * a persistent
  * grid of waves_per_cu wavefronts per compute unit takes from a work counter;
  * the chunks of one read AND their group masks into per-read state and the
  * last one expands the answer, so long and short reads share the GPU evenly
  * and a read stops probing once one chunk found a repetition empty.
- * chunk_bytes 0 = 512, waves_per_cu 0 = 16.  The queue keeps per-read state
- * in device memory owned by the handle, grown on demand. */
+ * chunk_bytes 0 = 512, waves_per_cu 0 = 16.  AUTO takes one wavefront per
+ * read when the reads average at most 2 048 bytes, else the queue.  Both
+ * keep per-read state (ID-list form, queue) in device memory owned by the
+ * handle, grown on demand. */
 #define RAMBO_QUERY_AUTO 0
 #define RAMBO_QUERY_WAVE_PER_READ 1
 #define RAMBO_QUERY_QUEUE 2

@@ -63,6 +63,35 @@ def time_query_seqs(g: rb.Rambo, offsets, chars, out, nk, reps: int = 3) -> floa
     return best
 
 
+def capture_query_seqs(g: rb.Rambo, offsets, chars, out, nk):
+    """A hipGraph (torch.cuda.CUDAGraph) of one batched rambo_query_seqs call
+    with the current query policy: the launches of the batch recorded once
+    and replayed as one unit.  The call is made once first, so that the
+    library's per-read state is already large enough (nothing is allocated
+    while recording)."""
+    g.query_seqs(offsets, chars, out=out, nkmers=nk)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.query_seqs(offsets, chars, out=out, nkmers=nk)
+    torch.cuda.synchronize()
+    return graph
+
+
+def time_graph(graph, reps: int = 3) -> float:
+    """Best of reps, in seconds, of one replay."""
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        graph.replay()
+        e.record(stream)
+        e.synchronize()
+        best = min(best, s.elapsed_time(e) / 1e3)
+    return best
+
+
 def tune_query_seqs(g: rb.Rambo, offsets, chars, tag: str = "reads", use_cache: bool = True):
     """Pick and apply the fastest queue shape for this batch kind.  Returns a
     dict with the choice, its time and the sweep."""

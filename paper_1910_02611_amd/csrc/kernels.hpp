@@ -617,6 +617,112 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One 64-window step of a read over rows wider than 4 words (compile-time R
+// and eta).  GL = SW/4 lanes share a window, each loading one 16-byte slice
+// of every row, so a load instruction reads whole rows of 64/GL windows and
+// each row's bytes are used at once; GL such rounds cover the step's
+// windows.  The windows' mixes and validity move to the sharing lanes by
+// shuffles.  Repetition 0 goes first (a read with no cell left there is
+// finished); then the other repetitions, all rows of a round in flight.
+// The per-slice ANDs are reduced over the lanes of the same slice and
+// folded into G (R x SW words of LDS); dead is set when some repetition is
+// empty.
+template <int SW, int R_T, int ETA_T>
+__device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bool valid, uint32_t *G, bool &dead,
+                                                uint32_t lane)
+{
+    constexpr int GL = SW / 4, WPI = kWave / GL;
+    static_assert(GL >= 2 && GL * 4 == SW, "wide rows");
+    const uint32_t part = lane % GL, sub = lane / GL;
+    const uint32_t hx_lo = (uint32_t)hx, hx_hi = (uint32_t)(hx >> 32), ok_in = valid ? 1u : 0u;
+    auto window = [&](int it, uint64_t &h, bool &ok) {
+        const int src = it * WPI + (int)sub;
+        h = ((uint64_t)(uint32_t)__shfl((int)hx_hi, src, kWave) << 32) | (uint32_t)__shfl((int)hx_lo, src, kWave);
+        ok = __shfl((int)ok_in, src, kWave) != 0;
+    };
+    auto slice = [&](uint32_t r, uint64_t h, int j) {
+        const uint64_t row = bf_position(h, P.seeds[r * ETA_T + j], P);
+        return *reinterpret_cast<const u32x4 *>(P.index + (uint64_t)r * P.words_per_rep + row * SW + part * 4);
+    };
+    auto reduce = [&](u32x4 v) {
+        for (int off = GL; off < kWave; off <<= 1) {
+            v.x &= (uint32_t)__shfl_xor((int)v.x, off, kWave);
+            v.y &= (uint32_t)__shfl_xor((int)v.y, off, kWave);
+            v.z &= (uint32_t)__shfl_xor((int)v.z, off, kWave);
+            v.w &= (uint32_t)__shfl_xor((int)v.w, off, kWave);
+        }
+        return v;
+    };
+    const u32x4 ones = {~0u, ~0u, ~0u, ~0u};
+    u32x4 acc0 = ones;
+#pragma unroll 4
+    for (int it = 0; it < GL; ++it) {
+        uint64_t h;
+        bool ok;
+        window(it, h, ok);
+        u32x4 a = ones;
+        if (ok) {
+#pragma unroll
+            for (int j = 0; j < ETA_T; ++j)
+                a &= slice(0, h, j);
+        }
+        acc0 &= a;
+    }
+    acc0 = reduce(acc0);
+    if (sub == 0) {
+        G[part * 4 + 0] &= acc0.x;
+        G[part * 4 + 1] &= acc0.y;
+        G[part * 4 + 2] &= acc0.z;
+        G[part * 4 + 3] &= acc0.w;
+    }
+    wave_sync_lds();
+    uint32_t left = 0;
+    for (int w = 0; w < SW; ++w)
+        left |= G[w];
+    if (left == 0) {
+        dead = true;
+        return;
+    }
+    if constexpr (R_T > 1) {
+        u32x4 acc[R_T - 1];
+#pragma unroll
+        for (int r = 0; r < R_T - 1; ++r)
+            acc[r] = ones;
+#pragma unroll 2
+        for (int it = 0; it < GL; ++it) {
+            uint64_t h;
+            bool ok;
+            window(it, h, ok);
+            if (ok) {
+                u32x4 rows[R_T - 1][ETA_T];
+#pragma unroll
+                for (int r = 1; r < R_T; ++r)
+#pragma unroll
+                    for (int j = 0; j < ETA_T; ++j)
+                        rows[r - 1][j] = slice(r, h, j);
+#pragma unroll
+                for (int r = 1; r < R_T; ++r)
+#pragma unroll
+                    for (int j = 0; j < ETA_T; ++j)
+                        acc[r - 1] &= rows[r - 1][j];
+            }
+        }
+#pragma unroll
+        for (int r = 1; r < R_T; ++r) {
+            const u32x4 v = reduce(acc[r - 1]);
+            if (sub == 0) {
+                uint32_t *g = G + r * SW + part * 4;
+                g[0] &= v.x;
+                g[1] &= v.y;
+                g[2] &= v.z;
+                g[3] &= v.w;
+            }
+        }
+    }
+    wave_sync_lds();
+    dead = any_rep_empty(G, R_T, SW);
+}
+
 // Sec. 3.2.1 for the windows of one read (bytes end at pe) that start in
 // [p_start, p_stop): each step takes 64 windows (one per lane), gathers their
 // rows, ANDs the group masks over the lanes and into the running masks G
@@ -648,6 +754,12 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
         const bool valid = (p + lane < p_stop) && window_code(A, Bg, lane, P.k, kmask, x);
         nk += (uint32_t)__popcll(__ballot(valid));
         const uint64_t hx = mix64(x);
+        if constexpr (R_T > 0 && SW >= 8) {
+            if (!dead)
+                probe_step_wide<SW, R_T, ETA_T>(P, hx, valid, G, dead, lane);
+            A = Bg;
+            continue;
+        }
         if (!dead) {
             if constexpr (R_T > 0) {
                 // Repetition 0 first: once its running AND has no cell left the
@@ -714,11 +826,12 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
 
 // Sec. 3.2.1: one wave per read.  The read is expanded once: by the partition
 // identity, AND over k-mers of the expanded answers equals the expansion of
-// the AND of the group masks.
+// the AND of the group masks.  Without a mask output the group masks and
+// the window count are stored in the per-read state instead (ID-list form).
 template <int SW, int R_T, int ETA_T>
 __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t *offsets, uint64_t n_reads,
                                                        const uint8_t *chars, uint64_t n_chars, uint32_t *out,
-                                                       uint32_t *out_nk)
+                                                       uint32_t *out_nk, uint32_t *state_G, uint32_t *state_nk)
 {
     constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
     __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
@@ -743,6 +856,15 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
     read_windows_and<SW, R_T, ETA_T>(P, chars, pe, p0, pe, G, nk, dead);
     if (out_nk && lane == 0)
         out_nk[q] = nk;
+    if (!out) {
+        // ID-list form: the final group masks and count go to the per-read
+        // state that the ID kernels read
+        for (uint32_t i = lane; i < R * SW; i += kWave)
+            state_G[q * R * SW + i] = G[i];
+        if (lane == 0)
+            state_nk[q] = nk;
+        return;
+    }
     uint32_t *o = out + q * P.W;
     const bool empty = dead || nk == 0;
     for (uint32_t w = lane; w < P.W; w += kWave)

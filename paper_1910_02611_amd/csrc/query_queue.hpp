@@ -10,8 +10,8 @@
 //  k_rq_persist : a fixed grid of waves pops items from the counter; each
 //                 runs its chunk's windows (probe, AND, early exit), ANDs the
 //                 result into the read's state with atomics and raises the
-//                 read's flag once some repetition is empty, so later chunks
-//                 of that read only count windows.  The wave that finishes a
+//                 read's flag when some repetition is empty in the chunk, so
+//                 later chunks of that read only count windows.  The wave that finishes a
 //                 read's last chunk expands it and writes the answer (unless
 //                 no mask output is given: then the final group masks stay in
 //                 the state for the ID-list kernels).
@@ -150,13 +150,15 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
         if (lane == 0 && nk)
             atomicAdd(Q.nk + q, nk);
         if (!was_dead) {
-            // AND this chunk's masks into the read's; keep the merged value
+            // AND this chunk's masks into the read's (a word of all ones
+            // changes nothing); a repetition empty in the chunk empties the
+            // read
             for (uint32_t i = lane; i < rsw; i += kWave) {
                 const uint32_t mine = G[i];
-                G[i] = atomicAnd(Q.G + q * rsw + i, mine) & mine;
+                if (mine != ~0u)
+                    atomicAnd(Q.G + q * rsw + i, mine);
             }
-            wave_sync_lds();
-            if (any_rep_empty(G, R, SW) && lane == 0)
+            if (dead && lane == 0)
                 atomicOr(Q.dead + q, 1u);
         }
         uint32_t left = 0;

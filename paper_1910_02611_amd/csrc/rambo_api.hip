@@ -149,7 +149,7 @@ void launch_query_seqs_t(const rambo *h, const uint64_t *offsets, uint64_t n_rea
 {
     StageScope sc(h, "k_query_seqs", st);
     hipLaunchKernelGGL((k_query_seqs<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_reads, kWavesPerBlock)),
-                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk);
+                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk, h->rq.G, h->rq.nk);
 }
 
 // Row widths of the workloads get kernels with compile-time R and eta (all
@@ -380,6 +380,18 @@ int ensure_read_queue(rambo *h, uint64_t n_reads)
     h->scan_part = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(h->rq_mem) + qb);
     h->rq_cap = cap;
     return RAMBO_OK;
+}
+
+// One wave per read, or the work queue: as set by rambo_set_query_policy;
+// automatically, one wave per read unless reads are long on average (then
+// splitting them into chunks balances the load).
+constexpr uint64_t kWaveReadMaxMeanBytes = 2048;
+
+bool wave_per_read(const rambo *h, uint64_t n_reads, uint64_t n_chars)
+{
+    if (h->query_mode != RAMBO_QUERY_AUTO)
+        return h->query_mode == RAMBO_QUERY_WAVE_PER_READ;
+    return n_chars <= kWaveReadMaxMeanBytes * n_reads;
 }
 
 // The three launches of the work-queue read query.  The batch has n_host
@@ -849,7 +861,7 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
         return RAMBO_OK;
     if (!offsets || !out_masks || (n_chars > 0 && !chars))
         return fail(h, RAMBO_EINVAL, "rambo_query_seqs: NULL array");
-    if (h->query_mode == RAMBO_QUERY_WAVE_PER_READ) {
+    if (wave_per_read(h, n_reads, n_chars)) {
         with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream});
         return launch_check(h, "rambo_query_seqs");
     }
@@ -873,8 +885,11 @@ extern "C" int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_
     int rc = ensure_read_queue(h, n_reads);
     if (rc)
         return rc;
-    // group masks and window counts only: the answers stay in the queue state
-    launch_read_queue(h, h->rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, nullptr, out_nkmers, stream);
+    // group masks and window counts only: the answers stay in the per-read state
+    if (wave_per_read(h, n_reads, n_chars))
+        with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, nullptr, out_nkmers, stream});
+    else
+        launch_read_queue(h, h->rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, nullptr, out_nkmers, stream);
     const uint64_t waves = std::min<uint64_t>(n_reads, (uint64_t)h->num_cus * 16);
     const dim3 grid((uint32_t)div_up(waves, kWavesPerBlock));
     const size_t lds = (size_t)kWavesPerBlock * h->cfg.R * h->SW * 4;

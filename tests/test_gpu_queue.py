@@ -67,3 +67,30 @@ def test_queue_mid_shape_reads():
         m, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
         assert np.array_equal(host_u32(nk), wn.astype(np.uint32))
         assert np.array_equal(host_u32(m), want)
+
+
+@pytest.mark.parametrize("mode", [rb.QUERY_WAVE_PER_READ, rb.QUERY_QUEUE])
+def test_captured_graph_replays_match_oracle(tiny, mode):
+    # the batched query recorded once as a graph and replayed several times,
+    # with eager calls (other inputs) in between: every replay gives the
+    # oracle's answers
+    from paper_1910_02611_amd import autotune
+    import torch
+    cfg, sets, g, rd, want, wn = tiny
+    g.set_query_policy(mode, 256, 8)
+    try:
+        off, ch = dev(rd.offsets, np.int64), dev(rd.chars, np.uint8)
+        out = torch.empty((rd.n, g.W), dtype=torch.int32, device="cuda")
+        nk = torch.empty(rd.n, dtype=torch.int32, device="cuda")
+        graph = autotune.capture_query_seqs(g, off, ch, out, nk)
+        other = synth.config_batched_reads(sets, 300, seed=3019)
+        for _ in range(3):
+            out.zero_()
+            nk.zero_()
+            graph.replay()
+            g.query_seqs(dev(other.offsets, np.int64), dev(other.chars, np.uint8))   # eager work between replays
+            torch.cuda.synchronize()
+            assert np.array_equal(host_u32(nk), wn)
+            assert np.array_equal(host_u32(out), want)
+    finally:
+        g.set_query_policy(rb.QUERY_AUTO)
