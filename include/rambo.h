@@ -173,9 +173,11 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
  * sorts the targets by address into regions of the index and ORs each region
  * in on-chip memory, which avoids the device's atomic-rate limit on bulk
  * inserts; AUTO picks by the number of targets.  scratch_bytes caps the
- * device scratch of the partitioned path (0 = a quarter of free memory, at
- * most 32 GiB); larger inserts are processed in batches.  The scratch is
- * allocated at the first partitioned insert and kept by the handle. */
+ * device scratch of the partitioned path (0 = half of the free memory, at
+ * most 128 GiB); larger inserts are processed in batches, each of which
+ * reads and writes the index regions it touches.  The scratch is sized for
+ * the first partitioned insert, kept by the handle, and released by the
+ * next call of this function that changes scratch_bytes. */
 #define RAMBO_INSERT_AUTO 0
 #define RAMBO_INSERT_DIRECT 1
 #define RAMBO_INSERT_PARTITIONED 2

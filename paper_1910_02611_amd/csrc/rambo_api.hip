@@ -463,7 +463,7 @@ uint64_t scratch_bytes_for(const BinGeom &G, uint64_t T, uint64_t &capA, uint64_
 }
 
 // Allocate the scratch of the partitioned path once: as many targets per
-// batch as fit the limit (default: a quarter of free memory, at most 32 GiB).
+// batch as fit the limit (default: half of free memory, at most 128 GiB).
 int ensure_scratch(rambo *h, uint64_t want_targets)
 {
     if (h->bin_mem)
@@ -473,15 +473,17 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
             return fail(h, RAMBO_EHIP, "hipMemGetInfo failed");
-        limit = free_b / 4;
-        if (limit > (32ull << 30))
-            limit = 32ull << 30;
+        limit = free_b / 2;
+        if (limit > (128ull << 30))
+            limit = 128ull << 30;
     }
     uint64_t capA = 0, capB = 0;
     uint64_t T = want_targets > (1ull << 24) ? want_targets : (1ull << 24);
-    if (T > (1ull << 31))
-        T = 1ull << 31;
-    while (T > 4096 && scratch_bytes_for(h->bin, T, capA, capB) > limit)
+    if (T > (1ull << 35))
+        T = 1ull << 35;
+    // slab positions and fill counters are 32-bit
+    while (T > 4096 && (scratch_bytes_for(h->bin, T, capA, capB) > limit || capA >= (1ull << 31) ||
+                        capB >= (1ull << 31)))
         T = T / 4 * 3;
     const uint64_t bytes = scratch_bytes_for(h->bin, T, capA, capB);
     if (bytes > limit)
