@@ -76,6 +76,8 @@ def lib():
             "orc_copy_bfu": (None, [vp, u32, u32, vp]),
             "orc_bits_at": (None, [vp, u32, vp, u64, vp]),
             "orc_max_threads": (i32, []),
+            "orc_fold": (i32, [vp]),
+            "orc_set_partition": (i32, [vp, vp]),
             "orc_scan_rows": (i32, [vp, vp, vp, vp, u64, u64, vp, vp, u64, vp, i32, i32]),
             "orc_window_keys": (u64, [vp, vp, vp, u64, vp, u64]),
             "orc_query_seqs_rows": (i32, [vp, vp, vp, u64, vp, u64, vp, vp, vp, i32]),
@@ -260,6 +262,20 @@ class OracleIndex:
         out = np.zeros((rows.size, self.B), np.uint8)
         lib().orc_bits_at(self._h, r, _ptr(rows), rows.size, _ptr(out))
         return out
+
+    def fold(self):
+        """Folding over: B -> B/2 (cell b + B/2 OR-ed into cell b)."""
+        rc = lib().orc_fold(self._h)
+        if rc != 0:
+            raise ValueError("orc_fold failed (%d)" % rc)
+        self.B //= 2
+
+    def set_partition(self, phi):
+        """Install the partition phi[r, i] (an empty index only; test hook)."""
+        phi = np.ascontiguousarray(phi, np.uint32)
+        rc = lib().orc_set_partition(self._h, _ptr(phi))
+        if rc != 0:
+            raise ValueError("orc_set_partition failed (%d)" % rc)
 
     # rows of indexes too large for host memory (works with FLAG_NO_FILTERS)
     @property

@@ -489,6 +489,63 @@ void orc_query_seqs(const orc_index *h, const uint64_t *offsets, const unsigned 
     }
 }
 
+/* ---------------------------------------------------------------- folding */
+
+/* Rebuild SetIDs(M[b,r]) from phi (ascending member lists). */
+static void orc_build_members(orc_index *h)
+{
+    uint64_t pos = 0;
+    for (uint32_t r = 0; r < h->R; r++)
+        for (uint32_t b = 0; b < h->B; b++) {
+            h->member_off[(size_t)r * h->B + b] = pos;
+            for (uint32_t i = 0; i < h->K; i++)
+                if (h->phi[(size_t)r * h->K + i] == b)
+                    h->member_ids[pos++] = i;
+        }
+    h->member_off[(size_t)h->R * h->B] = pos;
+}
+
+/* Folding over (Sec. 5.2, the appendix): B -> B/2 by OR-ing the filter of
+ * cell b + B/2 into the filter of cell b in every repetition; a set that was
+ * in cell b + B/2 is now in cell b, so phi becomes phi mod (B/2).  B must be
+ * even. */
+int orc_fold(orc_index *h)
+{
+    if (h->B % 2 != 0 || (h->flags & ORC_FLAG_NO_FILTERS))
+        return ORC_EINVAL;
+    uint32_t half = h->B / 2;
+    uint64_t **bfu = calloc((size_t)h->R * half, sizeof(uint64_t *));
+    if (!bfu)
+        return ORC_ENOMEM;
+    for (uint32_t r = 0; r < h->R; r++)
+        for (uint32_t b = 0; b < half; b++) {
+            uint64_t *lo = h->bfu[(size_t)r * h->B + b], *hi = h->bfu[(size_t)r * h->B + b + half];
+            for (uint64_t w = 0; w < h->words; w++)
+                lo[w] |= hi[w];
+            free(hi);
+            bfu[(size_t)r * half + b] = lo;
+        }
+    free(h->bfu);
+    h->bfu = bfu;
+    h->B = half;
+    for (uint64_t t = 0; t < (uint64_t)h->R * h->K; t++)
+        h->phi[t] %= half;
+    orc_build_members(h);
+    return ORC_OK;
+}
+
+/* Replace the partition by phi[r*K + i] < B (test hook: an index built
+ * directly with a given partition).  Only on an empty index. */
+int orc_set_partition(orc_index *h, const uint32_t *phi)
+{
+    for (uint64_t t = 0; t < (uint64_t)h->R * h->K; t++)
+        if (phi[t] >= h->B)
+            return ORC_EINVAL;
+    memcpy(h->phi, phi, (size_t)h->R * h->K * sizeof(uint32_t));
+    orc_build_members(h);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------- rows of large indexes */
 
 /* Index sizes beyond host memory are checked through rows: row p of

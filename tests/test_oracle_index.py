@@ -386,3 +386,36 @@ def test_read_answers_from_rows_equal_full_oracle():
     assert np.array_equal(got, want)
     with pytest.raises(ValueError):   # a row it was not given
         lean.query_seqs_rows(rd.offsets, rd.chars, keys[1:], rows[1:])
+
+
+# ------------------------------------------------------------ folding over
+
+@pytest.mark.parametrize("B", [8, 50])
+def test_fold_equals_index_built_with_halved_partition(B):
+    # folding over (OR of cell b + B/2 into cell b) gives the index that the
+    # partition phi mod (B/2) builds directly, bit for bit, and its answers
+    cfg = dict(K=120, B=B, R=3, eta=2, k=31, m=1 << 12)
+    sets = synth.genome_sets(501, K=120, n_ancestors=6, ancestor_len=400, sub_rate=0.02)
+    folded = oracle.OracleIndex(**cfg, seed=77)
+    folded.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 4)
+    phi = folded.phi().copy()
+    folded.fold()
+    assert folded.B == B // 2
+    assert np.array_equal(folded.phi(), phi % (B // 2))
+    direct = oracle.OracleIndex(**dict(cfg, B=B // 2), seed=77)
+    direct.set_partition(phi % (B // 2))
+    direct.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 4)
+    for r in range(cfg["R"]):
+        for b in range(B // 2):
+            assert np.array_equal(folded.bfu_words(r, b), direct.bfu_words(r, b))
+    rd = synth.reads(502, sets, 100, median_len=80, min_len=31, max_len=300, substr_frac=0.7)
+    assert np.array_equal(folded.query_seqs(rd.offsets, rd.chars)[0], direct.query_seqs(rd.offsets, rd.chars)[0])
+    # folding never loses a holder: truth is still inside every answer
+    exact = bf.ExactMSMT(cfg["k"])
+    for i in range(sets.n):
+        exact.add_seq(int(sets.set_ids[i]), sets.seq(i))
+    answers = folded.query_seqs(rd.offsets, rd.chars)[0]
+    for q in range(rd.n):
+        truth = exact.query_seq(rd.seq(q))
+        if truth is not None:
+            assert truth <= set(oracle.mask_to_ids(answers[q], cfg["K"]))
