@@ -211,6 +211,20 @@ int rambo_set_query_policy(rambo_t *h, int mode, uint32_t chunk_bytes, uint32_t 
 int rambo_set_timing(rambo_t *h, int enable);
 int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max_stages);
 
+/* Folding over (Sec. 5.2 and the appendix's parallel-indexing experiment):
+ * B -> B/2 by OR-ing the filter of cell b + B/2 into the filter of cell b
+ * in every repetition; the sets of cell b + B/2 then belong to cell b
+ * (phi_r becomes phi_r mod B/2), the answers keep every true holder and the
+ * index takes half the memory (row stride max(8, next_pow2(B/2)) bits).
+ * Later inserts and queries use the folded partition.  B must be even and
+ * no query server may be attached (RAMBO_EINVAL otherwise); RAMBO_ENOMEM
+ * when the new index cannot be allocated (the old one is then kept).  Synchronous: waits for the work on `stream`,
+ * then replaces the index; the handle's scratch and per-read state are
+ * released (rambo_get_info reports the new layout).  Graphs captured from
+ * this handle before the fold hold the old index and must be captured
+ * again. */
+int rambo_fold(rambo_t *h, hipStream_t stream);
+
 /* Zero every Bloom filter (an empty index with the same hashes). */
 int rambo_clear(rambo_t *h, hipStream_t stream);
 

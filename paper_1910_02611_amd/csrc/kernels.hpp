@@ -65,6 +65,60 @@ __global__ __launch_bounds__(kBlock) void k_build_cellmask(const uint16_t *phi, 
     }
 }
 
+// ----------------------------------------------------------- folding over
+
+// 32 bits of a repetition's bit string starting at bit `bit` (bits past the
+// block read as 0).
+__device__ __forceinline__ uint32_t bits32_at(const uint32_t *rep, uint64_t nwords, uint64_t bit)
+{
+    const uint64_t w = bit >> 5;
+    const uint32_t sh = (uint32_t)(bit & 31);
+    const uint32_t lo = w < nwords ? rep[w] : 0u;
+    const uint32_t hi = w + 1 < nwords ? rep[w + 1] : 0u;
+    return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+}
+
+// Folding over (B -> B/2 = half): thread per word of the new index.  New
+// row p, column c < half = old column c OR old column c + half of row p;
+// old rows have stride S bits, new rows S2.
+__global__ __launch_bounds__(kBlock) void k_fold(const uint32_t *src, uint32_t *dst, uint32_t R, uint64_t m,
+                                                 uint32_t S, uint32_t S2, uint64_t wpr, uint64_t wpr2, uint32_t half)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (uint64_t)R * wpr2)
+        return;
+    const uint64_t r = t / wpr2, w = t % wpr2;
+    const uint32_t *rep = src + r * wpr;
+    uint32_t out = 0;
+    if (S2 >= 32) {
+        const uint64_t p = w * 32 / S2;
+        const uint32_t c0 = (uint32_t)(w * 32 % S2);
+        if (p < m && c0 < half) {
+            uint32_t v = bits32_at(rep, wpr, p * S + c0) | bits32_at(rep, wpr, p * S + c0 + half);
+            if (half - c0 < 32)
+                v &= (1u << (half - c0)) - 1u;
+            out = v;
+        }
+    } else {
+        const uint32_t rpw = 32 / S2;   // rows per word; half < S2 <= 16
+        for (uint32_t sl = 0; sl < rpw; ++sl) {
+            const uint64_t p = w * rpw + sl;
+            if (p >= m)
+                break;
+            const uint32_t v = (bits32_at(rep, wpr, p * S) | bits32_at(rep, wpr, p * S + half)) & ((1u << half) - 1u);
+            out |= v << (sl * S2);
+        }
+    }
+    dst[t] = out;
+}
+
+__global__ __launch_bounds__(kBlock) void k_phi_mod(uint16_t *phi, uint64_t n, uint32_t half)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n)
+        phi[t] = (uint16_t)(phi[t] % half);
+}
+
 // ------------------------------------------------------- window walking
 
 // Cursor over the CSR of sequences: the sequence s that holds byte p.

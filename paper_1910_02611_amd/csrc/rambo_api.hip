@@ -48,6 +48,7 @@ struct rambo {
     int num_cus = 256;
     void *rq_mem = nullptr;
     uint64_t rq_cap = 0;               // reads the queue state holds
+    int servers = 0;                   // query servers attached (their graphs hold index pointers)
     ReadQueue rq{};
     uint64_t *scan_part = nullptr;     // tile totals of the ID-list scan (in rq_mem)
     // kernel timing (rambo_set_timing)
@@ -979,6 +980,77 @@ extern "C" int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint6
         with_row_words(h, QuerySeqsLaunch{h, offsets + q, 1, chars, n_chars, out_masks + q * h->W,
                                           out_nkmers ? out_nkmers + q : nullptr, stream});
     return launch_check(h, "rambo_query_seqs_plain");
+}
+
+extern "C" int rambo_fold(rambo_t *h, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    const rambo_config c = h->cfg;
+    if (c.B < 2 || c.B % 2 != 0)
+        return fail(h, RAMBO_EINVAL, "rambo_fold: B must be even");
+    if (h->servers)
+        return fail(h, RAMBO_EINVAL, "rambo_fold: a query server is attached to the handle");
+    const uint32_t half = c.B / 2;
+    const uint32_t S2 = next_pow2(half < 8 ? 8u : half);
+    const uint64_t wpr2 = div_up(div_up(c.m * S2, 32), 4) * 4;
+    uint32_t *index2 = nullptr;
+    if (hipMalloc(&index2, (uint64_t)c.R * wpr2 * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, RAMBO_ENOMEM, "rambo_fold: device allocation failed");
+    }
+    const uint64_t n2 = (uint64_t)c.R * wpr2;
+    {
+        StageScope sc(h, "k_fold", stream);
+        hipLaunchKernelGGL(k_fold, dim3((uint32_t)div_up(n2, kBlock)), dim3(kBlock), 0, stream, h->index, index2, c.R,
+                           c.m, h->S, S2, h->words_per_rep, wpr2, half);
+    }
+    const uint64_t nphi = (uint64_t)c.R * c.K;
+    hipLaunchKernelGGL(k_phi_mod, dim3((uint32_t)div_up(nphi, kBlock)), dim3(kBlock), 0, stream, h->phi, nphi, half);
+    int rc = launch_check(h, "rambo_fold");
+    if (!rc)
+        rc = hip_check(h, hipStreamSynchronize(stream), "rambo_fold");
+    if (rc) {
+        (void)hipFree(index2);
+        return rc;
+    }
+    // the handle now describes the folded index; tables and scratch whose
+    // shape depends on B are rebuilt or dropped
+    (void)hipFree(h->index);
+    h->index = index2;
+    h->cfg.B = half;
+    h->S = S2;
+    h->SW = S2 >= 32 ? S2 / 32 : 1;
+    h->words_per_rep = wpr2;
+    h->index_bytes = (uint64_t)c.R * wpr2 * 4;
+    Params &P = h->P;
+    P.index = index2;
+    P.B = half;
+    P.S_log2 = log2_exact(S2);
+    P.words_per_rep = wpr2;
+    if (h->bin_mem) {
+        (void)hipFree(h->bin_mem);
+        h->bin_mem = nullptr;
+    }
+    plan_partition(h);
+    if (h->rq_mem) {
+        (void)hipFree(h->rq_mem);
+        h->rq_mem = nullptr;
+        h->rq_cap = 0;
+    }
+    if (h->member_off)
+        (void)hipFree(h->member_off);
+    if (h->members)
+        (void)hipFree(h->members);
+    h->member_off = h->members = nullptr;
+    const uint64_t cm_words = (uint64_t)c.R * half * h->W;
+    if ((rc = hip_check(h, hipMemset(h->cellmask, 0, cm_words * 4), "rambo_fold")))
+        return rc;
+    hipLaunchKernelGGL(k_build_cellmask, dim3((uint32_t)div_up((uint64_t)c.R * h->W, kBlock)), dim3(kBlock), 0, 0,
+                       h->phi, c.K, half, c.R, h->W, h->cellmask);
+    if ((rc = launch_check(h, "rambo_fold")) || (rc = hip_check(h, hipDeviceSynchronize(), "rambo_fold")))
+        return rc;
+    return build_member_lists(h);
 }
 
 extern "C" int rambo_clear(rambo_t *h, hipStream_t stream)

@@ -292,6 +292,7 @@ extern "C" int rambo_serve_create(rambo_t *h, const rambo_serve_config *cfg_in, 
         }
     }
     sv->worker = std::thread(serve_loop, sv);
+    ++h->servers;
     *out = sv;
     return RAMBO_OK;
 }
@@ -313,6 +314,7 @@ extern "C" void rambo_serve_destroy(rambo_server_t *sv)
         free_slot(s);
     }
     sv->h->timing = sv->timing_before;
+    --sv->h->servers;
     delete sv;
 }
 

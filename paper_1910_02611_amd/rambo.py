@@ -80,6 +80,7 @@ EXPORTS = {
     "rambo_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rambo_get_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_fold": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rambo_copy_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -163,13 +164,7 @@ class Rambo:
         if rc != OK:
             raise RamboError(rc, "rambo_create: " + (lib().rambo_last_error(None) or b"").decode())
         self._h = h
-        info = Info()
-        lib().rambo_get_info(self._h, ctypes.byref(info))
-        self.row_bits = info.row_bits
-        self.W = info.mask_words
-        self.words_per_rep = info.words_per_rep
-        self.index_bytes = info.index_bytes
-        self._index_ptr = info.index
+        self._refresh_info()
 
     # lifetime -------------------------------------------------------------
     def close(self):
@@ -294,6 +289,21 @@ class Rambo:
             self._check(n, "rambo_get_stage_times")
         raw = names.raw
         return {raw[48 * i:48 * (i + 1)].split(b"\0")[0].decode(): float(ms[i]) for i in range(min(n, max_stages))}
+
+    def _refresh_info(self):
+        info = Info()
+        lib().rambo_get_info(self._h, ctypes.byref(info))
+        self.row_bits = info.row_bits
+        self.W = info.mask_words
+        self.words_per_rep = info.words_per_rep
+        self.index_bytes = info.index_bytes
+        self._index_ptr = info.index
+
+    def fold(self, stream=None):
+        """Folding over: B -> B/2 (synchronous)."""
+        self._check(lib().rambo_fold(self._h, _stream(stream)), "rambo_fold")
+        self.B //= 2
+        self._refresh_info()
 
     def clear(self, stream=None):
         self._check(lib().rambo_clear(self._h, _stream(stream)), "rambo_clear")
