@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 FLAG_IDENTITY_PARTITION = 1
 FLAG_NO_FILTERS = 2   # parameters only, for the row scans of indexes larger than host memory
+FLAG_RAW_KEYS = 4     # terms are arbitrary 64-bit keys (documents and word unigrams), not k-mer codes
 NO_KMER = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -71,7 +72,7 @@ def lib():
             "orc_query_kmer": (i32, [vp, u64, vp]),
             "orc_query_kmers": (None, [vp, vp, u64, vp, i32]),
             "orc_query_seq": (u64, [vp, vp, u64, vp]),
-            "orc_query_seqs": (None, [vp, vp, vp, u64, vp, vp, i32]),
+            "orc_query_seqs": (i32, [vp, vp, vp, u64, vp, vp, i32]),
             "orc_fill_counts": (None, [vp, vp]),
             "orc_copy_bfu": (None, [vp, u32, u32, vp]),
             "orc_bits_at": (None, [vp, u32, vp, u64, vp]),
@@ -238,7 +239,9 @@ class OracleIndex:
         n = offsets.size - 1
         out = np.zeros((n, self.W), np.uint32)
         nk = np.zeros(n, np.uint64)
-        lib().orc_query_seqs(self._h, _ptr(offsets), _ptr(chars), n, _ptr(out), _ptr(nk), nthreads)
+        rc = lib().orc_query_seqs(self._h, _ptr(offsets), _ptr(chars), n, _ptr(out), _ptr(nk), nthreads)
+        if rc != 0:
+            raise ValueError("orc_query_seqs failed (%d)" % rc)
         return out, nk
 
     # inspection

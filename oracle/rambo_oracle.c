@@ -21,6 +21,10 @@
  *    base-4 digit.  Any other byte breaks the window.
  *  - A term is stored in canonical form: the smaller of its code and the
  *    code of its reverse complement (complement of base b is 3-b).
+ *  - With ORC_FLAG_RAW_KEYS the terms are arbitrary 64-bit keys taken as
+ *    they are (documents as sets and word unigrams as terms, Sec. 5.3; the
+ *    caller maps a word to its key).  Such an index takes terms only: the
+ *    sequence functions refuse it.
  *  - Partition hash phi_r (Alg. 1, Sec. 3.1), applied to the set identity:
  *    phi_r(i) = ((a_r * i + b_r) mod P) mod B with P = 2^61 - 1, the
  *    Carter-Wegman 2-universal family the paper cites; repetitions 0..R-1.
@@ -57,6 +61,7 @@
 
 #define ORC_FLAG_IDENTITY_PARTITION 1u
 #define ORC_FLAG_NO_FILTERS 2u          /* parameters only: for the row scans of large indexes */
+#define ORC_FLAG_RAW_KEYS 4u            /* terms are 64-bit keys, not k-mer codes */
 #define ORC_NO_KMER UINT64_MAX
 
 static const uint64_t ORC_P61 = (1ULL << 61) - 1;
@@ -287,6 +292,21 @@ static int orc_bf_query(const orc_index *h, uint32_t r, uint32_t cell, uint64_t 
     return 1;
 }
 
+/* The stored term of an input: the canonical k-mer of a code in [0, 4^k),
+ * or the key itself in a raw-key index.  Returns 0 for a code that is not a
+ * term. */
+static int orc_term(const orc_index *h, uint64_t code, uint64_t *x)
+{
+    if (h->flags & ORC_FLAG_RAW_KEYS) {
+        *x = code;
+        return 1;
+    }
+    if (!orc_code_in_range(code, h->k))
+        return 0;
+    *x = orc_canonical(code, h->k);
+    return 1;
+}
+
 /* Alg. 1 for one term of one set: insert it into the set's cell of every
  * repetition. */
 int orc_insert_kmer(orc_index *h, uint32_t set_id, uint64_t code)
@@ -295,9 +315,9 @@ int orc_insert_kmer(orc_index *h, uint32_t set_id, uint64_t code)
         return ORC_EINVAL;
     if (set_id >= h->K)
         return ORC_ERANGE;
-    if (!orc_code_in_range(code, h->k))
+    uint64_t x;
+    if (!orc_term(h, code, &x))
         return ORC_EINVAL;
-    uint64_t x = orc_canonical(code, h->k);
     for (uint32_t r = 0; r < h->R; r++)
         orc_bf_insert(h, r, h->phi[(size_t)r * h->K + set_id], x);
     return ORC_OK;
@@ -306,6 +326,8 @@ int orc_insert_kmer(orc_index *h, uint32_t set_id, uint64_t code)
 /* Alg. 1 for every valid k-mer of one sequence of set set_id. */
 int orc_insert_seq(orc_index *h, uint32_t set_id, const unsigned char *chars, uint64_t len)
 {
+    if (h->flags & ORC_FLAG_RAW_KEYS)
+        return ORC_EINVAL;
     if (set_id >= h->K)
         return ORC_ERANGE;
     for (uint64_t t = 0; t + h->k <= len; t++) {
@@ -322,7 +344,7 @@ int orc_insert_seq(orc_index *h, uint32_t set_id, const unsigned char *chars, ui
 int orc_insert_seqs(orc_index *h, const uint32_t *set_ids, const uint64_t *offsets,
                     const unsigned char *chars, uint64_t n_seqs, int nthreads)
 {
-    if (h->flags & ORC_FLAG_NO_FILTERS)
+    if (h->flags & (ORC_FLAG_NO_FILTERS | ORC_FLAG_RAW_KEYS))
         return ORC_EINVAL;
     for (uint64_t s = 0; s < n_seqs; s++)
         if (set_ids[s] >= h->K)
@@ -358,9 +380,11 @@ int orc_insert_kmers(orc_index *h, const uint32_t *set_ids, const uint64_t *offs
     for (uint64_t s = 0; s < n_sets; s++) {
         if (set_ids[s] >= h->K)
             return ORC_ERANGE;
-        for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++)
-            if (!orc_code_in_range(codes[p], h->k))
+        for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++) {
+            uint64_t x;
+            if (!orc_term(h, codes[p], &x))
                 return ORC_EINVAL;
+        }
     }
     int64_t ncell = (int64_t)h->R * h->B;
 #ifdef _OPENMP
@@ -373,35 +397,41 @@ int orc_insert_kmers(orc_index *h, const uint32_t *set_ids, const uint64_t *offs
         for (uint64_t s = 0; s < n_sets; s++) {
             if (h->phi[(size_t)r * h->K + set_ids[s]] != cell)
                 continue;
-            for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++)
-                orc_bf_insert(h, r, cell, orc_canonical(codes[p], h->k));
+            for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++) {
+                uint64_t x;
+                orc_term(h, codes[p], &x);
+                orc_bf_insert(h, r, cell, x);
+            }
         }
     }
     return ORC_OK;
 }
 
 /* Alg. 2, the Bloom-filter tests: G[r*B + b] = 1 iff term x passes the BF
- * test of cell (r,b). */
+ * test of cell (r,b) (all 0 for a code that is not a term). */
 void orc_query_cells(const orc_index *h, uint64_t code, unsigned char *G)
 {
-    uint64_t x = orc_canonical(code, h->k);
+    uint64_t x;
+    const int ok = orc_term(h, code, &x);
     for (uint32_t r = 0; r < h->R; r++)
         for (uint32_t b = 0; b < h->B; b++)
-            G[(size_t)r * h->B + b] = (unsigned char)orc_bf_query(h, r, b, x);
+            G[(size_t)r * h->B + b] = (unsigned char)(ok && orc_bf_query(h, r, b, x));
 }
 
 static void orc_mask_set(uint32_t *mask, uint32_t i) { mask[i >> 5] |= 1u << (i & 31); }
 
 /* Alg. 2 for one term: G_r = union of SetIDs(M[b,r]) over the cells b whose
  * BF holds x; A = intersection over r of G_r.  mask has ceil(K/32) words.
- * A code outside [0, 4^k) is not a term and answers the empty set. */
+ * A code outside [0, 4^k) is not a term (unless the index takes raw keys)
+ * and answers the empty set. */
 int orc_query_kmer(const orc_index *h, uint64_t code, uint32_t *mask)
 {
     if (h->flags & ORC_FLAG_NO_FILTERS)
         return ORC_EINVAL;
     uint32_t W = (h->K + 31) / 32;
     memset(mask, 0, W * sizeof(uint32_t));
-    if (!orc_code_in_range(code, h->k))
+    uint64_t x;
+    if (!orc_term(h, code, &x))
         return ORC_EINVAL;
     unsigned char *G = malloc((size_t)h->R * h->B);
     unsigned char *inG = malloc(h->K);
@@ -448,14 +478,17 @@ void orc_query_kmers(const orc_index *h, const uint64_t *codes, uint64_t n, uint
 
 /* Sec. 3.2.1: the answer for a sequence is the conjunction of the answers of
  * all its k-mers (the sliding window), taken literally, with no early exit.
- * Returns the number of valid k-mers; with none, the answer is empty. */
+ * Returns the number of valid k-mers; with none, the answer is empty.  A
+ * raw-key index has no k-mers: every sequence answers the empty set. */
 uint64_t orc_query_seq(const orc_index *h, const unsigned char *chars, uint64_t len, uint32_t *mask)
 {
     uint32_t W = (h->K + 31) / 32;
-    uint32_t *one = malloc(W * sizeof(uint32_t));
-    uint64_t n = 0;
     for (uint32_t w = 0; w < W; w++)
         mask[w] = 0;
+    if (h->flags & ORC_FLAG_RAW_KEYS)
+        return 0;
+    uint32_t *one = malloc(W * sizeof(uint32_t));
+    uint64_t n = 0;
     for (uint32_t i = 0; i < h->K; i++)
         orc_mask_set(mask, i);
     for (uint64_t t = 0; t + h->k <= len; t++) {
@@ -473,9 +506,11 @@ uint64_t orc_query_seq(const orc_index *h, const unsigned char *chars, uint64_t 
     return n;
 }
 
-void orc_query_seqs(const orc_index *h, const uint64_t *offsets, const unsigned char *chars,
-                    uint64_t n_reads, uint32_t *out, uint64_t *nkmers, int nthreads)
+int orc_query_seqs(const orc_index *h, const uint64_t *offsets, const unsigned char *chars,
+                   uint64_t n_reads, uint32_t *out, uint64_t *nkmers, int nthreads)
 {
+    if (h->flags & ORC_FLAG_RAW_KEYS)
+        return ORC_EINVAL;
     uint32_t W = (h->K + 31) / 32;
 #ifdef _OPENMP
     if (nthreads > 0)
@@ -487,6 +522,7 @@ void orc_query_seqs(const orc_index *h, const uint64_t *offsets, const unsigned 
         if (nkmers)
             nkmers[q] = n;
     }
+    return ORC_OK;
 }
 
 /* ---------------------------------------------------------------- folding */
@@ -587,7 +623,7 @@ int orc_scan_rows(const orc_index *h, const uint32_t *set_ids, const uint64_t *o
                   const uint64_t *keys, uint64_t n_keys, uint64_t *rows, int nthreads, int progress)
 {
     uint64_t done = 0;   /* sequences finished, for the progress lines */
-    if (D > 0 && h->m % D != 0)
+    if ((D > 0 && h->m % D != 0) || (h->flags & ORC_FLAG_RAW_KEYS))
         return ORC_EINVAL;
     for (uint64_t s = 0; s < n_seqs; s++)
         if (set_ids[s] >= h->K)
@@ -727,6 +763,8 @@ int orc_query_seqs_rows(const orc_index *h, const uint64_t *offsets, const unsig
                         uint64_t n_reads, const uint64_t *keys, uint64_t n_keys, const uint64_t *rows,
                         uint32_t *out, uint64_t *nkmers, int nthreads)
 {
+    if (h->flags & ORC_FLAG_RAW_KEYS)
+        return ORC_EINVAL;
     uint32_t W = (h->K + 31) / 32;
     int rc = ORC_OK;
 #ifdef _OPENMP

@@ -171,6 +171,73 @@ def reads(seed: int, sets: SeqBatch, n: int, *, median_len: int, min_len: int, m
     return SeqBatch(chars, offsets, None, meta=dict(source_set=src))
 
 
+# ---------------------------------------------------------------- documents
+
+@dataclass
+class KeyBatch:
+    """CSR of 64-bit keys: keys of item i are keys[offsets[i] .. offsets[i+1])."""
+    keys: np.ndarray                   # uint64
+    offsets: np.ndarray                # uint64, n+1
+    set_ids: np.ndarray | None = None  # uint32, n (sets only)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.offsets.size - 1
+
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+
+def zipf_ranks(rng: np.random.Generator, n: int, vocab: int, s: float) -> np.ndarray:
+    """n word ranks in [0, vocab), rank r drawn with probability proportional
+    to (r+1)^-s (a Zipf law truncated to the vocabulary)."""
+    cdf = np.cumsum(np.arange(1, vocab + 1, dtype=np.float64) ** -s)
+    cdf /= cdf[-1]
+    out = np.empty(n, np.int64)
+    for a in range(0, n, 1 << 24):
+        b = min(n, a + (1 << 24))
+        out[a:b] = np.minimum(np.searchsorted(cdf, rng.random(b - a)), vocab - 1)
+    return out
+
+
+def documents(seed: int, K: int, *, vocab: int, median_len: int, min_len: int, max_len: int,
+              zipf_s: float = 1.07) -> KeyBatch:
+    """K documents as sets of word keys, a stand-in for the word-unigram
+    corpora of Sec. 5.3: a vocabulary of `vocab` distinct random 64-bit keys
+    (the word -> key map is the caller's, so words are just keys here);
+    document i has a log-normal number of tokens in [min_len, max_len] drawn
+    from a Zipf law over the vocabulary ranks, and keeps its distinct words.
+    meta: the vocabulary (rank order) and the Zipf exponent."""
+    rng = rng_for(seed)
+    words = np.unique(rng.integers(0, 2**64, size=vocab + vocab // 64 + 64, dtype=np.uint64))
+    words = rng.permutation(words)[:vocab]
+    lens = lognormal_lengths(rng, K, median_len, min_len, max_len)
+    ranks = zipf_ranks(rng, int(lens.sum()), vocab, zipf_s)
+    # distinct (document, rank) pairs, in document order then rank order
+    pairs = np.unique(np.repeat(np.arange(K, dtype=np.int64), lens) * vocab + ranks)
+    doc = pairs // vocab
+    offsets = np.zeros(K + 1, np.uint64)
+    np.cumsum(np.bincount(doc, minlength=K), out=offsets[1:])
+    keys = np.ascontiguousarray(words[pairs % vocab], np.uint64)
+    return KeyBatch(keys, offsets, np.arange(K, dtype=np.uint32), dict(vocab=words, zipf_s=zipf_s))
+
+
+def word_queries(seed: int, docs: KeyBatch, n: int, present_frac: float = 0.5) -> np.ndarray:
+    """n single-word queries (uint64 keys): round(n * present_frac) vocabulary
+    words drawn by the same Zipf law as the text (popular words are asked
+    for more often, as in a query log), the rest random keys outside the
+    vocabulary.  Shuffled."""
+    rng = rng_for(seed)
+    vocab = docs.meta["vocab"]
+    n_in = int(round(n * present_frac))
+    hit = vocab[zipf_ranks(rng, n_in, vocab.size, docs.meta["zipf_s"])]
+    miss = rng.integers(0, 2**64, size=n - n_in, dtype=np.uint64)
+    miss = miss[~np.isin(miss, vocab)]
+    q = np.concatenate([hit, miss, rng.integers(0, 2**64, size=n - n_in - miss.size, dtype=np.uint64)])
+    return rng.permutation(q).astype(np.uint64)
+
+
 # ---------------------------------------------------------------- workloads
 
 def config_tiny(seed: int = 1001) -> SeqBatch:
@@ -243,3 +310,12 @@ INDEX_TINY = dict(K=64, B=8, R=3, m=1 << 18, eta=2, k=31)
 INDEX_MID = dict(K=1000, B=50, R=4, m=1 << 28, eta=2, k=31)
 INDEX_SERVED = dict(K=10_000, B=200, R=5, m=1 << 29, eta=2, k=31)
 INDEX_LARGE = dict(K=100_000, B=1000, R=6, m=1 << 27, eta=2, k=31)
+# the word-unigram index of Sec. 5.3 (the Wikipedia sample's K, B, R and
+# filter size); eta is this workload's choice
+INDEX_WIKI = dict(K=17_618, B=2000, R=2, m=200_000, eta=4, k=31)
+
+
+def config_wiki(seed: int = 1006) -> KeyBatch:
+    """17 618 documents over a 500 000-word vocabulary, about 1 500 tokens
+    each (median; 50 to 20 000), Zipf exponent 1.07."""
+    return documents(seed, 17_618, vocab=500_000, median_len=1500, min_len=50, max_len=20_000)

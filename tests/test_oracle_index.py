@@ -419,3 +419,94 @@ def test_fold_equals_index_built_with_halved_partition(B):
         truth = exact.query_seq(rd.seq(q))
         if truth is not None:
             assert truth <= set(oracle.mask_to_ids(answers[q], cfg["K"]))
+
+
+# --------------------------------------------------- raw 64-bit keys (Sec. 5.3)
+
+def test_raw_key_sets_exactly_its_positions():
+    # one key outside any k-mer range, in one set: every repetition's cell of
+    # that set holds exactly the eta multiply-shift positions of the key
+    # itself (no canonical form, no range check); every other cell is empty
+    cfg = dict(K=6, B=3, R=3, eta=3, k=5, m=4096)
+    o = oracle.OracleIndex(**cfg, seed=91, flags=oracle.FLAG_RAW_KEYS)
+    x = (1 << 63) + 12345
+    assert o.insert_kmers(np.array([4], np.uint32), np.array([0, 1], np.uint64), np.array([x], np.uint64)) == 0
+    _, _, s, phi = o.params()
+    for r in range(cfg["R"]):
+        for b in range(cfg["B"]):
+            want = np.zeros(cfg["m"], np.uint8)
+            if b == phi[r, 4]:
+                want[[oracle.position(x, int(s[r, j]), cfg["m"]) for j in range(cfg["eta"])]] = 1
+            assert np.array_equal(o.bfu_bits(r, b), want), (r, b)
+
+
+def test_raw_keys_are_not_canonicalised():
+    # a k-mer code and its reverse complement are one term of a k-mer index
+    # but two keys of a raw-key index
+    k = 11
+    code = oracle.encode_kmer(b"ACGTTGCAAAC")
+    rc = oracle.revcomp(code, k)
+    assert rc != code
+    cfg = dict(K=4, B=2, R=2, eta=2, k=k, m=1 << 16)
+    one = lambda c: (np.array([1], np.uint32), np.array([0, 1], np.uint64), np.array([c], np.uint64))
+    km = oracle.OracleIndex(**cfg, seed=5)
+    raw = oracle.OracleIndex(**cfg, seed=5, flags=oracle.FLAG_RAW_KEYS)
+    km.insert_kmers(*one(rc))
+    raw.insert_kmers(*one(oracle.canonical(code, k)))
+    same = all(np.array_equal(km.bfu_words(r, b), raw.bfu_words(r, b)) for r in range(2) for b in range(2))
+    assert same                       # canonical code as a raw key = the k-mer term
+    raw2 = oracle.OracleIndex(**cfg, seed=5, flags=oracle.FLAG_RAW_KEYS)
+    raw2.insert_kmers(*one(max(code, rc)))
+    assert not all(np.array_equal(raw2.bfu_words(r, b), raw.bfu_words(r, b)) for r in range(2) for b in range(2))
+
+
+def test_raw_key_index_equals_kmer_index_on_canonical_codes():
+    # inserting every window's canonical code as a raw key builds the same
+    # filters as inserting the sequences (Alg. 1 over the same terms)
+    cfg = dict(K=30, B=6, R=3, eta=2, k=21, m=1 << 14)
+    sets = synth.genome_sets(93, K=30, n_ancestors=3, ancestor_len=300)
+    km = build_oracle(sets, cfg, 17)
+    codes = oracle.extract(sets.offsets, sets.chars, cfg["k"])
+    keep = codes != oracle.NO_KMER
+    seg = np.repeat(np.arange(sets.n), sets.lengths().astype(np.int64))
+    off = np.zeros(sets.n + 1, np.uint64)
+    np.cumsum(np.bincount(seg[keep], minlength=sets.n), out=off[1:])
+    raw = oracle.OracleIndex(**cfg, seed=17, flags=oracle.FLAG_RAW_KEYS)
+    assert raw.insert_kmers(sets.set_ids, off, codes[keep], 4) == 0
+    for r in range(cfg["R"]):
+        for b in range(cfg["B"]):
+            assert np.array_equal(raw.bfu_words(r, b), km.bfu_words(r, b))
+
+
+def test_raw_key_documents_no_false_negatives_and_exact_when_filters_are_perfect():
+    # documents as sets of word keys: every document holding a word is in its
+    # answer (Sec. 4.1); with filters far larger than the sets, the answer is
+    # exactly the documents whose cell holds a true holder in every
+    # repetition (Alg. 2 with no Bloom-filter error)
+    docs = synth.documents(95, 60, vocab=3000, median_len=60, min_len=5, max_len=400)
+    cfg = dict(K=60, B=8, R=3, eta=3, k=31, m=1 << 22)
+    o = oracle.OracleIndex(**cfg, seed=19, flags=oracle.FLAG_RAW_KEYS)
+    assert o.insert_kmers(docs.set_ids, docs.offsets, docs.keys, 4) == 0
+    holders = {}
+    for d in range(docs.n):
+        for x in docs.keys[int(docs.offsets[d]):int(docs.offsets[d + 1])].tolist():
+            holders.setdefault(x, set()).add(d)
+    q = synth.word_queries(96, docs, 2000)
+    got = o.query_kmers(q, nthreads=4)
+    phi = o.phi()
+    for t, x in enumerate(q.tolist()):
+        ids = set(oracle.mask_to_ids(got[t], cfg["K"]))
+        true = holders.get(x, set())
+        assert true <= ids
+        cells = [{int(phi[r, i]) for i in true} for r in range(cfg["R"])]
+        want = {i for i in range(cfg["K"]) if all(int(phi[r, i]) in cells[r] for r in range(cfg["R"]))}
+        assert ids == want
+
+
+def test_raw_key_index_refuses_sequences():
+    cfg = dict(K=4, B=2, R=1, eta=1, k=5, m=64)
+    o = oracle.OracleIndex(**cfg, seed=1, flags=oracle.FLAG_RAW_KEYS)
+    s = synth.genome_sets(3, K=4, n_ancestors=1, ancestor_len=50)
+    assert o.insert_seqs(s.set_ids, s.offsets, s.chars) != 0
+    with pytest.raises(ValueError):
+        o.query_seqs(s.offsets, s.chars)
