@@ -282,6 +282,92 @@ def serving(g, sets, n_requests: int, loads, slots: int = 4):
     }
 
 
+def documents(n_queries: int, steps: int = 3):
+    """Word-unigram document index on raw 64-bit keys (Sec. 5.3, the
+    Wikipedia sample's shape: K = 17 618 documents, B = 2 000, R = 2,
+    m = 200 000, eta = 4) over synthetic Zipf documents (about 1.7e7
+    distinct document-word pairs): key inserts per second and single-word
+    queries per second, each phase timed with HIP events, with the roofline
+    of its kernel."""
+    import torch
+    from paper_1910_02611_amd import synth
+    from paper_1910_02611_amd.rambo import Rambo, FLAG_RAW_KEYS
+    cfg = synth.INDEX_WIKI
+    t = time.time()
+    docs = synth.config_wiki()
+    q = synth.word_queries(3006, docs, n_queries)
+    log("documents: %d docs, %d keys, %d queries (%.1f s to generate)" % (docs.n, docs.keys.size, q.size,
+                                                                         time.time() - t))
+    g = Rambo(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed=2006, flags=FLAG_RAW_KEYS)
+    d = (to_dev(docs.set_ids, np.int32), to_dev(docs.offsets, np.int64), to_dev(docs.keys, np.int64))
+    dq = to_dev(q, np.int64)
+    out = torch.empty((q.size, g.W), dtype=torch.int32, device="cuda")
+    g.insert_kmers(*d)
+    g.query_kmers(dq, out=out)
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    g.stage_times()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for e in ev:
+        g.clear()
+        e[0].record()
+        g.insert_kmers(*d)
+        e[1].record()
+        g.query_kmers(dq, out=out)
+        e[2].record()
+    torch.cuda.synchronize()
+    kernels = {k: v / steps for k, v in g.stage_times().items()}
+    g.set_timing(False)
+    if g.sync_status() != 0:
+        raise SystemExit("device error flag set (documents)")
+    t_ins = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    t_q = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    n_keys, RE, S, W = int(docs.keys.size), cfg["R"] * cfg["eta"], g.row_bits, g.W
+    work = {"k_insert_kmers": (n_keys * RE * 2 * SECTOR, "one 64-B sector read-modify-write per bit target"),
+            "k_query_kmers": (q.size * (RE * max(SECTOR, S // 8) + 4 * W + 8),
+                              "R*eta rows of S/8 bytes + K-bit answer + key per query")}
+    roofs = []
+    for name, (amount, what) in work.items():
+        ms = kernels.get(name)
+        if ms:
+            a = amount / (ms / 1e3) / 1e9
+            roofs.append({"kernel": name, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": a / HBM_PEAK_GBS, "ms": ms, "work_per_launch": amount, "work": what})
+    res = {"workload": "word unigrams: K=17618 documents, B=2000, R=2, m=200000, eta=4 (raw 64-bit keys)",
+           "keys": n_keys, "queries": int(q.size), "index_bytes": g.index_bytes,
+           "insert_ms": t_ins, "keys_inserted_per_s": n_keys / t_ins * 1e3,
+           "query_ms": t_q, "word_queries_per_s": q.size / t_q * 1e3, "kernel_ms": kernels, "rooflines": roofs}
+    log("documents: insert %.2f ms (%.3g keys/s), query %.2f ms (%.3g queries/s)"
+        % (t_ins, res["keys_inserted_per_s"], t_q, res["word_queries_per_s"]))
+    for r in roofs:
+        log("  %-16s %8.3f ms  %.3g GB/s (%.1f%%)" % (r["kernel"], r["ms"], r["achieved"], 100 * r["frac"]))
+    g.close()
+    return res
+
+
+def fold_timing(g):
+    """Folding over the resident index once (B -> B/2): the k_fold kernel's
+    duration against reading the old index and writing the new one once,
+    and the whole call (tables rebuilt on the host included)."""
+    old_bytes, B = g.index_bytes, g.B
+    g.set_timing(True)
+    g.stage_times()
+    t0 = time.perf_counter()
+    g.fold()
+    wall = time.perf_counter() - t0
+    ms = g.stage_times()["k_fold"]
+    g.set_timing(False)
+    moved = old_bytes + g.index_bytes
+    achieved = moved / (ms / 1e3) / 1e9
+    log("fold B %d -> %d: k_fold %.3f ms (%.0f GB/s, %.1f%% of HBM peak), call %.1f ms"
+        % (B, g.B, ms, achieved, 100 * achieved / HBM_PEAK_GBS, wall * 1e3))
+    return {"B_from": B, "B_to": g.B, "index_bytes_from": old_bytes, "index_bytes_to": g.index_bytes,
+            "call_ms": wall * 1e3,
+            "roofline": {"kernel": "k_fold", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "ms": ms, "work_per_launch": moved,
+                         "work": "old index read once + folded index written once"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +376,9 @@ def main():
     ap.add_argument("--queries", type=int, default=10_000_000)
     ap.add_argument("--plain-prefix", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fold", action="store_true", help="skip folding the index over at the end")
+    ap.add_argument("--doc-queries", type=int, default=1_000_000,
+                    help="word queries of the document-index section (0 = skip)")
     ap.add_argument("--reads", type=int, default=100_000, help="batched-read section size (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=3000, help="requests per serving load point (0 = skip)")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.8,1.0")
@@ -370,11 +459,16 @@ def main():
         half = min(res["serving"]["points"], key=lambda p: abs(p["load"] - 0.5))
         res["latency"] = {"p50_ms": half["p50_ms"], "p99_ms": half["p99_ms"], "load": half["load"],
                           "requests_per_s": half["qps"]}
+    if not args.no_fold:
+        res["fold"] = fold_timing(g)
     g.close()
     del out, codes, dsets
     torch.cuda.empty_cache()
     if args.reads > 0:
         res["batched_reads"] = batched_reads(args.reads)
+    if args.doc_queries > 0:
+        res["documents"] = documents(args.doc_queries)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         t = time.time()
         res["cpu_baseline"] = cpu_baseline(sets, q, cfg)

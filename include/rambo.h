@@ -69,6 +69,15 @@ extern "C" {
  * is a plain array of Bloom filters, the special case of Sec. 4.3). */
 #define RAMBO_FLAG_IDENTITY_PARTITION 1u
 
+/* Terms are arbitrary 64-bit keys taken as they are, with no canonical
+ * k-mer form and no range check: documents as sets and word unigrams as
+ * terms (Sec. 5.3; mapping a word to its key is the caller's).  Such an
+ * index takes keys through rambo_insert_kmers and rambo_query_kmers, whose
+ * "codes" are then the keys; k is unused, and every entry point that takes
+ * sequences (insert_seqs, query_seqs, query_seqs_ids, extract_kmers, the
+ * plain sequence path and the query server) returns RAMBO_EINVAL. */
+#define RAMBO_FLAG_RAW_KEYS 4u
+
 /* Limits of this implementation. */
 #define RAMBO_MAX_B 4096u
 #define RAMBO_MAX_R 16u
@@ -110,7 +119,8 @@ void rambo_destroy(rambo_t *h);
  * non-decreasing, with offsets[n_sets] <= n_codes.  Codes need not be
  * canonical.  Repeated calls OR into the same index (streaming updates,
  * Sec. 3.1); order does not matter.  Device errors: RAMBO_ERANGE (set id),
- * RAMBO_ECODE (code >= 4^k) - the item is skipped. */
+ * RAMBO_ECODE (code >= 4^k, k-mer indexes only) - the item is skipped.
+ * With RAMBO_FLAG_RAW_KEYS the codes are the keys. */
 int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets,
                        uint64_t n_sets, const uint64_t *codes, uint64_t n_codes,
                        hipStream_t stream);
@@ -124,7 +134,8 @@ int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint64_t *offse
                       hipStream_t stream);
 
 /* Alg. 2 for n k-mer codes: out_masks[q*W .. q*W+W) receives the answer of
- * codes[q].  A code >= 4^k gets an empty mask (and RAMBO_ECODE). */
+ * codes[q].  A code >= 4^k gets an empty mask (and RAMBO_ECODE); with
+ * RAMBO_FLAG_RAW_KEYS every 64-bit code is a key. */
 int rambo_query_kmers(rambo_t *h, const uint64_t *codes, uint64_t n,
                       uint32_t *out_masks, hipStream_t stream);
 

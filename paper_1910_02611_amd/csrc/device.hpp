@@ -38,6 +38,7 @@ struct Params {
     uint32_t K, B, R, eta, k, W;
     uint32_t S_log2;            // log2 of the row stride in bits
     uint32_t m_log2;            // log2(m) when m is a power of two, else 0
+    uint32_t raw_keys;          // 1: terms are 64-bit keys taken as they are (no canonical k-mer form)
     uint32_t rep_first;         // bit t: probe t is the first of its repetition
     uint32_t rep_last;          // bit t: probe t is the last of its repetition
     uint8_t rep_of[RAMBO_MAX_RETA];    // repetition of probe t = r*eta + j

@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_insert_kmers(Params P, const uint32_
         atomicOr(P.err, kErrCode);
         return;
     }
-    const uint64_t hx = mix64(canonical(code, P.k));
+    const uint64_t hx = mix64(P.raw_keys ? code : canonical(code, P.k));
     for (uint32_t r = 0; r < P.R; ++r) {
         const uint32_t col = P.phi[(uint64_t)r * P.K + set];
         for (uint32_t j = 0; j < P.eta; ++j)
@@ -511,22 +511,98 @@ __device__ __forceinline__ void probe_rep(const Params &P, uint64_t hx, uint32_t
 // K-bit answer word w from the group masks g (R x SW words, uniform across
 // the lanes that share it): AND over r of the union of SetIDs(M[b,r]) over
 // the cells b set in g_r (Alg. 2).
-__device__ __forceinline__ uint32_t expand_word(const Params &P, const uint32_t *g, uint32_t SW, uint32_t w)
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    for (int d = 32; d >= 1; d >>= 1)
+        v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t lane)
+{
+    uint32_t x = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= (uint32_t)d)
+            x += y;
+    }
+    return x - v;
+}
+
+// Bits of word x of a bit string of n bits that lie below n.
+__device__ __forceinline__ uint32_t bits_below(uint32_t x, uint32_t n)
+{
+    const uint32_t lo = x * 32;
+    return lo + 32 <= n ? ~0u : (lo >= n ? 0u : (1u << (n - lo)) - 1u);
+}
+
+// Alg. 2 takes, per repetition, the union of the sets of the positive
+// cells.  The B cells of a repetition partition the K sets, so that union
+// is also the complement (below K) of the union over the negative cells:
+// bit r of the result says repetition r has more positive cells than
+// negative ones and is built from the negative cells.  *cost: cells walked;
+// *empty (when given): some repetition has no positive cell.
+__device__ __forceinline__ uint32_t complement_reps(const Params &P, const uint32_t *g, uint32_t R, uint32_t SW,
+                                                    uint32_t *cost, bool *empty = nullptr)
+{
+    uint32_t neg = 0, c = 0;
+    bool none = false;
+    for (uint32_t r = 0; r < R; ++r) {
+        uint32_t npos = 0;
+        for (uint32_t sw = 0; sw < SW; ++sw)
+            npos += (uint32_t)__builtin_popcount(g[r * SW + sw]);
+        none = none || npos == 0;
+        if (2 * npos > P.B) {
+            neg |= 1u << r;
+            c += P.B - npos;
+        } else {
+            c += npos;
+        }
+    }
+    *cost = c;
+    if (empty)
+        *empty = none;
+    return neg;
+}
+
+// Expanding from the partition (K*R lookups of 2 bytes) beats walking
+// `cost` cell masks of W words when cost * W exceeds K * R.
+__device__ __forceinline__ bool partition_cheaper(const Params &P, uint32_t cost, uint32_t R)
+{
+    return (uint64_t)cost * P.W > (uint64_t)P.K * R;
+}
+
+// Word w of the answer from the group masks g (R x SW words): the AND over
+// repetitions of the union of the cell masks of the positive cells, or of
+// the complement of the union over the negative cells for the repetitions
+// in `neg` (complement_reps).
+__device__ __forceinline__ uint32_t expand_word(const Params &P, const uint32_t *g, uint32_t SW, uint32_t w,
+                                                uint32_t neg)
 {
     uint32_t acc = ~0u;
     for (uint32_t r = 0; r < P.R; ++r) {
+        const bool c = (neg >> r) & 1u;
         uint32_t u = 0;
         for (uint32_t sw = 0; sw < SW; ++sw) {
             uint32_t bits = g[r * SW + sw];
+            if (c)
+                bits = ~bits & bits_below(sw, P.B);
             while (bits) {
                 const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
                 bits &= bits - 1;
                 u |= P.cellmask[((uint64_t)r * P.B + b) * P.W + w];
             }
         }
-        acc &= u;
+        acc &= c ? ~u : u;
     }
-    return acc;
+    return acc & bits_below(w, P.K);
 }
 
 __device__ __forceinline__ bool any_rep_empty(const uint32_t *g, uint32_t R, uint32_t SW)
@@ -539,6 +615,155 @@ __device__ __forceinline__ bool any_rep_empty(const uint32_t *g, uint32_t R, uin
             return true;
     }
     return false;
+}
+
+// Answer words of one query from the partition instead of the cell masks:
+// set i is in the answer iff its cell phi_r(i) is positive in every
+// repetition (the union-then-intersection of Alg. 2, evaluated per set).
+// The same bits as the cell masks give, but the work is K*R lookups whatever
+// the number of positive cells, which wins when many cells are positive and
+// many negative (a term held by about half of the sets).  The whole wave
+// takes one query: 64 sets per step, 8 steps of loads in flight; lane l
+// keeps word l of a 2048-set stripe and stores it.  g: the query's R x SW
+// group-mask words.  R_T > 0: R fixed at compile time.
+template <int R_T>
+__device__ __forceinline__ void expand_by_partition(const Params &P, const uint32_t *g, uint32_t SW, uint32_t R,
+                                                    uint32_t *o, uint32_t lane)
+{
+    constexpr int TB = 8;
+    constexpr int RN = R_T > 0 ? R_T : 1;
+    for (uint32_t base = 0; base < P.K; base += 64 * 32) {
+        uint32_t mine = 0;
+        const uint32_t tmax = min(32u, (P.K - base + 63) / 64);
+        for (uint32_t t0 = 0; t0 < tmax; t0 += TB) {
+            bool in[TB];
+            if constexpr (R_T > 0) {
+                uint32_t cell[TB][RN];
+#pragma unroll
+                for (int u = 0; u < TB; ++u) {
+                    const uint32_t i = base + (t0 + u) * 64 + lane;
+                    in[u] = t0 + u < tmax && i < P.K;
+#pragma unroll
+                    for (int r = 0; r < RN; ++r)
+                        cell[u][r] = in[u] ? P.phi[(uint64_t)r * P.K + i] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < TB; ++u)
+#pragma unroll
+                    for (int r = 0; r < RN; ++r)
+                        in[u] = in[u] && ((g[r * SW + (cell[u][r] >> 5)] >> (cell[u][r] & 31)) & 1u);
+            } else {
+#pragma unroll
+                for (int u = 0; u < TB; ++u) {
+                    const uint32_t i = base + (t0 + u) * 64 + lane;
+                    in[u] = t0 + u < tmax && i < P.K;
+                    for (uint32_t r = 0; r < R && in[u]; ++r) {
+                        const uint32_t b = P.phi[(uint64_t)r * P.K + i];
+                        in[u] = (g[r * SW + (b >> 5)] >> (b & 31)) & 1u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                const uint64_t m = __ballot(in[u]);
+                if ((lane >> 1) == t0 + u)
+                    mine = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
+            }
+        }
+        const uint32_t w = base / 32 + lane;
+        if (w < P.W)
+            o[w] = mine;
+    }
+}
+
+// Cells walked per answer by expand_answer_wave (K <= 32 W, so the cell
+// path is taken only with cost <= 32 R <= 512).
+constexpr uint32_t kListCap = 512;
+constexpr uint32_t kSegs = RAMBO_MAX_R + 1;
+
+// One query's answer words o[0 .. W) by the whole wave from its group masks
+// G (R x SW words, wave-uniform).  Zeros when empty.  Else, when the cell
+// masks are less work than the partition: per repetition the shorter of its
+// positive and negative cell lists goes to the wave's LDS list lst (the
+// cells of repetition r at lst[seg[r] .. seg[r+1])), then every answer word
+// ORs those cells' mask words (complemented for a negative list) and ANDs
+// over repetitions; otherwise expand_by_partition.  lst: kListCap entries,
+// seg: kSegs entries, both the wave's own.
+template <int R_T>
+__device__ __forceinline__ void expand_answer_wave(const Params &P, const uint32_t *G, uint32_t R, uint32_t SW,
+                                                   bool empty, uint32_t *o, uint32_t lane, uint16_t *lst,
+                                                   uint16_t *seg)
+{
+    uint32_t cost = 0, neg = 0;
+    if (!empty) {
+        bool none;
+        neg = complement_reps(P, G, R, SW, &cost, &none);
+        empty = none;
+    }
+    if (empty) {
+        for (uint32_t w = lane; w < P.W; w += kWave)
+            o[w] = 0u;
+        return;
+    }
+    if (cost > kListCap || partition_cheaper(P, cost, R)) {
+        expand_by_partition<R_T>(P, G, SW, R, o, lane);
+        return;
+    }
+    uint32_t pos = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        if (lane == 0)
+            seg[r] = (uint16_t)pos;
+        const bool c = (neg >> r) & 1u;
+        for (uint32_t sw0 = 0; sw0 < SW; sw0 += kWave) {
+            const uint32_t sw = sw0 + lane;
+            uint32_t bits = 0;
+            if (sw < SW) {
+                bits = G[r * SW + sw];
+                if (c)
+                    bits = ~bits & bits_below(sw, P.B);
+            }
+            const uint32_t cnt = (uint32_t)__builtin_popcount(bits);
+            uint32_t at = pos + wave_excl_scan_u32(cnt, lane);
+            while (bits) {
+                lst[at++] = (uint16_t)(sw * 32 + (uint32_t)__builtin_ctz(bits));
+                bits &= bits - 1;
+            }
+            pos += wave_sum_u32(cnt);
+        }
+    }
+    if (lane == 0)
+        seg[R] = (uint16_t)pos;
+    wave_sync_lds();
+    if ((P.W & 3u) == 0) {
+        u32x4 *o4 = reinterpret_cast<u32x4 *>(o);
+        for (uint32_t w4 = lane; w4 < P.W / 4; w4 += kWave) {
+            const uint32_t w = 4 * w4;
+            u32x4 acc = {~0u, ~0u, ~0u, ~0u};
+            for (uint32_t r = 0; r < R; ++r) {
+                u32x4 u = {0u, 0u, 0u, 0u};
+                const uint32_t e1 = seg[r + 1];
+                for (uint32_t e = seg[r]; e < e1; ++e)
+                    u |= *reinterpret_cast<const u32x4 *>(P.cellmask + ((uint64_t)r * P.B + lst[e]) * P.W + w);
+                acc &= ((neg >> r) & 1u) ? ~u : u;
+            }
+            const u32x4 valid = {bits_below(w, P.K), bits_below(w + 1, P.K), bits_below(w + 2, P.K),
+                                 bits_below(w + 3, P.K)};
+            o4[w4] = acc & valid;
+        }
+    } else {
+        for (uint32_t w = lane; w < P.W; w += kWave) {
+            uint32_t acc = ~0u;
+            for (uint32_t r = 0; r < R; ++r) {
+                uint32_t u = 0;
+                const uint32_t e1 = seg[r + 1];
+                for (uint32_t e = seg[r]; e < e1; ++e)
+                    u |= P.cellmask[((uint64_t)r * P.B + lst[e]) * P.W + w];
+                acc &= ((neg >> r) & 1u) ? ~u : u;
+            }
+            o[w] = acc & bits_below(w, P.K);
+        }
+    }
+    wave_sync_lds();   // the list is the next answer's
 }
 
 // ---------------------------------------------------------- term queries
@@ -569,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
     const bool ok = live && code <= P.kmask;
     if (live && !ok && part == 0)
         atomicOr(P.err, kErrCode);
-    const uint64_t hx = mix64(canonical(code & P.kmask, P.k));
+    const uint64_t hx = mix64(P.raw_keys ? code : canonical(code & P.kmask, P.k));
 
     if constexpr (R_T > 0) {
         // Repetition 0 first: a term with no positive cell there has an empty
@@ -606,42 +831,95 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
                 gq[r * SW + part * L + w] = acc[w];
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
+
+    if constexpr (SW > 4) {
+        // Wide rows (few queries per wave): the whole wave expands one query
+        // at a time (expand_answer_wave).
+        __shared__ uint16_t lst[kWavesPerBlock * kListCap];
+        __shared__ uint16_t seg[kWavesPerBlock * kSegs];
+        for (uint32_t qi = 0; qi < (uint32_t)QPW; ++qi) {
+            const uint64_t q2 = qbase + qi;
+            if (q2 >= n)
+                break;
+            expand_answer_wave<R_T>(P, gs + (wv * QPW + qi) * RMAX * SW, R, SW, false, out + q2 * P.W, lane,
+                                    lst + wv * kListCap, seg + wv * kSegs);
+        }
+        return;
+    }
+
+    // Narrow rows: per query, empty (some repetition has no positive cell),
+    // or expanded from the cell masks (positive cells, or the complement of
+    // the negative ones per repetition: nm), or from the partition when that
+    // is less work (expand_by_partition).  Bit qi of ne / by_part.
+    __shared__ uint32_t nm[kWavesPerBlock * QPW];
+    uint32_t neg = 0, cost = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        uint32_t npos = 0;
+#pragma unroll
+        for (int w = 0; w < L; ++w)
+            npos += (uint32_t)__builtin_popcount(gq[r * SW + part * L + w]);
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1)
+            npos += (uint32_t)__shfl_xor((int)npos, off, kWave);
+        if (2 * npos > P.B) {
+            neg |= 1u << r;
+            cost += P.B - npos;
+        } else {
+            cost += npos;
+        }
+    }
+    if (part == 0)
+        nm[wv * QPW + ql] = neg;
+    const uint64_t heavy_g = __ballot(live && part == 0 && partition_cheaper(P, cost, R));
+    wave_sync_lds();
+    const uint32_t ql2 = lane < (uint32_t)QPW ? lane : 0u;
+    const bool nonempty = lane < (uint32_t)QPW && qbase + lane < n &&
+                          !any_rep_empty(gs + (wv * QPW + ql2) * RMAX * SW, R, SW);
+    const uint64_t ne = __ballot(nonempty);
+    const uint64_t by_part = ne & __ballot(lane < (uint32_t)QPW && ((heavy_g >> (lane * G)) & 1));
 
     if ((P.W & 3u) == 0) {
         // The wave's answers are QPW * W consecutive words: each lane takes 4
         // of them (one 16-byte store) per step.  Empty answers are zeros;
         // the others OR 16-byte slices of the cell masks.
-        const uint32_t ql2 = lane < (uint32_t)QPW ? lane : 0u;
-        const bool nonempty = lane < (uint32_t)QPW && qbase + lane < n &&
-                              !any_rep_empty(gs + (wv * QPW + ql2) * RMAX * SW, R, SW);
-        const uint64_t ne = __ballot(nonempty);
         const uint32_t W4 = P.W / 4;
         const uint64_t n_here = min((uint64_t)QPW, n - qbase);
         const uint32_t total4 = (uint32_t)n_here * W4;
         u32x4 *o4 = reinterpret_cast<u32x4 *>(out + qbase * P.W);
         for (uint32_t i = lane; i < total4; i += kWave) {
             const uint32_t qi = i / W4, w = (i - qi * W4) * 4;
+            if ((by_part >> qi) & 1)
+                continue;
             u32x4 acc = {0u, 0u, 0u, 0u};
             if ((ne >> qi) & 1) {
                 const uint32_t *g2 = gs + (wv * QPW + qi) * RMAX * SW;
+                const uint32_t negq = nm[wv * QPW + qi];
                 acc = ~acc;
                 for (uint32_t r = 0; r < R; ++r) {
+                    const bool c = (negq >> r) & 1u;
                     u32x4 u = {0u, 0u, 0u, 0u};
                     for (uint32_t sw = 0; sw < (uint32_t)SW; ++sw) {
                         uint32_t bits = g2[r * SW + sw];
+                        if (c)
+                            bits = ~bits & bits_below(sw, P.B);
                         while (bits) {
                             const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
                             bits &= bits - 1;
                             u |= *reinterpret_cast<const u32x4 *>(P.cellmask + ((uint64_t)r * P.B + b) * P.W + w);
                         }
                     }
-                    acc &= u;
+                    acc &= c ? ~u : u;
                 }
+                const u32x4 valid = {bits_below(w, P.K), bits_below(w + 1, P.K), bits_below(w + 2, P.K),
+                                     bits_below(w + 3, P.K)};
+                acc &= valid;
             }
             o4[i] = acc;
+        }
+        for (uint64_t bp = by_part; bp; bp &= bp - 1) {
+            const uint32_t qi = (uint32_t)__builtin_ctzll(bp);
+            expand_by_partition<R_T>(P, gs + (wv * QPW + qi) * RMAX * SW, SW, R, out + (qbase + qi) * P.W, lane);
         }
         return;
     }
@@ -654,22 +932,22 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
         const uint64_t q2 = qbase + qi;
         if (q2 >= n)
             break;
+        if ((by_part >> qi) & 1)
+            continue;
         const uint32_t *g2 = gs + (wv * QPW + qi) * RMAX * SW;
-        const bool empty = any_rep_empty(g2, R, SW);
+        const bool empty = !((ne >> qi) & 1);
+        const uint32_t negq = nm[wv * QPW + qi];
         uint32_t *o = out + q2 * P.W;
         for (uint32_t w = wl; w < P.W; w += WG)
-            o[w] = empty ? 0u : expand_word(P, g2, SW, w);
+            o[w] = empty ? 0u : expand_word(P, g2, SW, w, negq);
+    }
+    for (uint64_t bp = by_part; bp; bp &= bp - 1) {
+        const uint32_t qi = (uint32_t)__builtin_ctzll(bp);
+        expand_by_partition<R_T>(P, gs + (wv * QPW + qi) * RMAX * SW, SW, R, out + (qbase + qi) * P.W, lane);
     }
 }
 
 // ------------------------------------------------------ sequence queries
-
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // One 64-window step of a read over rows wider than 4 words (compile-time R
 // and eta).  GL = SW/4 lanes share a window, each loading one 16-byte slice
@@ -919,10 +1197,10 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
             state_nk[q] = nk;
         return;
     }
-    uint32_t *o = out + q * P.W;
-    const bool empty = dead || nk == 0;
-    for (uint32_t w = lane; w < P.W; w += kWave)
-        o[w] = empty ? 0u : expand_word(P, G, SW, w);
+    __shared__ uint16_t lst[kWavesPerBlock * kListCap];
+    __shared__ uint16_t seg[kWavesPerBlock * kSegs];
+    expand_answer_wave<R_T>(P, G, R, SW, dead || nk == 0, out + q * P.W, lane, lst + wv * kListCap,
+                            seg + wv * kSegs);
 }
 
 }  // namespace rambo_dev

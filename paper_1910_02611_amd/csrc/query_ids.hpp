@@ -24,24 +24,6 @@ namespace rambo_dev {
 constexpr int kErrOverflow = 4;
 constexpr uint32_t kScanTile = 1024;   // elements per block of the u64 scan (256 threads x 4)
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-    for (int d = 32; d >= 1; d >>= 1)
-        v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t lane)
-{
-    uint32_t x = v;
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, kWave);
-        if (lane >= (uint32_t)d)
-            x += y;
-    }
-    return x - v;
-}
-
 // Loads read q's final group masks (R x SW words) into the wave's LDS G and
 // tells whether its answer is empty (no valid window, or some repetition
 // without a positive cell).
@@ -144,9 +126,12 @@ __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uin
             const Enum e = plan_enum(P, G, SW);
             if (e.by_members)
                 for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t, bool pass) { c += pass ? 1u : 0u; });
-            else
+            else {
+                uint32_t cost;
+                const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
                 for (uint32_t w = lane; w < P.W; w += kWave)
-                    c += __builtin_popcount(expand_word(P, G, SW, w));
+                    c += __builtin_popcount(expand_word(P, G, SW, w, neg));
+            }
         }
         c = wave_sum_u32(c);
         if (lane == 0)
@@ -292,9 +277,11 @@ __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uin
                 ids[o0 + t] = buf[t];
         } else {
             uint64_t base = o0;
+            uint32_t cost;
+            const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
             for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
                 const uint32_t w = w0 + lane;
-                uint32_t word = w < P.W ? expand_word(P, G, SW, w) : 0u;
+                uint32_t word = w < P.W ? expand_word(P, G, SW, w, neg) : 0u;
                 const uint32_t c = __builtin_popcount(word);
                 uint64_t pos = base + wave_excl_scan_u32(c, lane);
                 while (word) {

@@ -124,6 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
     const uint32_t rsw = R * SW;
     const uint32_t lane = lane_id();
     uint32_t *G = Gs[threadIdx.x / kWave];
+    __shared__ uint16_t lst[kWavesPerBlock * kListCap];
+    __shared__ uint16_t seg[kWavesPerBlock * kSegs];
+    uint16_t *my_lst = lst + (threadIdx.x / kWave) * kListCap, *my_seg = seg + (threadIdx.x / kWave) * kSegs;
     const uint32_t total = Q.items[n_reads];
 
     for (;;) {
@@ -177,10 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
         for (uint32_t i = lane; i < rsw; i += kWave)
             G[i] = __hip_atomic_load(Q.G + q * rsw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wave_sync_lds();
-        const bool empty = nk_all == 0 || any_rep_empty(G, R, SW);
-        uint32_t *o = out + q * P.W;
-        for (uint32_t w = lane; w < P.W; w += kWave)
-            o[w] = empty ? 0u : expand_word(P, G, SW, w);
+        expand_answer_wave<R_T>(P, G, R, SW, nk_all == 0, out + q * P.W, lane, my_lst, my_seg);
         wave_sync_lds();
     }
 }

@@ -174,6 +174,12 @@ void with_shape(const rambo *h, F &&f)
             }
         }
     }
+    if constexpr (SW == 64) {
+        if (E == 4 && R == 2) {   // the word-unigram index of Sec. 5.3 (B = 2000)
+            f.template operator()<64, 2, 4>();
+            return;
+        }
+    }
     f.template operator()<SW, 0, 0>();
 }
 
@@ -625,7 +631,7 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
     const rambo_config c = *cfg;
     if (c.K < 1 || c.B < 1 || c.B > c.K || c.B > RAMBO_MAX_B || c.R < 1 || c.R > RAMBO_MAX_R || c.eta < 1 ||
         (uint64_t)c.R * c.eta > RAMBO_MAX_RETA || c.k < 1 || c.k > 32 || c.m < 64 || c.m > (1ull << 48) ||
-        (c.flags & ~RAMBO_FLAG_IDENTITY_PARTITION))
+        (c.flags & ~(RAMBO_FLAG_IDENTITY_PARTITION | RAMBO_FLAG_RAW_KEYS)))
         return fail(nullptr, RAMBO_EINVAL, "rambo_create: configuration out of range");
 
     rambo *h = new (std::nothrow) rambo();
@@ -667,7 +673,8 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
         }
     P.m = c.m;
     P.words_per_rep = h->words_per_rep;
-    P.kmask = c.k >= 32 ? ~0ull : ((1ull << (2 * c.k)) - 1);
+    P.raw_keys = (c.flags & RAMBO_FLAG_RAW_KEYS) ? 1u : 0u;
+    P.kmask = c.k >= 32 || P.raw_keys ? ~0ull : ((1ull << (2 * c.k)) - 1);
     P.K = c.K;
     P.B = c.B;
     P.R = c.R;
@@ -806,6 +813,14 @@ extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_by
     return RAMBO_OK;
 }
 
+// Sequence input needs k-mer terms: a raw-key index refuses it.
+int refuse_raw_keys(rambo *h, const char *what)
+{
+    if (!(h->cfg.flags & RAMBO_FLAG_RAW_KEYS))
+        return RAMBO_OK;
+    return fail(h, RAMBO_EINVAL, std::string(what) + ": the index holds raw 64-bit keys, not k-mers");
+}
+
 extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_sets,
                                   const uint64_t *codes, uint64_t n_codes, hipStream_t stream)
 {
@@ -827,6 +842,8 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
 {
     if (!h)
         return RAMBO_EINVAL;
+    if (const int rr = refuse_raw_keys(h, "rambo_insert_seqs"))
+        return rr;
     if (n_seqs == 0 || n_chars == 0)
         return RAMBO_OK;
     if (!set_ids || !offsets || !chars)
@@ -860,6 +877,8 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
 {
     if (!h)
         return RAMBO_EINVAL;
+    if (const int rr = refuse_raw_keys(h, "rambo_query_seqs"))
+        return rr;
     if (n_reads == 0)
         return RAMBO_OK;
     if (!offsets || !out_masks || (n_chars > 0 && !chars))
@@ -881,6 +900,8 @@ extern "C" int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_
 {
     if (!h)
         return RAMBO_EINVAL;
+    if (const int rr = refuse_raw_keys(h, "rambo_query_seqs_ids"))
+        return rr;
     if (!id_offsets || (n_reads > 0 && !offsets) || (n_chars > 0 && !chars) || (cap > 0 && !ids))
         return fail(h, RAMBO_EINVAL, "rambo_query_seqs_ids: NULL array");
     if (n_reads == 0)
@@ -939,6 +960,8 @@ extern "C" int rambo_extract_kmers(rambo_t *h, const uint64_t *offsets, uint64_t
 {
     if (!h)
         return RAMBO_EINVAL;
+    if (const int rr = refuse_raw_keys(h, "rambo_extract_kmers"))
+        return rr;
     if (n_chars == 0)
         return RAMBO_OK;
     if (!chars || !out_codes || (n_seqs > 0 && !offsets))
@@ -972,6 +995,8 @@ extern "C" int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint6
 {
     if (!h)
         return RAMBO_EINVAL;
+    if (const int rr = refuse_raw_keys(h, "rambo_query_seqs_plain"))
+        return rr;
     if (n_reads == 0)
         return RAMBO_OK;
     if (!offsets || !out_masks || (n_chars > 0 && !chars))

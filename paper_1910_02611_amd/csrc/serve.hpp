@@ -256,6 +256,8 @@ extern "C" int rambo_serve_create(rambo_t *h, const rambo_serve_config *cfg_in, 
     if (!h || !out)
         return RAMBO_EINVAL;
     *out = nullptr;
+    if (const int rr = refuse_raw_keys(h, "rambo_serve_create"))
+        return rr;
     rambo_serve_config c = cfg_in ? *cfg_in : rambo_serve_config{};
     if (c.mem_budget == 0)
         c.mem_budget = 1ull << 30;

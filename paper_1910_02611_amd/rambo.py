@@ -23,6 +23,7 @@ EHIP = -1000
 ECODE = -1001
 ETIMEDOUT = -110
 FLAG_IDENTITY_PARTITION = 1
+FLAG_RAW_KEYS = 4   # terms are 64-bit keys (documents and word unigrams) passed as the k-mer codes
 INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED = 0, 1, 2
 QUERY_AUTO, QUERY_WAVE_PER_READ, QUERY_QUEUE = 0, 1, 2
 NO_KMER = -1   # UINT64_MAX viewed as int64
