@@ -265,8 +265,18 @@ def serving(g, sets, n_requests: int, loads, slots: int = 4):
     with Server(g, max_slots=slots, use_graphs=True) as srv:
         serve.saturated(srv, reqs[: min(200, len(reqs))], g.W)   # warm-up
         res = serve.sweep(srv, reqs, g.W, loads)
+        # streaming inserts among the queries at half load: every 20 ms, 32
+        # pieces of 5 kbp added to random sets
+        rate = 0.5 * res["saturated"]["qps"]
+        arr = synth.poisson_arrivals(5100, len(reqs), rate)
+        ins = serve.insert_stream(5101, sets, max(1, int(arr[-1] / 0.02)), 0.02, 32, 5000)
+        mixed = serve.run_open_loop(srv, reqs, arr, g.W, inserts=ins)
         res["server"] = srv.stats()
     sat = res["saturated"]
+    log("serving with inserts at load 0.5: %d inserts of %d bases each, query p50 %.3f ms p99 %.3f ms, "
+        "insert p50 %.3f ms p99 %.3f ms" % (mixed["inserts"], mixed["insert_bases"] // mixed["inserts"],
+                                            mixed["p50_ms"], mixed["p99_ms"], mixed["insert_p50_ms"],
+                                            mixed["insert_p99_ms"]))
     log("serving: saturated %.4g requests/s (%.4g reads/s), p50 %.3f ms p99 %.3f ms"
         % (sat["qps"], sat["reads_per_s"], sat["p50_ms"], sat["p99_ms"]))
     for p in res["points"]:
@@ -278,6 +288,8 @@ def serving(g, sets, n_requests: int, loads, slots: int = 4):
                     "70%% set substrings; %d requests per point, %d slots, graph replay" % (len(reqs), slots),
         "saturated": {k: sat[k] for k in ("qps", "reads_per_s", "p50_ms", "p99_ms")},
         "points": [{k: p[k] for k in keep} for p in res["points"]],
+        "with_inserts": {k: mixed[k] for k in ("qps", "p50_ms", "p99_ms", "inserts", "insert_bases",
+                                               "insert_p50_ms", "insert_p99_ms")},
         "server": res["server"],
     }
 

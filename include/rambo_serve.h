@@ -58,12 +58,28 @@ void rambo_serve_destroy(rambo_server_t *s);
  * (>= 0), or RAMBO_EINVAL if the request is larger than one batch. */
 int64_t rambo_serve_submit(rambo_server_t *s, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars);
 
+/* Queue an insertion (Alg. 1; streaming updates, Sec. 3.1) of n_seqs
+ * sequences given in HOST memory: every valid k-window of bytes
+ * chars[offsets[s] .. offsets[s+1]) goes into set set_ids[s] (offsets:
+ * n_seqs+1 entries, non-decreasing).  The data are copied before the call
+ * returns.  Requests take effect in submission order: the insert waits for
+ * every batch admitted before it and later requests wait for the insert, so
+ * a query submitted before it is answered without its terms and one
+ * submitted after it with them.  The insert uses atomic ORs into the index
+ * and a device staging buffer of the server (grown to the largest insert).
+ * Returns the request id (>= 0) or RAMBO_EINVAL; rambo_serve_wait on the id
+ * returns the insert's status (RAMBO_ERANGE for a set id >= K: that
+ * sequence is skipped). */
+int64_t rambo_serve_submit_insert(rambo_server_t *s, const uint32_t *set_ids, const uint64_t *offsets,
+                                  uint64_t n_seqs, const uint8_t *chars);
+
 /* Wait up to timeout_us microseconds (-1: no limit) for request id; on
  * success copy its masks (n_reads x W words) and, if nkmers is not NULL, its
  * valid-window counts to host memory, store the time from submission to the
  * results reaching host memory in *latency_ms (if not NULL), and forget the
  * request.  RAMBO_ETIMEDOUT leaves it pending; RAMBO_EINVAL for an unknown
- * id. */
+ * id.  For an insert request nothing is copied (masks and nkmers may be
+ * NULL) and the insert's own status is returned. */
 int rambo_serve_wait(rambo_server_t *s, int64_t id, uint32_t *masks, uint32_t *nkmers, double *latency_ms,
                      int64_t timeout_us);
 

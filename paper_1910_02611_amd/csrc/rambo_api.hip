@@ -813,6 +813,19 @@ extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_by
     return RAMBO_OK;
 }
 
+// Alg. 1 with one atomic OR per bit target, straight into the index.
+int insert_seqs_direct(rambo *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
+                       const uint8_t *chars, uint64_t n_chars, hipStream_t stream)
+{
+    h->index_zero = false;
+    const uint64_t waves = div_up(n_chars, kChunk);
+    const InsertSeqsFn ins = pick_shape<InsertSeqsFn, InsertSeqsK>(h->cfg.R, h->cfg.eta);
+    StageScope sc(h, "k_insert_seqs", stream);
+    hipLaunchKernelGGL(ins, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P, set_ids,
+                       offsets, n_seqs, chars, n_chars, kChunk);
+    return launch_check(h, "rambo_insert_seqs");
+}
+
 // Sequence input needs k-mer terms: a raw-key index refuses it.
 int refuse_raw_keys(rambo *h, const char *what)
 {
@@ -850,13 +863,7 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
         return fail(h, RAMBO_EINVAL, "rambo_insert_seqs: NULL array");
     if (use_partitioned(h, n_chars))
         return insert_seqs_partitioned(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
-    h->index_zero = false;
-    const uint64_t waves = div_up(n_chars, kChunk);
-    const InsertSeqsFn ins = pick_shape<InsertSeqsFn, InsertSeqsK>(h->cfg.R, h->cfg.eta);
-    StageScope sc(h, "k_insert_seqs", stream);
-    hipLaunchKernelGGL(ins, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->P, set_ids,
-                       offsets, n_seqs, chars, n_chars, kChunk);
-    return launch_check(h, "rambo_insert_seqs");
+    return insert_seqs_direct(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
 }
 
 extern "C" int rambo_query_kmers(rambo_t *h, const uint64_t *codes, uint64_t n, uint32_t *out_masks,

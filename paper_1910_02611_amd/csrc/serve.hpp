@@ -6,7 +6,10 @@
 // batch of queued requests (host pack into pinned staging, one H2D copy of
 // offsets and one of bytes, the three work-queue kernels - replayed from a
 // hipGraph captured per slot when asked - and one D2H copy of masks and
-// counts), then sleeps briefly only when there is nothing to do.
+// counts), then sleeps briefly only when there is nothing to do.  An insert
+// request is a barrier in the FIFO: batches stop at it, it runs once every
+// earlier batch has finished, and later requests wait for it, so answers are
+// those of running the requests one by one in submission order.
 #pragma once
 
 #include <chrono>
@@ -32,6 +35,9 @@ struct ServeRequest {
     std::vector<uint32_t> masks;     // n_reads * W
     std::vector<uint32_t> nk;        // n_reads
     bool done = false;
+    bool insert = false;             // an insertion of n_reads sequences into set_ids
+    std::vector<uint32_t> set_ids;
+    int status = RAMBO_OK;
 };
 
 struct ServeSlot {
@@ -69,6 +75,8 @@ struct rambo_server {
     bool stop = false;
     std::thread worker;
     uint64_t n_batches = 0, n_requests = 0, n_reads = 0;
+    void *ins_mem = nullptr;          // device staging of insert requests (grown on demand)
+    uint64_t ins_cap = 0;
     int device = 0;
     bool timing_before = false;
 };
@@ -157,6 +165,8 @@ bool start_batch(rambo_server *sv, ServeSlot &s)
         uint64_t reads = 0, bytes = 0;
         while (!sv->queue.empty()) {
             const auto &r = sv->queue.front();
+            if (r->insert)
+                break;
             const uint64_t rb = r->offsets.back();
             if (reads + r->n_reads > c.max_batch_reads || bytes + rb > c.max_batch_bytes)
                 break;
@@ -219,6 +229,53 @@ void finish_batch(rambo_server *sv, ServeSlot &s)
     s.busy = false;
 }
 
+// Run insert request r (every earlier batch has finished): stage its data on
+// the device, insert with atomics (no scratch), wait, and read the error
+// flags.  Returns the request's status.
+int run_insert(rambo_server *sv, ServeRequest &r)
+{
+    rambo *h = sv->h;
+    const uint64_t n = r.n_reads, nb = r.chars.size();
+    const uint64_t o_off = div_up(4 * n, 256) * 256, o_chars = o_off + div_up(8 * (n + 1), 256) * 256;
+    const uint64_t need = o_chars + div_up(nb, 256) * 256;
+    if (need > sv->ins_cap) {
+        if (sv->ins_mem)
+            (void)hipFree(sv->ins_mem);
+        sv->ins_cap = 0;
+        if (hipMalloc(&sv->ins_mem, need) != hipSuccess) {
+            (void)hipGetLastError();
+            sv->ins_mem = nullptr;
+            return RAMBO_ENOMEM;
+        }
+        sv->ins_cap = need;
+    }
+    uint8_t *d = static_cast<uint8_t *>(sv->ins_mem);
+    hipStream_t st = sv->slots[0].stream;
+    if (hipMemcpyAsync(d, r.set_ids.data(), 4 * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d + o_off, r.offsets.data(), 8 * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (nb && hipMemcpyAsync(d + o_chars, r.chars.data(), nb, hipMemcpyHostToDevice, st) != hipSuccess)) {
+        (void)hipGetLastError();
+        return RAMBO_EHIP;
+    }
+    int rc = RAMBO_OK;
+    if (nb)
+        rc = insert_seqs_direct(h, reinterpret_cast<const uint32_t *>(d), reinterpret_cast<const uint64_t *>(d + o_off),
+                                n, d + o_chars, nb, st);
+    const int rs = rambo_sync_status(h, st);
+    return rc ? rc : rs;
+}
+
+void finish_insert(rambo_server *sv, const std::shared_ptr<ServeRequest> &r)
+{
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->t_done = Clock::now();
+        r->done = true;
+        sv->n_requests += 1;
+    }
+    sv->cv_done.notify_all();
+}
+
 void serve_loop(rambo_server *sv)
 {
     (void)hipSetDevice(sv->device);   // the current device is per thread
@@ -234,6 +291,21 @@ void serve_loop(rambo_server *sv)
             if (!s.busy && start_batch(sv, s))
                 progress = true;
             any_busy = any_busy || s.busy;
+        }
+        if (!any_busy) {
+            std::shared_ptr<ServeRequest> ins;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                if (!sv->queue.empty() && sv->queue.front()->insert) {
+                    ins = sv->queue.front();
+                    sv->queue.pop_front();
+                }
+            }
+            if (ins) {
+                ins->status = run_insert(sv, *ins);
+                finish_insert(sv, ins);
+                continue;
+            }
         }
         if (progress)
             continue;
@@ -315,6 +387,8 @@ extern "C" void rambo_serve_destroy(rambo_server_t *sv)
             (void)hipStreamSynchronize(s.stream);
         free_slot(s);
     }
+    if (sv->ins_mem)
+        (void)hipFree(sv->ins_mem);
     sv->h->timing = sv->timing_before;
     --sv->h->servers;
     delete sv;
@@ -332,6 +406,36 @@ extern "C" int64_t rambo_serve_submit(rambo_server_t *sv, const uint64_t *offset
     r->n_reads = n_reads;
     r->offsets.resize(n_reads + 1);
     for (uint64_t i = 0; i <= n_reads; ++i) {
+        const uint64_t o = offsets[i] < b0 ? b0 : (offsets[i] > b1 ? b1 : offsets[i]);
+        r->offsets[i] = o - b0;
+    }
+    if (b1 > b0)
+        r->chars.assign(chars + b0, chars + b1);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->id = sv->next_id++;
+        r->t_submit = Clock::now();
+        sv->live[r->id] = r;
+        sv->queue.push_back(r);
+    }
+    sv->cv_work.notify_one();
+    return r->id;
+}
+
+extern "C" int64_t rambo_serve_submit_insert(rambo_server_t *sv, const uint32_t *set_ids, const uint64_t *offsets,
+                                             uint64_t n_seqs, const uint8_t *chars)
+{
+    if (!sv || !offsets || !set_ids || n_seqs == 0)
+        return RAMBO_EINVAL;
+    const uint64_t b0 = offsets[0], b1 = offsets[n_seqs];
+    if (b1 < b0 || (b1 > b0 && !chars))
+        return RAMBO_EINVAL;
+    auto r = std::make_shared<ServeRequest>();
+    r->insert = true;
+    r->n_reads = n_seqs;
+    r->set_ids.assign(set_ids, set_ids + n_seqs);
+    r->offsets.resize(n_seqs + 1);
+    for (uint64_t i = 0; i <= n_seqs; ++i) {
         const uint64_t o = offsets[i] < b0 ? b0 : (offsets[i] > b1 ? b1 : offsets[i]);
         r->offsets[i] = o - b0;
     }
@@ -373,7 +477,7 @@ extern "C" int rambo_serve_wait(rambo_server_t *sv, int64_t id, uint32_t *masks,
         std::memcpy(nkmers, r->nk.data(), r->nk.size() * 4);
     if (latency_ms)
         *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
-    return RAMBO_OK;
+    return r->status;
 }
 
 extern "C" int rambo_serve_stats(rambo_server_t *sv, uint64_t *batches, uint64_t *requests, uint64_t *reads,

@@ -98,6 +98,8 @@ EXPORTS = {
     "rambo_serve_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "rambo_serve_destroy": (None, [ctypes.c_void_p]),
     "rambo_serve_submit": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "rambo_serve_submit_insert": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_uint64, ctypes.c_void_p]),
     "rambo_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
     "rambo_serve_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
@@ -373,6 +375,30 @@ class Server:
         if rid < 0:
             raise RamboError(int(rid), "rambo_serve_submit")
         return int(rid)
+
+    def submit_insert(self, set_ids, offsets, chars) -> int:
+        """Queue the insertion of sequences chars[offsets[s]:offsets[s+1]]
+        into sets set_ids[s] (host arrays); it takes effect between the
+        requests submitted before and after it.  Returns the request id (for
+        wait_insert)."""
+        import numpy as np
+        ids = np.ascontiguousarray(set_ids, dtype=np.uint32)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        ch = np.ascontiguousarray(chars, dtype=np.uint8)
+        rid = lib().rambo_serve_submit_insert(self._s, ids.ctypes.data, off.ctypes.data, ids.size,
+                                              ch.ctypes.data if ch.size else None)
+        if rid < 0:
+            raise RamboError(int(rid), "rambo_serve_submit_insert")
+        return int(rid)
+
+    def wait_insert(self, rid: int, timeout_us: int = -1) -> float:
+        """Wait for insert request rid; raises on its error status.  Returns
+        its latency in ms."""
+        lat = ctypes.c_double()
+        rc = lib().rambo_serve_wait(self._s, rid, None, None, ctypes.byref(lat), timeout_us)
+        if rc != OK:
+            raise RamboError(rc, "rambo_serve_wait (insert)")
+        return lat.value
 
     def wait(self, rid: int, n_reads: int, timeout_us: int = -1):
         """(masks [n_reads, W] uint32, window counts [n_reads] uint32,

@@ -26,18 +26,30 @@ def split_requests(batch: synth.SeqBatch) -> list[tuple[np.ndarray, np.ndarray]]
     return [synth.request(batch, r) for r in range(len(ro) - 1)]
 
 
-def run_open_loop(server: rambo.Server, reqs, arrivals: np.ndarray, W: int) -> dict:
+def run_open_loop(server: rambo.Server, reqs, arrivals: np.ndarray, W: int, inserts=None) -> dict:
     """Submit reqs[i] at arrivals[i] seconds (relative to the start); return
-    latencies (ms), throughput and a checksum of the answers."""
+    latencies (ms), throughput and a checksum of the answers.  inserts: an
+    optional list of (time, set_ids, offsets, chars) insert requests
+    submitted at their times among the queries (streaming updates)."""
     n = len(reqs)
     ids = [None] * n
     lag = np.zeros(n)
     ready = [threading.Event() for _ in range(n)]
+    ins = sorted(inserts or [], key=lambda x: x[0])
+    ins_ids = []
     t0 = time.perf_counter() + 0.01
 
     def submitter():
+        j = 0
         for i, (off, ch) in enumerate(reqs):
             due = t0 + arrivals[i]
+            while j < len(ins) and t0 + ins[j][0] <= due:
+                d2 = t0 + ins[j][0]
+                now = time.perf_counter()
+                if d2 > now:
+                    time.sleep(d2 - now)
+                ins_ids.append(server.submit_insert(*ins[j][1:]))
+                j += 1
             now = time.perf_counter()
             if due > now:
                 time.sleep(due - now)
@@ -45,6 +57,8 @@ def run_open_loop(server: rambo.Server, reqs, arrivals: np.ndarray, W: int) -> d
             ids[i] = server.submit(off, ch)
             lag[i] = max(0.0, now - due)
             ready[i].set()
+        for k in range(j, len(ins)):
+            ins_ids.append(server.submit_insert(*ins[k][1:]))
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -61,9 +75,14 @@ def run_open_loop(server: rambo.Server, reqs, arrivals: np.ndarray, W: int) -> d
     t_end = time.perf_counter()
     th.join()
     span = t_end - t0
-    return dict(requests=n, reads=reads, seconds=span, qps=n / span, reads_per_s=reads / span,
-                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                mean_ms=float(lat.mean()), max_submit_lag_ms=float(1e3 * lag.max()), checksum=check)
+    out = dict(requests=n, reads=reads, seconds=span, qps=n / span, reads_per_s=reads / span,
+               p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+               mean_ms=float(lat.mean()), max_submit_lag_ms=float(1e3 * lag.max()), checksum=check)
+    if ins:
+        il = np.array([server.wait_insert(r) for r in ins_ids])
+        out.update(inserts=len(ins), insert_bases=int(sum(int(x[2][-1]) for x in ins)),
+                   insert_p50_ms=float(np.percentile(il, 50)), insert_p99_ms=float(np.percentile(il, 99)))
+    return out
 
 
 def saturated(server: rambo.Server, reqs, W: int) -> dict:
@@ -84,6 +103,28 @@ def sweep(server: rambo.Server, reqs, W: int, fractions, seed: int = 5004, per_p
         r["load"] = f
         points.append(r)
     return dict(saturated=sat, points=points)
+
+
+def insert_stream(seed: int, sets: synth.SeqBatch, n_inserts: int, period_s: float, seqs_per_insert: int,
+                  seq_len: int) -> list:
+    """n_inserts insert requests, one every period_s seconds, each of
+    seqs_per_insert pieces of seq_len bases cut from random set genomes and
+    added to random sets (new terms for those sets)."""
+    rng = synth.rng_for(seed)
+    lens = sets.lengths().astype(np.int64)
+    out = []
+    for j in range(n_inserts):
+        src = rng.integers(0, sets.n, size=seqs_per_insert)
+        parts = []
+        for s in src:
+            L = min(seq_len, int(lens[s]))
+            a = int(sets.offsets[s]) + int(rng.integers(0, int(lens[s]) - L + 1))
+            parts.append(sets.chars[a:a + L])
+        off = np.zeros(seqs_per_insert + 1, np.uint64)
+        np.cumsum([p.size for p in parts], out=off[1:])
+        ids = rng.integers(0, int(sets.set_ids.max()) + 1, size=seqs_per_insert).astype(np.uint32)
+        out.append(((j + 1) * period_s, ids, off, np.concatenate(parts)))
+    return out
 
 
 def main():

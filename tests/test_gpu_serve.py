@@ -127,3 +127,50 @@ def test_errors(served):
             srv.wait(12345, 1, timeout_us=0)
     with pytest.raises(rb.RamboError):        # budget too small for one slot
         rb.Server(g, mem_budget=1024)
+
+
+@pytest.mark.parametrize("use_graphs", [False, True])
+def test_streaming_inserts_between_queries(use_graphs):
+    """Inserts submitted between queries (streaming updates, Sec. 3.1) take
+    effect in submission order: queries before the k-th insert equal the
+    oracle with the first k-1 insert batches, queries after it the oracle
+    with k, however the requests are batched."""
+    cfg = dict(K=64, B=8, R=3, eta=2, k=31, m=1 << 18)
+    sets = synth.genome_sets(4100, K=64, n_ancestors=8, ancestor_len=4000, median_len=2000, min_len=500,
+                             max_len=4000)
+    o, g = make_pair(cfg, seed=77)
+    parts = np.array_split(np.arange(sets.n), 3)     # three insert batches
+    reqs = serve.split_requests(synth.served_requests(4101, sets, 30, max_len=1500))
+    phases = []
+    with rb.Server(g, max_slots=3, use_graphs=use_graphs) as srv:
+        ids = []
+        for k, part in enumerate(parts):
+            sub_off = np.concatenate([[0], np.cumsum(sets.lengths()[part])]).astype(np.uint64)
+            sub_chars = np.concatenate([sets.chars[int(sets.offsets[i]):int(sets.offsets[i + 1])] for i in part])
+            ids.append(("q", k, [srv.submit(off, ch) for off, ch in reqs]))
+            ids.append(("i", k, srv.submit_insert(sets.set_ids[part], sub_off, sub_chars)))
+        ids.append(("q", len(parts), [srv.submit(off, ch) for off, ch in reqs]))
+        for kind, k, rid in ids:
+            if kind == "i":
+                assert srv.wait_insert(rid, timeout_us=TIMEOUT_US) >= 0
+            else:
+                phases.append([srv.wait(r, len(off) - 1, timeout_us=TIMEOUT_US)[:2] for r, (off, _) in zip(rid, reqs)])
+        # a bad set id: the insert reports it, the server goes on
+        bad = srv.submit_insert(np.array([cfg["K"]], np.uint32), np.array([0, 40], np.uint64),
+                                np.frombuffer(b"ACGT" * 10, np.uint8))
+        with pytest.raises(rb.RamboError) as e:
+            srv.wait_insert(bad, timeout_us=TIMEOUT_US)
+        assert e.value.code == rb.ERANGE
+        after = srv.wait(srv.submit(*reqs[0]), len(reqs[0][0]) - 1, timeout_us=TIMEOUT_US)[:2]
+    for k, got in enumerate(phases):
+        if k > 0:
+            part = parts[k - 1]
+            assert o.insert_seqs(sets.set_ids[part], np.concatenate([[0], np.cumsum(sets.lengths()[part])]),
+                                 np.concatenate([sets.chars[int(sets.offsets[i]):int(sets.offsets[i + 1])]
+                                                 for i in part]), 8) == 0
+        want = []
+        for off, ch in reqs:
+            m, nk = o.query_seqs(off, ch, nthreads=8)
+            want.append((m, nk.astype(np.uint32)))
+        check(got, want)
+    check([after], [want[0]])
