@@ -112,6 +112,53 @@ __global__ __launch_bounds__(kBlock) void k_fold(const uint32_t *src, uint32_t *
     dst[t] = out;
 }
 
+// Folding over for new rows of 32 or 64 bits (SW2 = 1 or 2 words; then
+// S = 2 S2): thread per 4 words of the new index (one 16-byte store; wpr2 is
+// a multiple of 4, so they share a repetition), which come from the 8 old
+// words at twice their offset (two aligned 16-byte loads; a vector that
+// starts past the m rows in use is not read and folds to 0).  Each old row
+// as a 64- or 128-bit value V gives the new row (V | V >> half) below half.
+template <int SW2>
+__global__ __launch_bounds__(kBlock) void k_fold_narrow(const uint32_t *src, uint32_t *dst, uint32_t R, uint64_t m,
+                                                        uint64_t wpr, uint64_t wpr2, uint32_t half)
+{
+    static_assert(SW2 == 1 || SW2 == 2, "narrow rows");
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t per_rep = wpr2 / 4;
+    if (t >= (uint64_t)R * per_rep)
+        return;
+    const uint64_t r = t / per_rep, w0 = (t % per_rep) * 4;
+    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src + r * wpr);
+    const uint64_t used = 2 * m * SW2;   // old words holding rows 0 .. m-1
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    const u32x4 a = 2 * w0 < used ? s4[w0 / 2] : zero;
+    const u32x4 b = 2 * w0 + 4 < used ? s4[w0 / 2 + 1] : zero;
+    const uint32_t o[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t v[4];
+    if constexpr (SW2 == 1) {
+        // S = 64, half in [17, 32]
+        const uint64_t mask = (1ull << half) - 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t V = (uint64_t)o[2 * j] | ((uint64_t)o[2 * j + 1] << 32);
+            v[j] = (uint32_t)((V | (V >> half)) & mask);
+        }
+    } else {
+        // S = 128, half in [33, 64]
+        const uint64_t mask = half < 64 ? (1ull << half) - 1 : ~0ull;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint64_t L = (uint64_t)o[4 * q] | ((uint64_t)o[4 * q + 1] << 32);
+            const uint64_t H = (uint64_t)o[4 * q + 2] | ((uint64_t)o[4 * q + 3] << 32);
+            const uint64_t hi = half < 64 ? (L >> half) | (H << (64 - half)) : H;
+            const uint64_t N = (L | hi) & mask;
+            v[2 * q] = (uint32_t)N;
+            v[2 * q + 1] = (uint32_t)(N >> 32);
+        }
+    }
+    reinterpret_cast<u32x4 *>(dst + r * wpr2)[w0 / 4] = u32x4{v[0], v[1], v[2], v[3]};
+}
+
 __global__ __launch_bounds__(kBlock) void k_phi_mod(uint16_t *phi, uint64_t n, uint32_t half)
 {
     const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;

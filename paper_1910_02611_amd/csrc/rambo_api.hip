@@ -1034,8 +1034,15 @@ extern "C" int rambo_fold(rambo_t *h, hipStream_t stream)
     const uint64_t n2 = (uint64_t)c.R * wpr2;
     {
         StageScope sc(h, "k_fold", stream);
-        hipLaunchKernelGGL(k_fold, dim3((uint32_t)div_up(n2, kBlock)), dim3(kBlock), 0, stream, h->index, index2, c.R,
-                           c.m, h->S, S2, h->words_per_rep, wpr2, half);
+        if (S2 == 32 && h->S == 64)
+            hipLaunchKernelGGL(k_fold_narrow<1>, dim3((uint32_t)div_up(n2 / 4, kBlock)), dim3(kBlock), 0, stream,
+                               h->index, index2, c.R, c.m, h->words_per_rep, wpr2, half);
+        else if (S2 == 64 && h->S == 128)
+            hipLaunchKernelGGL(k_fold_narrow<2>, dim3((uint32_t)div_up(n2 / 4, kBlock)), dim3(kBlock), 0, stream,
+                               h->index, index2, c.R, c.m, h->words_per_rep, wpr2, half);
+        else
+            hipLaunchKernelGGL(k_fold, dim3((uint32_t)div_up(n2, kBlock)), dim3(kBlock), 0, stream, h->index, index2,
+                               c.R, c.m, h->S, S2, h->words_per_rep, wpr2, half);
     }
     const uint64_t nphi = (uint64_t)c.R * c.K;
     hipLaunchKernelGGL(k_phi_mod, dim3((uint32_t)div_up(nphi, kBlock)), dim3(kBlock), 0, stream, h->phi, nphi, half);

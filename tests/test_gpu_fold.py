@@ -17,6 +17,8 @@ SHAPES = [
     dict(K=70, B=16, R=3, eta=2, k=31, m=1 << 12),    # S 16 -> 8
     dict(K=100, B=50, R=4, eta=2, k=31, m=5000),      # S 64 -> 32, 25 of 32 columns used
     dict(K=130, B=64, R=2, eta=3, k=31, m=1 << 12),   # S 64 -> 32, all columns used
+    dict(K=300, B=100, R=3, eta=2, k=31, m=3001),     # S 128 -> 64, 50 of 64 columns used
+    dict(K=300, B=128, R=2, eta=2, k=31, m=1 << 12),  # S 128 -> 64, all columns used
     dict(K=400, B=200, R=5, eta=2, k=31, m=1 << 12),  # S 256 -> 128
     dict(K=1500, B=1000, R=3, eta=2, k=31, m=2048),   # S 1024 -> 512
 ]
