@@ -664,63 +664,81 @@ __device__ __forceinline__ bool any_rep_empty(const uint32_t *g, uint32_t R, uin
     return false;
 }
 
-// Answer words of one query from the partition instead of the cell masks:
-// set i is in the answer iff its cell phi_r(i) is positive in every
-// repetition (the union-then-intersection of Alg. 2, evaluated per set).
-// The same bits as the cell masks give, but the work is K*R lookups whatever
-// the number of positive cells, which wins when many cells are positive and
-// many negative (a term held by about half of the sets).  The whole wave
-// takes one query: 64 sets per step, 8 steps of loads in flight; lane l
-// keeps word l of a 2048-set stripe and stores it.  g: the query's R x SW
-// group-mask words.  R_T > 0: R fixed at compile time.
-template <int R_T>
-__device__ __forceinline__ void expand_by_partition(const Params &P, const uint32_t *g, uint32_t SW, uint32_t R,
-                                                    uint32_t *o, uint32_t lane)
+// Answer words from the partition instead of the cell masks: set i is in
+// the answer iff its cell phi_r(i) is positive in every repetition (the
+// union-then-intersection of Alg. 2, evaluated per set).  The same bits as
+// the cell masks give, but the work is K*R lookups whatever the number of
+// positive cells, which wins when many cells are positive and many negative
+// (a term held by about half of the sets).  The whole wave takes up to NQ
+// queries at once, so each phi load serves all of them: 64 sets per step, 8
+// steps of loads in flight; lane l keeps word l of a 2048-set stripe of each
+// query and stores it.  g[q]: query q's R x SW group-mask words, o[q] its
+// answer; n <= NQ queries (wave-uniform).  R_T > 0: R fixed at compile time.
+template <int R_T, int NQ>
+__device__ __forceinline__ void expand_by_partition(const Params &P, const uint32_t *const (&g)[NQ], uint32_t n,
+                                                    uint32_t SW, uint32_t R, uint32_t *const (&o)[NQ], uint32_t lane)
 {
     constexpr int TB = 8;
     constexpr int RN = R_T > 0 ? R_T : 1;
     for (uint32_t base = 0; base < P.K; base += 64 * 32) {
-        uint32_t mine = 0;
+        uint32_t mine[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            mine[q] = 0u;
         const uint32_t tmax = min(32u, (P.K - base + 63) / 64);
         for (uint32_t t0 = 0; t0 < tmax; t0 += TB) {
-            bool in[TB];
-            if constexpr (R_T > 0) {
-                uint32_t cell[TB][RN];
+            bool valid[TB];
+            uint32_t cell[TB][RN];
 #pragma unroll
-                for (int u = 0; u < TB; ++u) {
-                    const uint32_t i = base + (t0 + u) * 64 + lane;
-                    in[u] = t0 + u < tmax && i < P.K;
-#pragma unroll
-                    for (int r = 0; r < RN; ++r)
-                        cell[u][r] = in[u] ? P.phi[(uint64_t)r * P.K + i] : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < TB; ++u)
+            for (int u = 0; u < TB; ++u) {
+                const uint32_t i = base + (t0 + u) * 64 + lane;
+                valid[u] = t0 + u < tmax && i < P.K;
+                if constexpr (R_T > 0) {
 #pragma unroll
                     for (int r = 0; r < RN; ++r)
-                        in[u] = in[u] && ((g[r * SW + (cell[u][r] >> 5)] >> (cell[u][r] & 31)) & 1u);
-            } else {
-#pragma unroll
-                for (int u = 0; u < TB; ++u) {
-                    const uint32_t i = base + (t0 + u) * 64 + lane;
-                    in[u] = t0 + u < tmax && i < P.K;
-                    for (uint32_t r = 0; r < R && in[u]; ++r) {
-                        const uint32_t b = P.phi[(uint64_t)r * P.K + i];
-                        in[u] = (g[r * SW + (b >> 5)] >> (b & 31)) & 1u;
-                    }
+                        cell[u][r] = valid[u] ? P.phi[(uint64_t)r * P.K + i] : 0u;
                 }
             }
 #pragma unroll
-            for (int u = 0; u < TB; ++u) {
-                const uint64_t m = __ballot(in[u]);
-                if ((lane >> 1) == t0 + u)
-                    mine = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
+            for (int q = 0; q < NQ; ++q) {
+                if ((uint32_t)q >= n)
+                    break;
+                const uint32_t *gq = g[q];
+#pragma unroll
+                for (int u = 0; u < TB; ++u) {
+                    bool in = valid[u];
+                    if constexpr (R_T > 0) {
+#pragma unroll
+                        for (int r = 0; r < RN; ++r)
+                            in = in && ((gq[r * SW + (cell[u][r] >> 5)] >> (cell[u][r] & 31)) & 1u);
+                    } else {
+                        const uint32_t i = base + (t0 + u) * 64 + lane;
+                        for (uint32_t r = 0; r < R && in; ++r) {
+                            const uint32_t b = P.phi[(uint64_t)r * P.K + i];
+                            in = (gq[r * SW + (b >> 5)] >> (b & 31)) & 1u;
+                        }
+                    }
+                    const uint64_t m = __ballot(in);
+                    if ((lane >> 1) == t0 + u)
+                        mine[q] = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
+                }
             }
         }
         const uint32_t w = base / 32 + lane;
-        if (w < P.W)
-            o[w] = mine;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if ((uint32_t)q < n && w < P.W)
+                o[q][w] = mine[q];
     }
+}
+
+template <int R_T>
+__device__ __forceinline__ void expand_by_partition(const Params &P, const uint32_t *g, uint32_t SW, uint32_t R,
+                                                    uint32_t *o, uint32_t lane)
+{
+    const uint32_t *const g1[1] = {g};
+    uint32_t *const o1[1] = {o};
+    expand_by_partition<R_T, 1>(P, g1, 1, SW, R, o1, lane);
 }
 
 // Cells walked per answer by expand_answer_wave (K <= 32 W, so the cell
@@ -736,10 +754,12 @@ constexpr uint32_t kSegs = RAMBO_MAX_R + 1;
 // ORs those cells' mask words (complemented for a negative list) and ANDs
 // over repetitions; otherwise expand_by_partition.  lst: kListCap entries,
 // seg: kSegs entries, both the wave's own.
+// With defer given, a query for the partition path is not expanded here:
+// *defer is set and the caller expands it (with others, sharing the loads).
 template <int R_T>
 __device__ __forceinline__ void expand_answer_wave(const Params &P, const uint32_t *G, uint32_t R, uint32_t SW,
                                                    bool empty, uint32_t *o, uint32_t lane, uint16_t *lst,
-                                                   uint16_t *seg)
+                                                   uint16_t *seg, bool *defer = nullptr)
 {
     uint32_t cost = 0, neg = 0;
     if (!empty) {
@@ -753,7 +773,10 @@ __device__ __forceinline__ void expand_answer_wave(const Params &P, const uint32
         return;
     }
     if (cost > kListCap || partition_cheaper(P, cost, R)) {
-        expand_by_partition<R_T>(P, G, SW, R, o, lane);
+        if (defer)
+            *defer = true;
+        else
+            expand_by_partition<R_T>(P, G, SW, R, o, lane);
         return;
     }
     uint32_t pos = 0;
@@ -883,14 +906,39 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
     if constexpr (SW > 4) {
         // Wide rows (few queries per wave): the whole wave expands one query
         // at a time (expand_answer_wave).
+        // Answers for the partition path are deferred and then expanded
+        // up to 4 at a time, sharing the phi loads.
         __shared__ uint16_t lst[kWavesPerBlock * kListCap];
         __shared__ uint16_t seg[kWavesPerBlock * kSegs];
+        uint64_t deferred = 0;
         for (uint32_t qi = 0; qi < (uint32_t)QPW; ++qi) {
             const uint64_t q2 = qbase + qi;
             if (q2 >= n)
                 break;
+            bool d = false;
             expand_answer_wave<R_T>(P, gs + (wv * QPW + qi) * RMAX * SW, R, SW, false, out + q2 * P.W, lane,
-                                    lst + wv * kListCap, seg + wv * kSegs);
+                                    lst + wv * kListCap, seg + wv * kSegs, &d);
+            if (d)
+                deferred |= 1ull << qi;
+        }
+        constexpr int NQ = 4;
+        while (deferred) {
+            const uint32_t *gq[NQ];
+            uint32_t *oq[NQ];
+            uint32_t k = 0;
+            for (; k < (uint32_t)NQ && deferred; ++k) {
+                const uint32_t qi = (uint32_t)__builtin_ctzll(deferred);
+                deferred &= deferred - 1;
+                gq[k] = gs + (wv * QPW + qi) * RMAX * SW;
+                oq[k] = out + (qbase + qi) * P.W;
+            }
+            for (uint32_t j = k; j < (uint32_t)NQ; ++j) {
+                gq[j] = gq[0];
+                oq[j] = oq[0];
+            }
+            const uint32_t *const (&gc)[NQ] = gq;
+            uint32_t *const (&oc)[NQ] = oq;
+            expand_by_partition<R_T, NQ>(P, gc, k, SW, R, oc, lane);
         }
         return;
     }
