@@ -19,7 +19,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import re
 import os
 import sys
 import time
@@ -96,11 +95,23 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock: 39
 TRAFFIC_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_mid.json")
 
 
-def kernel_rooflines(kernels, n_ins, n_queries, RE, S, W, index_bytes, fresh=True):
+def measured_traffic(names: dict) -> dict:
+    """HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE) from the
+    committed rocprofv3 summary, for stage name -> kernel name as profiled;
+    empty when the summary is missing or the kernel sources changed since."""
+    from paper_1910_02611_amd.profsum import load_traffic
+    t = load_traffic(TRAFFIC_JSON)
+    if t is None:
+        return {}
+    return {stage: t["kernels"][k]["bytes"] for stage, k in names.items() if k in t["kernels"]}
+
+
+def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh=True):
     """Roofline entry of each timed kernel: algorithmic work per launch over
     its measured duration.  fresh: the insert went into an all-zero index,
     so stage C writes the index without reading it."""
-    from paper_1910_02611_amd.profsum import load_traffic
+    RE = R * eta
+    SW = max(1, S // 32)
     targets = n_ins * RE
     work = {
         "k_bin_windows": ("alu", n_ins * (ALU_OPS_PER_WINDOW + RE * ALU_OPS_PER_TARGET), "TOP/s",
@@ -113,12 +124,10 @@ def kernel_rooflines(kernels, n_ins, n_queries, RE, S, W, index_bytes, fresh=Tru
         "k_query_kmers": ("hbm", n_queries * (RE * max(SECTOR, S // 8) + 4 * W + 8), "GB/s",
                           "R*eta row sectors + K-bit answer + code per query"),
     }
-    measured = load_traffic(TRAFFIC_JSON)
-    launch_bytes = {}
-    if measured is not None:
-        for name, v in measured["kernels"].items():
-            base = re.sub(r"<.*", "", name).replace("_hold", "")
-            launch_bytes[base] = v["bytes"]
+    launch_bytes = measured_traffic({"k_bin_windows": "k_bin_windows_hold<%d, %d>" % (R, eta),
+                                     "k_bin_regions": "k_bin_regions", "k_apply_regions": "k_apply_regions",
+                                     "k_insert_seqs": "k_insert_seqs<%d, %d>" % (R, eta),
+                                     "k_query_kmers": "k_query_kmers<%d, %d, %d>" % (SW, R, eta)})
     out = []
     for name, ms in kernels.items():
         if name not in work:
@@ -338,13 +347,16 @@ def documents(n_queries: int, steps: int = 3):
     work = {"k_insert_kmers": (n_keys * RE * 2 * SECTOR, "one 64-B sector read-modify-write per bit target"),
             "k_query_kmers": (q.size * (RE * max(SECTOR, S // 8) + 4 * W + 8),
                               "R*eta rows of S/8 bytes + K-bit answer + key per query")}
+    traffic = measured_traffic({"k_insert_kmers": "k_insert_kmers",
+                                "k_query_kmers": "k_query_kmers<%d, %d, %d>" % (max(1, S // 32), cfg["R"], cfg["eta"])})
     roofs = []
     for name, (amount, what) in work.items():
         ms = kernels.get(name)
         if ms:
             a = amount / (ms / 1e3) / 1e9
             roofs.append({"kernel": name, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": a / HBM_PEAK_GBS, "ms": ms, "work_per_launch": amount, "work": what})
+                          "frac": a / HBM_PEAK_GBS, "traffic": traffic.get(name), "ms": ms,
+                          "work_per_launch": amount, "work": what})
     res = {"workload": "word unigrams: K=17618 documents, B=2000, R=2, m=200000, eta=4 (raw 64-bit keys)",
            "keys": n_keys, "queries": int(q.size), "index_bytes": g.index_bytes,
            "insert_ms": t_ins, "keys_inserted_per_s": n_keys / t_ins * 1e3,
@@ -371,13 +383,15 @@ def fold_timing(g):
     g.set_timing(False)
     moved = old_bytes + g.index_bytes
     achieved = moved / (ms / 1e3) / 1e9
+    kname = {32: "k_fold_narrow<1>", 64: "k_fold_narrow<2>"}.get(g.row_bits, "k_fold")
     log("fold B %d -> %d: k_fold %.3f ms (%.0f GB/s, %.1f%% of HBM peak), call %.1f ms"
         % (B, g.B, ms, achieved, 100 * achieved / HBM_PEAK_GBS, wall * 1e3))
     return {"B_from": B, "B_to": g.B, "index_bytes_from": old_bytes, "index_bytes_to": g.index_bytes,
             "call_ms": wall * 1e3,
-            "roofline": {"kernel": "k_fold", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "ms": ms, "work_per_launch": moved,
-                         "work": "old index read once + folded index written once"}}
+            "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic({"k_fold": kname}).get("k_fold"), "ms": ms,
+                         "work_per_launch": moved, "work": "old index read once + folded index written once"}}
 
 
 def main():
@@ -430,7 +444,7 @@ def main():
         % (ms_per_step, t_clear, t_ins, ins_per_s, t_q, q_per_s))
 
     R, eta, S, W = cfg["R"], cfg["eta"], g.row_bits, g.W
-    roofs = kernel_rooflines(kernels, n_ins, q.n, R * eta, S, W, g.index_bytes)
+    roofs = kernel_rooflines(kernels, n_ins, q.n, R, eta, S, W, g.index_bytes)
     for r in roofs:
         log("  %-16s %8.3f ms  %-3s %.3g %s (%.1f%% of %.4g)" % (r["kernel"], r["ms"], r["bound"], r["achieved"],
                                                                r["unit"], 100 * r["frac"], r["peak"]))

@@ -64,6 +64,7 @@ extern "C" {
 #define RAMBO_EOVERFLOW (-75)  /* output capacity too small */
 #define RAMBO_EHIP (-1000)     /* HIP runtime error; see rambo_last_error */
 #define RAMBO_ECODE (-1001)    /* a k-mer code >= 4^k was seen on the device */
+#define RAMBO_EIO (-5)         /* file could not be opened, read or written */
 
 /* Test hook: phi_r(i) = i mod B for every r (with B = K and R = 1 the index
  * is a plain array of Bloom filters, the special case of Sec. 4.3). */
@@ -235,6 +236,22 @@ int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max_stages);
  * this handle before the fold hold the old index and must be captured
  * again. */
 int rambo_fold(rambo_t *h, hipStream_t stream);
+
+/* Checkpoint: write the index to the file at path (created or replaced):
+ * a header with the configuration and layout, the partition phi (R x K u16)
+ * and the R x words_per_rep index words, all little-endian, through a
+ * pinned host buffer.  Waits for the work on `stream` first.  The streaming
+ * updates of Sec. 3.1 can resume from it.  RAMBO_EIO on a file error. */
+int rambo_save(rambo_t *h, const char *path, hipStream_t stream);
+
+/* Resume: create an index from a file rambo_save wrote (the same
+ * configuration, hash multipliers from its seed, its partition and its
+ * bits).  Synchronous.  RAMBO_EIO for a missing or short file, RAMBO_EINVAL
+ * for a file that is not an index or does not match its configuration. */
+int rambo_load(const char *path, rambo_t **out);
+
+/* The configuration of the index (after folding, B is the folded one). */
+int rambo_get_config(const rambo_t *h, rambo_config *out);
 
 /* Zero every Bloom filter (an empty index with the same hashes). */
 int rambo_clear(rambo_t *h, hipStream_t stream);

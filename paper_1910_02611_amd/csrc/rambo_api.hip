@@ -617,6 +617,26 @@ int build_member_lists(rambo *h)
     return RAMBO_OK;
 }
 
+// SetIDs tables from the current phi and B: the cell masks (zeroed, then
+// k_build_cellmask) and the member lists.  Synchronous.
+int rebuild_tables(rambo *h)
+{
+    const rambo_config &c = h->cfg;
+    if (h->member_off)
+        (void)hipFree(h->member_off);
+    if (h->members)
+        (void)hipFree(h->members);
+    h->member_off = h->members = nullptr;
+    int rc = hip_check(h, hipMemset(h->cellmask, 0, (uint64_t)c.R * c.B * h->W * 4), "tables");
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(k_build_cellmask, dim3((uint32_t)div_up((uint64_t)c.R * h->W, kBlock)), dim3(kBlock), 0, 0,
+                       h->phi, c.K, c.B, c.R, h->W, h->cellmask);
+    if ((rc = launch_check(h, "tables")) || (rc = hip_check(h, hipDeviceSynchronize(), "tables")))
+        return rc;
+    return build_member_lists(h);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -1077,19 +1097,136 @@ extern "C" int rambo_fold(rambo_t *h, hipStream_t stream)
         h->rq_mem = nullptr;
         h->rq_cap = 0;
     }
-    if (h->member_off)
-        (void)hipFree(h->member_off);
-    if (h->members)
-        (void)hipFree(h->members);
-    h->member_off = h->members = nullptr;
-    const uint64_t cm_words = (uint64_t)c.R * half * h->W;
-    if ((rc = hip_check(h, hipMemset(h->cellmask, 0, cm_words * 4), "rambo_fold")))
+    return rebuild_tables(h);
+}
+
+// ------------------------------------------------------------ save / load
+
+namespace {
+
+constexpr char kFileMagic[8] = {'R', 'A', 'M', 'B', 'O', 'I', 'X', '1'};
+
+struct FileHeader {
+    char magic[8];
+    rambo_config cfg;
+    uint64_t words_per_rep;
+    uint64_t index_bytes;
+    uint32_t row_bits;
+    uint32_t reserved;
+};
+
+// Copy n bytes between the device and a file through a pinned bounce buffer.
+int stream_file(rambo *h, FILE *f, void *dev, uint64_t n, bool to_file)
+{
+    constexpr uint64_t kChunk = 64ull << 20;
+    void *buf = nullptr;
+    if (hipHostMalloc(&buf, std::min(n, kChunk) + 1, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, RAMBO_ENOMEM, "save/load: pinned buffer");
+    }
+    int rc = RAMBO_OK;
+    for (uint64_t o = 0; o < n && !rc; o += kChunk) {
+        const uint64_t len = std::min(kChunk, n - o);
+        uint8_t *d = static_cast<uint8_t *>(dev) + o;
+        if (to_file) {
+            rc = hip_check(h, hipMemcpy(buf, d, len, hipMemcpyDeviceToHost), "rambo_save");
+            if (!rc && std::fwrite(buf, 1, len, f) != len)
+                rc = fail(h, RAMBO_EIO, "rambo_save: write failed");
+        } else {
+            if (std::fread(buf, 1, len, f) != len)
+                rc = fail(h, RAMBO_EIO, "rambo_load: file too short");
+            else
+                rc = hip_check(h, hipMemcpy(d, buf, len, hipMemcpyHostToDevice), "rambo_load");
+        }
+    }
+    (void)hipHostFree(buf);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int rambo_save(rambo_t *h, const char *path, hipStream_t stream)
+{
+    if (!h || !path)
+        return RAMBO_EINVAL;
+    int rc = hip_check(h, hipStreamSynchronize(stream), "rambo_save");
+    if (rc)
         return rc;
-    hipLaunchKernelGGL(k_build_cellmask, dim3((uint32_t)div_up((uint64_t)c.R * h->W, kBlock)), dim3(kBlock), 0, 0,
-                       h->phi, c.K, half, c.R, h->W, h->cellmask);
-    if ((rc = launch_check(h, "rambo_fold")) || (rc = hip_check(h, hipDeviceSynchronize(), "rambo_fold")))
+    FILE *f = std::fopen(path, "wb");
+    if (!f)
+        return fail(h, RAMBO_EIO, std::string("rambo_save: cannot open ") + path);
+    FileHeader hd{};
+    std::memcpy(hd.magic, kFileMagic, 8);
+    hd.cfg = h->cfg;
+    hd.words_per_rep = h->words_per_rep;
+    hd.index_bytes = h->index_bytes;
+    hd.row_bits = h->S;
+    if (std::fwrite(&hd, sizeof hd, 1, f) != 1)
+        rc = fail(h, RAMBO_EIO, "rambo_save: write failed");
+    if (!rc)
+        rc = stream_file(h, f, h->phi, (uint64_t)h->cfg.R * h->cfg.K * 2, true);
+    if (!rc)
+        rc = stream_file(h, f, h->index, h->index_bytes, true);
+    if (std::fclose(f) != 0 && !rc)
+        rc = fail(h, RAMBO_EIO, "rambo_save: close failed");
+    return rc;
+}
+
+extern "C" int rambo_load(const char *path, rambo_t **out)
+{
+    if (!path || !out)
+        return fail(nullptr, RAMBO_EINVAL, "rambo_load: NULL argument");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return fail(nullptr, RAMBO_EIO, std::string("rambo_load: cannot open ") + path);
+    FileHeader hd{};
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kFileMagic, 8) != 0) {
+        std::fclose(f);
+        return fail(nullptr, RAMBO_EINVAL, "rambo_load: not a RAMBO index file");
+    }
+    rambo_t *h = nullptr;
+    int rc = rambo_create(&hd.cfg, &h);
+    if (rc) {
+        std::fclose(f);
         return rc;
-    return build_member_lists(h);
+    }
+    if (hd.words_per_rep != h->words_per_rep || hd.index_bytes != h->index_bytes || hd.row_bits != h->S) {
+        std::fclose(f);
+        rambo_destroy(h);
+        return fail(nullptr, RAMBO_EINVAL, "rambo_load: layout does not match the configuration");
+    }
+    rc = stream_file(h, f, h->phi, (uint64_t)hd.cfg.R * hd.cfg.K * 2, false);
+    if (!rc) {
+        // the partition as saved (it may differ from the one the seed gives,
+        // e.g. after folding); it must stay within the cells
+        std::vector<uint16_t> phi((size_t)hd.cfg.R * hd.cfg.K);
+        rc = hip_check(h, hipMemcpy(phi.data(), h->phi, phi.size() * 2, hipMemcpyDeviceToHost), "rambo_load");
+        for (size_t i = 0; !rc && i < phi.size(); ++i)
+            if (phi[i] >= hd.cfg.B)
+                rc = fail(h, RAMBO_EINVAL, "rambo_load: partition value out of range");
+    }
+    if (!rc)
+        rc = stream_file(h, f, h->index, h->index_bytes, false);
+    std::fclose(f);
+    if (!rc)
+        rc = rebuild_tables(h);
+    if (rc) {
+        g_create_error = h->last_error;
+        rambo_destroy(h);
+        return rc;
+    }
+    h->index_zero = false;
+    *out = h;
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_get_config(const rambo_t *h, rambo_config *out)
+{
+    if (!h || !out)
+        return RAMBO_EINVAL;
+    *out = h->cfg;
+    return RAMBO_OK;
 }
 
 extern "C" int rambo_clear(rambo_t *h, hipStream_t stream)

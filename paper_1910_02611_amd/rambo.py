@@ -18,6 +18,7 @@ OK = 0
 EINVAL = -22
 ENOMEM = -12
 ERANGE = -34
+EIO = -5
 EOVERFLOW = -75
 EHIP = -1000
 ECODE = -1001
@@ -82,6 +83,9 @@ EXPORTS = {
     "rambo_get_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_fold": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p]),
+    "rambo_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rambo_get_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rambo_copy_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -168,6 +172,28 @@ class Rambo:
             raise RamboError(rc, "rambo_create: " + (lib().rambo_last_error(None) or b"").decode())
         self._h = h
         self._refresh_info()
+
+    @classmethod
+    def load(cls, path: str) -> "Rambo":
+        """An index resumed from a file written by save()."""
+        if not torch.cuda.is_available():
+            raise RuntimeError("Rambo needs a GPU")
+        h = ctypes.c_void_p()
+        rc = lib().rambo_load(str(path).encode(), ctypes.byref(h))
+        if rc != OK:
+            raise RamboError(rc, "rambo_load: " + (lib().rambo_last_error(None) or b"").decode())
+        self = cls.__new__(cls)
+        self._h = h
+        cfg = Config()
+        lib().rambo_get_config(h, ctypes.byref(cfg))
+        self.K, self.B, self.R, self.eta, self.k, self.m, self.seed = (cfg.K, cfg.B, cfg.R, cfg.eta, cfg.k, cfg.m,
+                                                                        cfg.seed)
+        self._refresh_info()
+        return self
+
+    def save(self, path: str, stream=None):
+        """Checkpoint the index to a file (waits for the work on stream)."""
+        self._check(lib().rambo_save(self._h, str(path).encode(), _stream(stream)), "rambo_save")
 
     # lifetime -------------------------------------------------------------
     def close(self):
