@@ -185,9 +185,16 @@ def cpu_baseline(sets, q, cfg, query_budget_s: float = 12.0):
         n_q += min(chunk, nq - pos)
         pos = (pos + chunk) % nq
     t_q = time.perf_counter() - t0
+    # one host thread (the setting of the paper's own timings), briefly
+    n1, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < 2.0:
+        o.query_kmers(codes[n1 % nq:n1 % nq + 20_000], 1)
+        n1 += min(20_000, nq - n1 % nq)
+    t1 = time.perf_counter() - t0
     o.close()
     return {
         "value": n_q / t_q, "unit": "k-mer queries/s", "cores": nthreads, "kind": "oracle",
+        "value_1_thread": n1 / t1,
         "sample": "%d k-mer queries (the first %d of the same stream, cycled) against the oracle index of "
                   "the first %d of %d sets; oracle insert of those sets: %d inserts in %.1f s (%.3g inserts/s)"
                   % (n_q, nq, n_sets, sets.n, n_ins, t_ins, n_ins / t_ins),

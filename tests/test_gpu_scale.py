@@ -101,12 +101,12 @@ def workload(request):
 def test_scale_rows_and_sampled_answers(workload):
     name, cfg, sets, g, o, rec = workload
     if name in ("served", "mini"):
-        reads = synth.served_requests(4104, sets, 40)      # about 1 300 reads of 150-5 000 bp
+        reads = synth.served_requests(4104, sets, 120)     # about 4 000 reads of 150-5 000 bp
         rd = synth.SeqBatch(reads.chars, reads.offsets)
     else:
-        rd = synth.reads(3105, sets, 600, median_len=150, min_len=150, max_len=150, substr_frac=0.8,
+        rd = synth.reads(3105, sets, 10_000, median_len=150, min_len=150, max_len=150, substr_frac=0.8,
                          read_sub_rate=0.01)
-    q = synth.kmer_queries(3106, sets, 3000, cfg["k"])
+    q = synth.kmer_queries(3106, sets, 100_000, cfg["k"])
     keys = np.unique(np.concatenate([o.window_keys(rd.offsets, rd.chars), o.window_keys(q.offsets, q.chars)]))
     nthreads = min(os.cpu_count() or 1, 16)
     t = time.time()
@@ -150,10 +150,11 @@ def test_scale_serving(workload):
     name, cfg, sets, g, o, rec = workload
     if name not in ("served", "mini"):
         pytest.skip("serving is measured on the served workload")
-    reqs = serve.split_requests(synth.served_requests(4004, sets, 4000))
+    # 10 000 requests per point, 8 points from 10% to 120% of the saturated rate
+    reqs = serve.split_requests(synth.served_requests(4004, sets, 10_000))
     with rb.Server(g, max_slots=4, use_graphs=True) as srv:
         serve.saturated(srv, reqs[:200], g.W)
-        res = serve.sweep(srv, reqs, g.W, [0.25, 0.5, 0.8, 1.0])
+        res = serve.sweep(srv, reqs, g.W, [0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2])
         res["server"] = srv.stats()
     keep = ("load", "offered_qps", "qps", "reads_per_s", "p50_ms", "p99_ms")
     log(rec, serving_saturated={k: res["saturated"][k] for k in ("qps", "reads_per_s", "p50_ms", "p99_ms")},
