@@ -398,8 +398,8 @@ int orc_insert_kmers(orc_index *h, const uint32_t *set_ids, const uint64_t *offs
             if (h->phi[(size_t)r * h->K + set_ids[s]] != cell)
                 continue;
             for (uint64_t p = offsets[s]; p < offsets[s + 1]; p++) {
-                uint64_t x;
-                orc_term(h, codes[p], &x);
+                uint64_t x = 0;
+                orc_term(h, codes[p], &x);   /* every code was checked above */
                 orc_bf_insert(h, r, cell, x);
             }
         }
