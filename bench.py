@@ -7,11 +7,19 @@ substitutions (~2.7e8 31-mers); index B = 50, R = 4, m = 2^28 bits per cell,
 eta = 2 (8 GiB bit-sliced); 1e7 single 31-mer queries, half drawn from the
 inserted genomes, half uniform random.
 
-One step = zero the index + insert every set (k_insert_seqs) + answer every
-query (k_query_kmers).  Inputs are resident in device memory before timing.
-`value` is k-mer queries per second of the query phase; inserts per second
-of the insert phase are reported beside it.  Phase times come from HIP
-events recorded on the stream the kernels run on.
+One step = zero the index + insert every set (partitioned insert, or
+k_insert_seqs for small inserts) + answer every query (k_query_kmers).
+Inputs are resident in device memory before timing.  `value` is k-mer
+queries per second of the query phase; inserts per second of the insert
+phase are reported beside it.  Phase times come from HIP events recorded on
+the stream the kernels run on.
+
+Further sections of the same JSON line: the one-launch-per-query comparator
+(`plain_path`), the query server on the mid index with and without streaming
+inserts (`serving`, `latency`), batched reads on the small index
+(`batched_reads`), folding the mid index over (`fold`), the word-unigram
+document index on raw 64-bit keys (`documents`) and the oracle on the host
+(`cpu_baseline`).
 
 Prints one JSON line.
 """
