@@ -253,7 +253,11 @@ int rambo_load(const char *path, rambo_t **out);
 /* The configuration of the index (after folding, B is the folded one). */
 int rambo_get_config(const rambo_t *h, rambo_config *out);
 
-/* Zero every Bloom filter (an empty index with the same hashes). */
+/* Zero every Bloom filter (an empty index with the same hashes).  Inserts,
+ * queries and clears may be recorded into a HIP graph on `stream` (stream
+ * capture) once each kind of call has run eagerly with its sizes, so that its
+ * scratch exists; recorded inserts always read the regions they update back,
+ * and recorded calls take no timing events. */
 int rambo_clear(rambo_t *h, hipStream_t stream);
 
 /* Layout of the index (see above). */

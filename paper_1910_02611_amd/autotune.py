@@ -78,6 +78,21 @@ def capture_query_seqs(g: rb.Rambo, offsets, chars, out, nk):
     return graph
 
 
+def capture(fn):
+    """A hipGraph (torch.cuda.CUDAGraph) of fn(), a sequence of library calls
+    on torch's current stream (inserts, clears, queries).  fn runs once
+    eagerly first, so that scratch and per-read state already have their size
+    (nothing is allocated while recording); inserts are idempotent, so the
+    extra eager run changes no answer."""
+    fn()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    torch.cuda.synchronize()
+    return graph
+
+
 def time_graph(graph, reps: int = 3) -> float:
     """Best of reps, in seconds, of one replay."""
     stream = torch.cuda.current_stream()

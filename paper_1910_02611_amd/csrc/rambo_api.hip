@@ -49,6 +49,7 @@ struct rambo {
     void *rq_mem = nullptr;
     uint64_t rq_cap = 0;               // reads the queue state holds
     int servers = 0;                   // query servers attached (their graphs hold index pointers)
+    bool recorded_insert = false;      // an insert was recorded into a graph: index_zero is never trusted again
     ReadQueue rq{};
     uint64_t *scan_part = nullptr;     // tile totals of the ID-list scan (in rq_mem)
     // kernel timing (rambo_set_timing)
@@ -65,13 +66,31 @@ struct rambo {
 namespace {
 
 // Brackets one kernel launch with two events on its stream when timing is on.
+// Whether work on stream st is being recorded into a graph (then nothing
+// runs now: host-side state must not assume the work has happened, and no
+// timing events are recorded).
+bool capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
+// The index is no longer known to be zero; an insert recorded into a graph
+// may run later unseen by the host, so from then on it never is.
+void note_insert(rambo *h, hipStream_t stream)
+{
+    h->index_zero = false;
+    if (capturing(stream))
+        h->recorded_insert = true;
+}
+
 struct StageScope {
     const rambo *h;
     hipStream_t st;
     hipEvent_t b = nullptr;
     StageScope(const rambo *h_, const char *name, hipStream_t st_) : h(h_), st(st_)
     {
-        if (!h->timing || h->stages.size() >= 100000)
+        if (!h->timing || h->stages.size() >= 100000 || capturing(st))
             return;
         hipEvent_t ev[2];
         for (hipEvent_t &e : ev) {
@@ -558,8 +577,10 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
     const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
     const size_t ldsA = A.lds, ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     // the first batch into an all-zero index need not read the regions back
-    uint32_t fresh = h->index_zero ? 1u : 0u;
-    h->index_zero = false;
+    // (never in a captured graph: a replay may find the index holding bits;
+    // and never once a recorded insert may have run unseen by the host)
+    uint32_t fresh = h->index_zero && !h->recorded_insert && !capturing(stream) ? 1u : 0u;
+    note_insert(h, stream);
     for (uint64_t p = 0; p < n_chars; p += batch_windows, fresh = 0) {
         const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
         { StageScope sc(h, "k_zero_u32", stream);
@@ -837,7 +858,7 @@ extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_by
 int insert_seqs_direct(rambo *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
                        const uint8_t *chars, uint64_t n_chars, hipStream_t stream)
 {
-    h->index_zero = false;
+    note_insert(h, stream);
     const uint64_t waves = div_up(n_chars, kChunk);
     const InsertSeqsFn ins = pick_shape<InsertSeqsFn, InsertSeqsK>(h->cfg.R, h->cfg.eta);
     StageScope sc(h, "k_insert_seqs", stream);
@@ -863,7 +884,7 @@ extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uin
         return RAMBO_OK;
     if (!set_ids || !offsets || !codes)
         return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
-    h->index_zero = false;
+    note_insert(h, stream);
     StageScope sc(h, "k_insert_kmers", stream);
     hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,
                        set_ids, offsets, n_sets, codes, n_codes);
@@ -1233,6 +1254,12 @@ extern "C" int rambo_clear(rambo_t *h, hipStream_t stream)
 {
     if (!h)
         return RAMBO_EINVAL;
+    if (capturing(stream)) {
+        // a fill kernel, not a memset node, in a graph; the host does not
+        // learn that the index is zero (the graph runs later)
+        hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(kBlock), 0, stream, h->index, h->index_bytes / 4);
+        return launch_check(h, "rambo_clear");
+    }
     const int rc = hip_check(h, hipMemsetAsync(h->index, 0, h->index_bytes, stream), "rambo_clear");
     if (rc == RAMBO_OK)
         h->index_zero = true;

@@ -6,7 +6,8 @@ import pytest
 
 from paper_1910_02611_amd import synth
 from paper_1910_02611_amd import rambo as rb
-from gpu_util import dev, host_u32, make_pair, gpu_insert_seqs
+import oracle
+from gpu_util import dev, host_u32, make_pair, gpu_insert_seqs, gpu_index_bits, oracle_index_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -94,3 +95,49 @@ def test_captured_graph_replays_match_oracle(tiny, mode):
             assert np.array_equal(host_u32(out), want)
     finally:
         g.set_query_policy(rb.QUERY_AUTO)
+
+
+@pytest.mark.parametrize("policy", [rb.INSERT_PARTITIONED, rb.INSERT_DIRECT])
+def test_captured_insert_pipelines_match_oracle(policy):
+    # a recorded [clear + insert A] and a recorded [insert B], replayed in
+    # several orders with eager work between the replays: every state equals
+    # the oracle's (a recorded insert reads its regions back, so it never
+    # drops bits that another insert put there)
+    import torch
+    from paper_1910_02611_amd import autotune
+    cfg = dict(K=100, B=50, R=4, eta=2, k=31, m=1 << 14)
+    sets = synth.genome_sets(4301, K=100, n_ancestors=5, ancestor_len=600, sub_rate=0.02)
+    half = sets.n // 2
+    A = synth.SeqBatch(sets.chars, sets.offsets[: half + 1], sets.set_ids[:half])
+    Bs = synth.SeqBatch(sets.chars, sets.offsets[half:], sets.set_ids[half:])
+    oa = oracle.OracleIndex(**cfg, seed=31)
+    oa.insert_seqs(A.set_ids, A.offsets, A.chars, 8)
+    oab = oracle.OracleIndex(**cfg, seed=31)
+    oab.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    ob = oracle.OracleIndex(**cfg, seed=31)
+    ob.insert_seqs(Bs.set_ids, Bs.offsets, Bs.chars, 8)
+    g = rb.Rambo(**cfg, seed=31)
+    g.set_insert_policy(policy, 1 << 20)    # small scratch: several batches per insert
+    dA = (dev(A.set_ids, np.int32), dev(A.offsets, np.int64), dev(A.chars, np.uint8))
+    dB = (dev(Bs.set_ids, np.int32), dev(Bs.offsets, np.int64), dev(Bs.chars, np.uint8))
+    g_clear_a = autotune.capture(lambda: (g.clear(), g.insert_seqs(*dA)))
+    g_b = autotune.capture(lambda: g.insert_seqs(*dB))
+    q = synth.kmer_queries(4302, sets, 2000, 31)
+    codes = dev(oracle.extract(q.offsets, q.chars, 31)[q.offsets[:-1].astype(np.int64)], np.int64)
+    for _ in range(3):
+        g_clear_a.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(gpu_index_bits(g), oracle_index_bits(oa))
+        g_b.replay()
+        g.query_kmers(codes)                       # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(gpu_index_bits(g), oracle_index_bits(oab))
+        g.clear()                                  # eager: the index is known to be zero
+        g_b.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(gpu_index_bits(g), oracle_index_bits(ob))
+        g.insert_seqs(*dA)                         # eager insert after the replay
+        torch.cuda.synchronize()
+        assert np.array_equal(gpu_index_bits(g), oracle_index_bits(oab))
+    assert g.sync_status() == rb.OK
+    g.close()
