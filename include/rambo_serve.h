@@ -83,6 +83,17 @@ int64_t rambo_serve_submit_insert(rambo_server_t *s, const uint32_t *set_ids, co
 int rambo_serve_wait(rambo_server_t *s, int64_t id, uint32_t *masks, uint32_t *nkmers, double *latency_ms,
                      int64_t timeout_us);
 
+/* Open-loop load driver (measurement): request i - the reads
+ * req_reads[i] .. req_reads[i+1]-1 of the host CSR read_offsets / chars,
+ * 1 to max_batch_reads reads - is submitted from a native thread at
+ * arrival_s[i] seconds after the start (non-decreasing), while the calling
+ * thread waits for the answers in order.  latency_ms[i] = arrival to answer
+ * in host memory (the submit lag included).  *checksum (if not NULL) hashes
+ * every answer word in request order.  Returns RAMBO_OK or the first error;
+ * the requests already submitted are answered either way. */
+int rambo_serve_replay(rambo_server_t *s, uint64_t n_req, const uint64_t *req_reads, const uint64_t *read_offsets,
+                       const uint8_t *chars, const double *arrival_s, double *latency_ms, uint64_t *checksum);
+
 /* Counters since creation: batches run, requests and reads answered, and the
  * number of slots. */
 int rambo_serve_stats(rambo_server_t *s, uint64_t *batches, uint64_t *requests, uint64_t *reads, uint32_t *slots);

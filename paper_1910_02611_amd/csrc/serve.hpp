@@ -480,6 +480,75 @@ extern "C" int rambo_serve_wait(rambo_server_t *sv, int64_t id, uint32_t *masks,
     return r->status;
 }
 
+extern "C" int rambo_serve_replay(rambo_server_t *sv, uint64_t n_req, const uint64_t *req_reads,
+                                  const uint64_t *read_offsets, const uint8_t *chars, const double *arrival_s,
+                                  double *latency_ms, uint64_t *checksum)
+{
+    if (!sv || !req_reads || !read_offsets || !arrival_s || !latency_ms)
+        return RAMBO_EINVAL;
+    for (uint64_t i = 0; i < n_req; ++i)
+        if (req_reads[i + 1] < req_reads[i] || req_reads[i + 1] - req_reads[i] > sv->cfg.max_batch_reads ||
+            req_reads[i + 1] == req_reads[i] || (i > 0 && arrival_s[i] < arrival_s[i - 1]))
+            return RAMBO_EINVAL;
+    std::vector<int64_t> ids(n_req, -1);
+    std::vector<double> lag(n_req, 0.0);
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t submitted = 0;
+    int submit_rc = RAMBO_OK;
+    const auto t0 = Clock::now() + std::chrono::milliseconds(5);
+    std::thread submitter([&] {
+        for (uint64_t i = 0; i < n_req; ++i) {
+            const auto due = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+            std::this_thread::sleep_until(due);
+            const auto now = Clock::now();
+            const uint64_t a = req_reads[i], n = req_reads[i + 1] - a;
+            const int64_t id = rambo_serve_submit(sv, read_offsets + a, n, chars);
+            std::lock_guard<std::mutex> lk(mu);
+            if (id < 0) {
+                submit_rc = (int)id;
+                break;
+            }
+            ids[i] = id;
+            lag[i] = now > due ? std::chrono::duration<double, std::milli>(now - due).count() : 0.0;
+            submitted = i + 1;
+            cv.notify_one();
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        submitted = n_req;   // wakes the collector even after a failed submit
+        cv.notify_one();
+    });
+    const uint32_t W = sv->h->W;
+    std::vector<uint32_t> masks, nk;
+    uint64_t sum = 0;
+    int rc = RAMBO_OK;
+    for (uint64_t i = 0; i < n_req; ++i) {
+        int64_t id;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return submitted > i; });
+            id = ids[i];
+        }
+        if (id < 0) {
+            rc = submit_rc ? submit_rc : RAMBO_EINVAL;
+            break;
+        }
+        const uint64_t n = req_reads[i + 1] - req_reads[i];
+        masks.resize(n * W);
+        nk.resize(n);
+        double ms = 0;
+        if ((rc = rambo_serve_wait(sv, id, masks.data(), nk.data(), &ms, -1)))
+            break;
+        latency_ms[i] = ms + lag[i];
+        for (uint32_t v : masks)
+            sum = sum * 1000003u + v;
+    }
+    submitter.join();
+    if (checksum)
+        *checksum = sum;
+    return rc;
+}
+
 extern "C" int rambo_serve_stats(rambo_server_t *sv, uint64_t *batches, uint64_t *requests, uint64_t *reads,
                                  uint32_t *slots)
 {

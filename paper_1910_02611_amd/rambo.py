@@ -104,6 +104,9 @@ EXPORTS = {
     "rambo_serve_submit": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     "rambo_serve_submit_insert": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_uint64, ctypes.c_void_p]),
+    "rambo_serve_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
     "rambo_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
     "rambo_serve_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
@@ -437,6 +440,25 @@ class Server:
         if rc != OK:
             raise RamboError(rc, "rambo_serve_wait")
         return masks, nk, lat.value
+
+    def replay(self, req_reads, read_offsets, chars, arrival_s):
+        """Native open-loop drive (rambo_serve_replay): request i = reads
+        req_reads[i] .. req_reads[i+1]-1 of the host CSR (read_offsets,
+        chars), submitted at arrival_s[i] seconds.  Returns (latencies in ms,
+        answer checksum)."""
+        import numpy as np
+        rr = np.ascontiguousarray(req_reads, dtype=np.uint64)
+        off = np.ascontiguousarray(read_offsets, dtype=np.uint64)
+        ch = np.ascontiguousarray(chars, dtype=np.uint8)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        n = rr.size - 1
+        lat = np.zeros(n, dtype=np.float64)
+        ck = ctypes.c_uint64()
+        rc = lib().rambo_serve_replay(self._s, n, rr.ctypes.data, off.ctypes.data, ch.ctypes.data, arr.ctypes.data,
+                                      lat.ctypes.data, ctypes.byref(ck))
+        if rc != OK:
+            raise RamboError(rc, "rambo_serve_replay")
+        return lat, ck.value
 
     def stats(self) -> dict:
         b, q, r = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

@@ -85,6 +85,36 @@ def run_open_loop(server: rambo.Server, reqs, arrivals: np.ndarray, W: int, inse
     return out
 
 
+def run_native(server: rambo.Server, batch: synth.SeqBatch, arrivals: np.ndarray) -> dict:
+    """The same measurement with the native driver (rambo_serve_replay): the
+    requests of a served_requests batch submitted at their arrival times
+    from a native thread, no Python between the requests."""
+    ro = batch.meta["request_offsets"]
+    t0 = time.perf_counter()
+    lat, check = server.replay(ro, batch.offsets, batch.chars, arrivals)
+    span = time.perf_counter() - t0
+    n = ro.size - 1
+    reads = int(ro[-1] - ro[0])
+    return dict(requests=n, reads=reads, seconds=span, qps=n / span, reads_per_s=reads / span,
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                mean_ms=float(lat.mean()), checksum=int(check))
+
+
+def sweep_native(server: rambo.Server, batch: synth.SeqBatch, fractions, seed: int = 5004) -> dict:
+    """Saturated rate (every request at time 0), then Poisson load at the
+    given fractions of it, with the native driver."""
+    n = batch.meta["request_offsets"].size - 1
+    sat = run_native(server, batch, np.zeros(n))
+    points = []
+    for j, f in enumerate(fractions):
+        rate = f * sat["qps"]
+        r = run_native(server, batch, synth.poisson_arrivals(seed + j, n, rate))
+        r["offered_qps"] = rate
+        r["load"] = f
+        points.append(r)
+    return dict(saturated=sat, points=points)
+
+
 def saturated(server: rambo.Server, reqs, W: int) -> dict:
     """Every request queued at once: the server's peak request rate."""
     return run_open_loop(server, reqs, np.zeros(len(reqs)), W)

@@ -8,6 +8,7 @@ import pytest
 
 from paper_1910_02611_amd import rambo as rb
 from paper_1910_02611_amd import serve, synth
+import oracle
 from gpu_util import make_pair, gpu_insert_seqs
 
 pytestmark = pytest.mark.gpu
@@ -174,3 +175,37 @@ def test_streaming_inserts_between_queries(use_graphs):
             want.append((m, nk.astype(np.uint32)))
         check(got, want)
     check([after], [want[0]])
+
+
+def _checksum(masks_in_order):
+    s = 0
+    for m in masks_in_order:
+        for v in np.asarray(m, dtype=np.uint32).reshape(-1).tolist():
+            s = (s * 1000003 + v) & ((1 << 64) - 1)
+    return s
+
+
+def test_native_replay_driver(served):
+    """rambo_serve_replay submits the requests from a native thread at their
+    arrival times; its checksum over every answer word equals the oracle's
+    answers in request order, saturated and paced."""
+    g, _, _ = served
+    cfg = synth.INDEX_TINY
+    sets = synth.config_tiny()
+    o = oracle.OracleIndex(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], 2001)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    batch = synth.served_requests(4020, sets, 60, max_len=1500)
+    ro = batch.meta["request_offsets"]
+    want = []
+    for r in range(ro.size - 1):
+        off, ch = synth.request(batch, r)
+        want.append(o.query_seqs(off, ch, nthreads=8)[0])
+    with rb.Server(g, max_slots=3, use_graphs=True) as srv:
+        for arrivals in (np.zeros(ro.size - 1), synth.poisson_arrivals(7, ro.size - 1, 2000.0)):
+            lat, ck = srv.replay(ro, batch.offsets, batch.chars, arrivals)
+            assert ck == _checksum(want)
+            assert (lat > 0).all()
+        bad = ro.copy()
+        bad[1] = bad[0]            # a request without reads
+        with pytest.raises(rb.RamboError):
+            srv.replay(bad, batch.offsets, batch.chars, np.zeros(ro.size - 1))
