@@ -824,10 +824,18 @@ __device__ __forceinline__ void expand_answer_wave(const Params &P, const uint32
         for (uint32_t w = lane; w < P.W; w += kWave) {
             uint32_t acc = ~0u;
             for (uint32_t r = 0; r < R; ++r) {
+                const uint32_t *m = P.cellmask + (uint64_t)r * P.B * P.W + w;
                 uint32_t u = 0;
+                uint32_t e = seg[r];
                 const uint32_t e1 = seg[r + 1];
-                for (uint32_t e = seg[r]; e < e1; ++e)
-                    u |= P.cellmask[((uint64_t)r * P.B + lst[e]) * P.W + w];
+                // four cells at a time: their loads are in flight together
+                for (; e + 4 <= e1; e += 4) {
+                    const uint32_t a = m[(uint64_t)lst[e] * P.W], b = m[(uint64_t)lst[e + 1] * P.W];
+                    const uint32_t c = m[(uint64_t)lst[e + 2] * P.W], d = m[(uint64_t)lst[e + 3] * P.W];
+                    u |= (a | b) | (c | d);
+                }
+                for (; e < e1; ++e)
+                    u |= m[(uint64_t)lst[e] * P.W];
                 acc &= ((neg >> r) & 1u) ? ~u : u;
             }
             o[w] = acc & bits_below(w, P.K);
