@@ -4,8 +4,10 @@ Requests arrive as a Poisson process; a submitter thread hands each one to
 the server at its arrival time, and the caller's thread collects the answers.
 Latency is arrival -> answer in host memory: the server's own submit ->
 result time plus however late the submitter was.  The server, its batching
-and every kernel are native; this module only paces submissions and reports
-percentiles.
+and every kernel are native.  Two drivers pace the submissions: the native
+one (rambo_serve_replay, run_native / sweep_native: no Python between
+requests) and a Python one (run_open_loop, which can also interleave insert
+requests); this module reports percentiles.
 
     python -m paper_1910_02611_amd.serve --index tiny --requests 20000
 """
@@ -175,10 +177,10 @@ def main():
                     torch.from_numpy(sets.offsets.view(np.int64)).to(dev),
                     torch.from_numpy(sets.chars).to(dev))
     torch.cuda.synchronize()
-    reqs = split_requests(synth.served_requests(4004, sets, args.requests))
+    batch = synth.served_requests(4004, sets, args.requests)
     del sets
     with rambo.Server(idx, max_slots=args.slots, use_graphs=args.graphs) as srv:
-        res = sweep(srv, reqs, idx.W, [float(x) for x in args.loads.split(",")])
+        res = sweep_native(srv, batch, [float(x) for x in args.loads.split(",")])
         res["server"] = srv.stats()
     print(json.dumps(res))
 
