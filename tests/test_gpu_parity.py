@@ -222,6 +222,8 @@ SHAPES = [
     dict(K=64, B=8, R=3, eta=1, k=31, m=1 << 12),
     dict(K=4096, B=256, R=3, eta=2, k=31, m=1 << 11),   # answer words a multiple of 4, 2 lanes per query
     dict(K=1024, B=64, R=5, eta=2, k=31, m=1 << 12),    # answer words a multiple of 4, one lane per query
+    dict(K=200, B=10, R=16, eta=2, k=31, m=1 << 11),    # the most repetitions, R * eta at its limit of 32
+    dict(K=50, B=4, R=2, eta=16, k=27, m=1 << 12),      # the most hashes per filter
 ]
 
 
