@@ -417,6 +417,27 @@ def documents(n_queries: int, steps: int = 3):
     return res
 
 
+def measured_ceilings(index_bytes: int, S: int, RE: int, q_per_s: float, ins_per_s: float) -> dict:
+    """Both phases against ceilings measured on this GPU over a buffer as large
+    as the index (so TLB and last-level-cache effects are included): k-mer
+    queries against random gathers of one row (S/8 bytes, at least 4), each
+    query credited with all R*eta rows (the early exit is not subtracted);
+    inserts against random 32-bit atomicOr, each insert needing R*eta bit
+    sets - the rate a one-atomic-per-target insert could reach."""
+    from paper_1910_02611_amd import roofline
+    G = max(4, S // 8)
+    m = roofline.measure(index_bytes, n_access=1 << 27, sizes=(G,))
+    gathers = m["gather"][str(G)]["accesses_per_s"]
+    atomics = m["atomic_or"]["accesses_per_s"]
+    log("measured ceilings over %.1f GiB: random %d-byte gathers %.3g/s, random atomicOr %.3g/s"
+        % (index_bytes / 2**30, G, gathers, atomics))
+    return {"buffer_bytes": index_bytes,
+            "query": {"achieved": q_per_s * RE, "ceiling": gathers, "unit": "row gathers/s",
+                      "frac": q_per_s * RE / gathers, "row_bytes": G},
+            "insert": {"achieved": ins_per_s * RE, "ceiling": atomics, "unit": "bit targets/s",
+                       "frac": ins_per_s * RE / atomics}}
+
+
 def fold_timing(g):
     """Folding over the resident index once (B -> B/2): the k_fold kernel's
     duration against reading the old index and writing the new one once,
@@ -451,6 +472,8 @@ def main():
     ap.add_argument("--plain-prefix", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fold", action="store_true", help="skip folding the index over at the end")
+    ap.add_argument("--no-measured-ceilings", action="store_true",
+                    help="skip measuring the random-gather and random-atomic ceilings over an index-sized buffer")
     ap.add_argument("--doc-queries", type=int, default=1_000_000,
                     help="word queries of the document-index section (0 = skip)")
     ap.add_argument("--reads", type=int, default=100_000, help="batched-read section size (0 = skip)")
@@ -497,6 +520,9 @@ def main():
         log("  %-16s %8.3f ms  %-3s %.3g %s (%.1f%% of %.4g)" % (r["kernel"], r["ms"], r["bound"], r["achieved"],
                                                                r["unit"], 100 * r["frac"], r["peak"]))
 
+    measured = None
+    if not args.no_measured_ceilings:
+        measured = measured_ceilings(g.index_bytes, S, R * eta, q_per_s, ins_per_s)
     if args.calib_copy_gib > 0:
         # a streaming copy of known size: the scale of the memory counters
         from paper_1910_02611_amd.rambo import lib
@@ -524,7 +550,7 @@ def main():
         "inserts_per_s": ins_per_s,
         "phase_ms": {"clear": t_clear, "insert": t_ins, "query": t_q},
         "kernel_ms": kernels,
-        "roofline": roofs[0], "roofline_other": roofs[1:],
+        "roofline": roofs[0], "roofline_other": roofs[1:], "measured_ceilings": measured,
         "plain_path": {"k_mer_queries_per_s": plain_rate, "prefix": args.plain_prefix,
                        "identical": plain_same, "speedup_batched": q_per_s / plain_rate if plain_rate else None},
     }
