@@ -108,3 +108,22 @@ def test_fold_of_an_empty_index_then_insert():
     gpu_insert_seqs(g, sets)
     assert np.array_equal(gpu_index_bits(g), oracle_index_bits(o))
     g.close()
+
+
+def test_fold_refused_while_a_server_is_attached():
+    # the server's captured graphs hold the index's address: folding (which
+    # replaces the index) is refused until the server is gone
+    cfg = dict(K=40, B=8, R=2, eta=2, k=21, m=3000)
+    sets = _sets(cfg, 91)
+    o, g = make_pair(cfg, seed=91)
+    gpu_insert_seqs(g, sets)
+    with rb.Server(g, max_slots=1, use_graphs=True):
+        with pytest.raises(rb.RamboError) as e:
+            g.fold()
+        assert e.value.code == rb.EINVAL
+    assert g.B == 8
+    g.fold()
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 4)
+    o.fold()
+    assert np.array_equal(gpu_index_bits(g), oracle_index_bits(o))
+    g.close()
