@@ -150,11 +150,13 @@ def test_scale_serving(workload):
     name, cfg, sets, g, o, rec = workload
     if name not in ("served", "mini"):
         pytest.skip("serving is measured on the served workload")
-    # 10 000 requests per point, 8 points from 10% to 120% of the saturated rate
-    reqs = serve.split_requests(synth.served_requests(4004, sets, 10_000))
+    # 10 000 requests per point, 8 points from 10% to 120% of the saturated
+    # rate, submissions paced by the native driver
+    batch = synth.served_requests(4004, sets, 10_000)
+    reqs = serve.split_requests(batch)
     with rb.Server(g, max_slots=4, use_graphs=True) as srv:
         serve.saturated(srv, reqs[:200], g.W)
-        res = serve.sweep(srv, reqs, g.W, [0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2])
+        res = serve.sweep_native(srv, batch, [0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2])
         res["server"] = srv.stats()
     keep = ("load", "offered_qps", "qps", "reads_per_s", "p50_ms", "p99_ms")
     log(rec, serving_saturated={k: res["saturated"][k] for k in ("qps", "reads_per_s", "p50_ms", "p99_ms")},
