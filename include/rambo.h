@@ -121,7 +121,10 @@ void rambo_destroy(rambo_t *h);
  * canonical.  Repeated calls OR into the same index (streaming updates,
  * Sec. 3.1); order does not matter.  Device errors: RAMBO_ERANGE (set id),
  * RAMBO_ECODE (code >= 4^k, k-mer indexes only) - the item is skipped.
- * With RAMBO_FLAG_RAW_KEYS the codes are the keys. */
+ * With RAMBO_FLAG_RAW_KEYS the codes are the keys.  The insert policy
+ * (rambo_set_insert_policy) applies as for sequences where the shape has a
+ * partitioned code kernel (R in 3..6 with eta = 2, or R = 2 with eta = 4);
+ * other shapes always insert directly. */
 int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets,
                        uint64_t n_sets, const uint64_t *codes, uint64_t n_codes,
                        hipStream_t stream);
@@ -180,7 +183,8 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
                            const uint8_t *chars, uint64_t n_chars, uint32_t *out_masks,
                            uint32_t *out_nkmers, hipStream_t stream);
 
-/* How rambo_insert_seqs applies bits (the result is the same either way):
+/* How rambo_insert_seqs and rambo_insert_kmers apply bits (the result is
+ * the same either way):
  * DIRECT issues one atomicOr per bit target (Alg. 1 as written); PARTITIONED
  * sorts the targets by address into regions of the index and ORs each region
  * in on-chip memory, which avoids the device's atomic-rate limit on bulk

@@ -256,10 +256,12 @@ __host__ __device__ constexpr size_t lds_bytes_stage_a_hold(uint32_t re, uint32_
     return hold_tile(re) * 6ull + na * 12ull + 64;
 }
 
-template <int R_T, int ETA_T>
-__global__ __launch_bounds__(kBlockP) __attribute__((amdgpu_waves_per_eu(4)))
-void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
-                        const uint8_t *chars, uint64_t n_chars, uint64_t p_begin, uint64_t p_end, uint32_t rounds)
+// The body, for any walker of terms (WindowWalker over sequences,
+// CodeWalker over codes or keys); init_walker(w, first, end) starts it on
+// the terms [first, end).
+template <int R_T, int ETA_T, class Walker, class Init>
+__device__ __forceinline__ void bin_hold(const Params &P, const BinGeom &G, const uint32_t *set_ids,
+                                         uint64_t p_begin, uint64_t p_end, uint32_t rounds, Init &&init_walker)
 {
     constexpr uint32_t RE = R_T * ETA_T;
     constexpr uint32_t ST = hold_steps(RE);
@@ -280,9 +282,9 @@ void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint
     const uint64_t w0 = p_begin + ((uint64_t)blockIdx.x * kWavesP + wv) * span;
     const uint64_t w1 = min(w0 + span, p_end);
     const bool busy = w0 < p_end;
-    WindowWalker walker;
+    Walker walker;
     if (busy)
-        walker.init(offsets, n_seqs, chars, n_chars, w0, w1, P.k, P.kmask);
+        init_walker(walker, w0, w1);
     SetCache cache;
     cache.init_seeds(P);
     for (uint32_t b = threadIdx.x; b < G.na; b += kBlockP)
@@ -335,6 +337,31 @@ void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint
         // counting) is reached only when every wave has finished this loop,
         // and the counting touches only cnt, which this loop does not read
     }
+}
+
+template <int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlockP) __attribute__((amdgpu_waves_per_eu(4)))
+void k_bin_windows_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
+                        const uint8_t *chars, uint64_t n_chars, uint64_t p_begin, uint64_t p_end, uint32_t rounds)
+{
+    bin_hold<R_T, ETA_T, WindowWalker>(P, G, set_ids, p_begin, p_end, rounds,
+                                       [&](WindowWalker &w, uint64_t first, uint64_t end) {
+                                           w.init(offsets, n_seqs, chars, n_chars, first, end, P.k, P.kmask);
+                                       });
+}
+
+// Stage A from codes or raw keys: the terms of code q (set set_ids[s] for
+// offsets[s] <= q < offsets[s+1]) instead of the windows of sequences.
+template <int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlockP) __attribute__((amdgpu_waves_per_eu(4)))
+void k_bin_codes_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_sets,
+                      const uint64_t *codes, uint64_t p_begin, uint64_t p_end, uint32_t rounds)
+{
+    bin_hold<R_T, ETA_T, CodeWalker>(P, G, set_ids, p_begin, p_end, rounds,
+                                     [&](CodeWalker &w, uint64_t first, uint64_t end) {
+                                         w.init(offsets, n_sets, codes, first, end, P.k, P.kmask, P.raw_keys != 0,
+                                                P.err);
+                                     });
 }
 
 // Stage B: block = (coarse bucket, tile of its slab).  The tile's entries

@@ -255,6 +255,53 @@ struct WindowWalker {
     }
 };
 
+// Walks a CSR of codes (or raw keys) [p0, p_end), 64 per step: at each step
+// lane l holds the term of code p + l and the set (CSR index) it belongs to.
+// Codes outside every set's range are not terms; k-mer codes >= 4^k are
+// reported through err and skipped.  The same interface as WindowWalker.
+struct CodeWalker {
+    const uint64_t *offsets;
+    uint64_t n_sets;
+    const uint64_t *codes;
+    uint32_t k;
+    uint64_t kmask;
+    bool raw;
+    int *err;
+    uint64_t p, p_end;
+    SeqCursor c;
+
+    __device__ __forceinline__ void init(const uint64_t *offsets_, uint64_t n_sets_, const uint64_t *codes_,
+                                         uint64_t p0, uint64_t p_end_, uint32_t k_, uint64_t kmask_, bool raw_,
+                                         int *err_)
+    {
+        offsets = offsets_;
+        n_sets = n_sets_;
+        codes = codes_;
+        k = k_;
+        kmask = kmask_;
+        raw = raw_;
+        err = err_;
+        p = p0;
+        p_end = p_end_;
+        c.init(offsets, n_sets, p0);
+    }
+
+    __device__ __forceinline__ void step(bool &valid, uint64_t &x, uint64_t &seq)
+    {
+        const uint64_t q = p + lane_id();
+        c.advance(offsets, n_sets, q);
+        const bool in = q < p_end && q >= c.beg && q < c.end;
+        const uint64_t code = in ? codes[q] : 0;
+        const bool bad = in && !raw && code > kmask;
+        if (bad)
+            atomicOr(err, kErrCode);
+        valid = in && !bad;
+        x = raw ? code : canonical(code & kmask, k);
+        seq = c.s;
+        p += kWave;
+    }
+};
+
 // The wave visits the windows starting at bytes [p0, p_end) and calls
 // f(p, valid, canonical code, sequence) on every lane of the wave together
 // (valid is false past p_end), so f may use wave-wide operations.

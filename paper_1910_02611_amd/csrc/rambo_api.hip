@@ -328,6 +328,27 @@ BinHoldFn pick_bin_hold(uint32_t R, uint32_t eta)
     return nullptr;
 }
 
+using BinCodesFn = void (*)(Params, BinGeom, const uint32_t *, const uint64_t *, uint64_t, const uint64_t *, uint64_t,
+                            uint64_t, uint32_t);
+
+// Stage A from codes or raw keys, for the compile-time shapes (those of the
+// sequence path and R = 2, eta = 4 of the documents index).
+BinCodesFn pick_bin_codes_hold(uint32_t R, uint32_t eta)
+{
+    if (eta == 2) {
+        switch (R) {
+        case 3: return k_bin_codes_hold<3, 2>;
+        case 4: return k_bin_codes_hold<4, 2>;
+        case 5: return k_bin_codes_hold<5, 2>;
+        case 6: return k_bin_codes_hold<6, 2>;
+        default: break;
+        }
+    }
+    if (eta == 4 && R == 2)
+        return k_bin_codes_hold<2, 4>;
+    return nullptr;
+}
+
 // The stage-A kernel of a shape, its steps per round and its LDS bytes.
 struct StageA {
     BinWindowsFn generic = nullptr;
@@ -523,7 +544,12 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     // stages A and B use more than the default 64 KiB of dynamic LDS
     const StageA A = stage_a(h);
     const void *binA = A.hold ? reinterpret_cast<const void *>(A.hold) : reinterpret_cast<const void *>(A.generic);
+    const BinCodesFn codesA = G.na <= kHoldBucketsPerThread * kBlockP ? pick_bin_codes_hold(h->cfg.R, h->cfg.eta)
+                                                                      : nullptr;
     if (hipFuncSetAttribute(binA, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds) != hipSuccess ||
+        (codesA && hipFuncSetAttribute(reinterpret_cast<const void *>(codesA),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_bytes_stage_a_hold(h->cfg.R * h->cfg.eta, G.na)) != hipSuccess) ||
         hipFuncSetAttribute(reinterpret_cast<const void *>(k_bin_regions),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_b(G.nf)) != hipSuccess) {
         (void)hipFree(h->bin_mem);
@@ -558,6 +584,45 @@ bool use_partitioned(const rambo *h, uint64_t n_chars)
     const double t_part = (T * 20.0 + (T < regions ? T : regions) * 2.0 * (1u << (kRegionLog2 - 3))) / kStreamRate +
                           100e-6;
     return t_part < t_direct;
+}
+
+// Stages A to C for codes or raw keys (the shape has a held-target kernel:
+// pick_bin_codes_hold), in batches of the scratch's capacity.
+int insert_kmers_partitioned(rambo *h, BinCodesFn binA, const uint32_t *set_ids, const uint64_t *offsets,
+                             uint64_t n_sets, const uint64_t *codes, uint64_t n_codes, hipStream_t stream)
+{
+    const uint64_t RE = (uint64_t)h->cfg.R * h->cfg.eta;
+    int rc = ensure_scratch(h, n_codes * RE);
+    if (rc)
+        return rc;
+    BinGeom &G = h->bin;
+    const size_t ldsA = lds_bytes_stage_a_hold((uint32_t)RE, G.na), ldsB = lds_bytes_stage_b(G.nf),
+                 ldsC = (1ull << (G.rb - 5)) * 4;
+    const uint64_t batch = h->bin_targets / RE;
+    const uint32_t steps = hold_steps((uint32_t)RE);
+    const uint32_t rounds = (uint32_t)div_up(kStageAWindowsPerWave, (uint64_t)steps * kWave);
+    const uint64_t block_codes = (uint64_t)kWavesP * rounds * steps * kWave;
+    const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
+    // as for sequences: only the first batch into an index known to be all
+    // zero skips reading the regions back
+    uint32_t fresh = h->index_zero && !h->recorded_insert && !capturing(stream) ? 1u : 0u;
+    note_insert(h, stream);
+    for (uint64_t p = 0; p < n_codes; p += batch, fresh = 0) {
+        const uint64_t pe = p + batch < n_codes ? p + batch : n_codes;
+        { StageScope sc(h, "k_zero_u32", stream);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
+                           (uint64_t)G.na + 2ull * G.na * G.nf); }   // fillA, fillB, dirty
+        { StageScope sc(h, "k_bin_codes", stream);
+        hipLaunchKernelGGL(binA, dim3((uint32_t)div_up(pe - p, block_codes)), dim3(kBlockP), ldsA, stream, h->P, G,
+                           set_ids, offsets, n_sets, codes, p, pe, rounds); }
+        { StageScope sc(h, "k_bin_regions", stream);
+        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
+        { StageScope sc(h, "k_apply_regions", stream);
+        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G, fresh); }
+        if ((rc = launch_check(h, "rambo_insert_kmers (partitioned)")))
+            return rc;
+    }
+    return RAMBO_OK;
 }
 
 int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
@@ -884,6 +949,9 @@ extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uin
         return RAMBO_OK;
     if (!set_ids || !offsets || !codes)
         return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
+    if (use_partitioned(h, n_codes) && h->bin.na <= kHoldBucketsPerThread * kBlockP)
+        if (const BinCodesFn binA = pick_bin_codes_hold(h->cfg.R, h->cfg.eta))
+            return insert_kmers_partitioned(h, binA, set_ids, offsets, n_sets, codes, n_codes, stream);
     note_insert(h, stream);
     StageScope sc(h, "k_insert_kmers", stream);
     hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,

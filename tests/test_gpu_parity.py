@@ -299,7 +299,9 @@ def test_partitioned_insert_reads_back_earlier_bits(tiny):
     keep = (codes != oracle.NO_KMER) & (seg < half)
     offs = np.zeros(half + 1, np.uint64)
     offs[1:] = np.cumsum(np.bincount(seg[keep], minlength=half))
+    g.set_insert_policy(rb.INSERT_DIRECT)
     g.insert_kmers(dev(first.set_ids, np.int32), dev(offs, np.int64), dev(codes[keep].copy(), np.int64))
+    g.set_insert_policy(rb.INSERT_PARTITIONED)
     gpu_insert_seqs(g, rest)
     assert torch.equal(g.index_words(), g_direct.index_words())
     g.clear()
