@@ -102,24 +102,28 @@ ALU_OPS_PER_TARGET = 12
 # a raw 64-bit key is only mixed (19) before its bit targets
 ALU_OPS_PER_KEY = 19
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock: 39.3 T int32 ops/s
-TRAFFIC_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_mid.json")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+TRAFFIC_JSON = os.path.join(PROFILES, "traffic_mid.json")
+TRAFFIC_DOCS_JSON = os.path.join(PROFILES, "traffic_documents.json")
 
 
-def measured_traffic(names: dict) -> dict:
+def measured_traffic(names: dict, path: str = TRAFFIC_JSON) -> dict:
     """HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE) from the
-    committed rocprofv3 summary, for stage name -> kernel name as profiled;
-    empty when the summary is missing or the kernel sources changed since."""
+    committed rocprofv3 summary of one workload, for stage name -> kernel
+    name as profiled; empty when the summary is missing or the kernel sources
+    changed since."""
     from paper_1910_02611_amd.profsum import load_traffic
-    t = load_traffic(TRAFFIC_JSON)
+    t = load_traffic(path)
     if t is None:
         return {}
     return {stage: t["kernels"][k]["bytes"] for stage, k in names.items() if k in t["kernels"]}
 
 
-def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh=True):
+def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh=True, traffic_json=TRAFFIC_JSON):
     """Roofline entry of each timed kernel: algorithmic work per launch over
     its measured duration.  fresh: the insert went into an all-zero index,
-    so stage C writes the index without reading it."""
+    so stage C writes the index without reading it.  traffic_json: the
+    profiled HBM bytes of this workload's launches."""
     RE = R * eta
     SW = max(1, S // 32)
     targets = n_ins * RE
@@ -142,7 +146,7 @@ def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh
                                      "k_insert_kmers": "k_insert_kmers",
                                      "k_bin_regions": "k_bin_regions", "k_apply_regions": "k_apply_regions",
                                      "k_insert_seqs": "k_insert_seqs<%d, %d>" % (R, eta),
-                                     "k_query_kmers": "k_query_kmers<%d, %d, %d>" % (SW, R, eta)})
+                                     "k_query_kmers": "k_query_kmers<%d, %d, %d>" % (SW, R, eta)}, traffic_json)
     out = []
     for name, ms in kernels.items():
         if name not in work:
@@ -387,7 +391,8 @@ def documents(n_queries: int, steps: int = 3):
     t_q = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     n_keys, RE, S, W = int(docs.keys.size), cfg["R"] * cfg["eta"], g.row_bits, g.W
     # every timed insert follows a clear: stage C writes without reading back
-    roofs = kernel_rooflines(kernels, n_keys, q.size, cfg["R"], cfg["eta"], S, W, g.index_bytes, fresh=True)
+    roofs = kernel_rooflines(kernels, n_keys, q.size, cfg["R"], cfg["eta"], S, W, g.index_bytes, fresh=True,
+                             traffic_json=TRAFFIC_DOCS_JSON)
     ins_ms = kernels.get("k_insert_kmers")
     if ins_ms:
         # the direct insert (chosen for small batches): the 100 MB index sits
@@ -460,6 +465,21 @@ def fold_timing(g):
                          "work_per_launch": moved, "work": "old index read once + folded index written once"}}
 
 
+def calib_copy(gib: float):
+    """A streaming copy of known size (none for 0): the scale of the memory
+    counters."""
+    if gib <= 0:
+        return
+    import torch
+    from paper_1910_02611_amd.rambo import lib
+    n = int(gib * 2**30) // 16 * 16
+    buf = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+    assert lib().rambo_roofline_copy(buf.data_ptr(), buf.data_ptr() + n, n,
+                                     torch.cuda.current_stream().cuda_stream) == 0
+    torch.cuda.synchronize()
+    del buf
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,6 +498,8 @@ def main():
     ap.add_argument("--serve-loads", default="0.25,0.5,0.8,1.0")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run one streaming copy of this size (memory-counter calibration)")
+    ap.add_argument("--documents-only", action="store_true",
+                    help="run only the document-index section (its own profile), printing its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: RAMBO's hot path here has no multi-GPU part "
@@ -489,6 +511,11 @@ def main():
     from paper_1910_02611_amd.rambo import Rambo
 
     torch.cuda.set_device(0)
+    if args.documents_only:
+        res = {"documents": documents(args.doc_queries, steps=args.steps)}
+        calib_copy(args.calib_copy_gib)
+        print(json.dumps(res), flush=True)
+        return
     cfg = synth.INDEX_MID
     sets, q = build_workload(args.queries)
     g = Rambo(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed=2002)
@@ -520,15 +547,7 @@ def main():
     measured = None
     if not args.no_measured_ceilings:
         measured = measured_ceilings(g.index_bytes, S, R * eta, q_per_s, ins_per_s)
-    if args.calib_copy_gib > 0:
-        # a streaming copy of known size: the scale of the memory counters
-        from paper_1910_02611_amd.rambo import lib
-        n = int(args.calib_copy_gib * 2**30) // 16 * 16
-        buf = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
-        assert lib().rambo_roofline_copy(buf.data_ptr(), buf.data_ptr() + n, n,
-                                         torch.cuda.current_stream().cuda_stream) == 0
-        torch.cuda.synchronize()
-        del buf
+    calib_copy(args.calib_copy_gib)
     plain_rate, plain_same = None, None
     if args.plain_prefix > 0:
         plain_rate, plain_same = plain_path(g, codes, out, min(args.plain_prefix, q.n))

@@ -97,3 +97,60 @@ def test_wikipedia_sized_index_matches_oracle():
     got = host_u32(g.query_kmers(dev(q, np.int64)))
     assert np.array_equal(got, want)
     g.close()
+
+
+# Compile-time wide shapes (rows of 256 and 1024 bits, eta = 2) on word
+# queries of which many have busy answers, built from the partition with
+# the phi loads shared among the wave's terms.
+WIDE_BUSY = [
+    dict(K=2000, B=200, R=3, eta=2, k=31, m=20_000),
+    dict(K=3000, B=250, R=6, eta=2, k=31, m=16_000),
+    dict(K=6000, B=600, R=4, eta=2, k=31, m=20_000),
+    dict(K=5000, B=1000, R=3, eta=2, k=31, m=12_000),
+]
+
+
+def _partition_share(o, cfg, q):
+    """Share of the queries whose answer the kernels build from the
+    partition: no repetition empty and the cheaper cell lists still cost
+    more than K * R lookups (or over 512 cells)."""
+    W = (cfg["K"] + 31) // 32
+    hits = 0
+    for x in q:
+        npos = o.query_cells(int(x)).sum(1)
+        if (npos == 0).any():
+            continue
+        cost = int(np.minimum(npos, cfg["B"] - npos).sum())
+        hits += cost > 512 or cost * W > cfg["K"] * cfg["R"]
+    return hits / len(q)
+
+
+@pytest.mark.parametrize("cfg", WIDE_BUSY, ids=lambda c: "K%(K)d-B%(B)d-R%(R)d" % c)
+def test_busy_answers_match_oracle(cfg):
+    seed = cfg["B"] + 29
+    docs = synth.documents(seed, cfg["K"], vocab=5000, median_len=150, min_len=1, max_len=800)
+    o, g = _pair(cfg, seed)
+    _insert(o, g, docs)
+    q = synth.word_queries(seed + 1, docs, 6000, present_frac=0.8)
+    assert _partition_share(o, cfg, q[:400]) > 0.1      # the partition path is exercised
+    want = o.query_kmers(q, nthreads=8)
+    for n in (6000, 4093, 37, 1):                        # many workgroups, ragged, one wave, one term
+        got = host_u32(g.query_kmers(dev(q[:n], np.int64)))
+        assert np.array_equal(got, want[:n]), n
+    g.close()
+
+
+@pytest.mark.parametrize("cfg", [dict(K=3000, B=2000, R=2, eta=4, k=31, m=4096),
+                                 dict(K=6000, B=600, R=4, eta=2, k=31, m=20_000)],
+                         ids=["B2000-R2-e4", "B600-R4-e2"])
+def test_large_word_batches_match_oracle(cfg):
+    # large batches (3e5 terms, tens of thousands of workgroups)
+    seed = 7
+    docs = synth.documents(seed, cfg["K"], vocab=5000, median_len=150, min_len=1, max_len=800)
+    o, g = _pair(cfg, seed)
+    _insert(o, g, docs)
+    q = synth.word_queries(seed + 1, docs, 300_000, present_frac=0.8)
+    want = o.query_kmers(q, nthreads=16)
+    assert np.array_equal(host_u32(g.query_kmers(dev(q, np.int64))), want)
+    assert np.array_equal(host_u32(g.query_kmers(dev(q[:70_001], np.int64))), want[:70_001])
+    g.close()
