@@ -122,9 +122,7 @@ void rambo_destroy(rambo_t *h);
  * Sec. 3.1); order does not matter.  Device errors: RAMBO_ERANGE (set id),
  * RAMBO_ECODE (code >= 4^k, k-mer indexes only) - the item is skipped.
  * With RAMBO_FLAG_RAW_KEYS the codes are the keys.  The insert policy
- * (rambo_set_insert_policy) applies as for sequences where the shape has a
- * partitioned code kernel (R in 3..6 with eta = 2, or R = 2 with eta = 4);
- * other shapes always insert directly. */
+ * (rambo_set_insert_policy) applies as for sequences. */
 int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uint64_t *offsets,
                        uint64_t n_sets, const uint64_t *codes, uint64_t n_codes,
                        hipStream_t stream);

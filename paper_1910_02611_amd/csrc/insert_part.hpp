@@ -154,15 +154,16 @@ struct RunReservationT {
 };
 using RunReservation = RunReservationT<kMaxBucketsPerThread>;
 
-// Stage A over the windows starting in [p_begin, p_end).  Wave w of block g
-// walks `rounds * steps * 64` consecutive windows; each round the workgroup
-// gathers the targets of `steps` steps of every wave (at most kTileA), sorts
-// them by coarse bucket in LDS and writes them out run by run.
-template <int R_T, int ETA_T>
-__global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, const uint32_t *set_ids,
-                                                         const uint64_t *offsets, uint64_t n_seqs,
-                                                         const uint8_t *chars, uint64_t n_chars, uint64_t p_begin,
-                                                         uint64_t p_end, uint32_t steps, uint32_t rounds)
+// Stage A over the terms [p_begin, p_end) of a walker (WindowWalker over
+// sequence windows, CodeWalker over codes or keys; init_walker(w, first,
+// end) starts it).  Wave w of block g walks `rounds * steps * 64`
+// consecutive terms; each round the workgroup gathers the targets of `steps`
+// steps of every wave (at most kTileA), sorts them by coarse bucket in LDS
+// and writes them out run by run.
+template <int R_T, int ETA_T, class Walker, class Init>
+__device__ __forceinline__ void bin_generic(const Params &P, const BinGeom &G, const uint32_t *set_ids,
+                                            uint64_t p_begin, uint64_t p_end, uint32_t steps, uint32_t rounds,
+                                            Init &&init_walker)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *ent = lds;                                          // kTileA: low bits of each target
@@ -181,9 +182,9 @@ __global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, co
     const uint64_t w0 = p_begin + ((uint64_t)blockIdx.x * kWavesP + wv) * span;
     const uint64_t w1 = min(w0 + span, p_end);
     const bool busy = w0 < p_end;
-    WindowWalker walker;
+    Walker walker;
     if (busy)
-        walker.init(offsets, n_seqs, chars, n_chars, w0, w1, P.k, P.kmask);
+        init_walker(walker, w0, w1);
     SetCache cache;
     cache.init_seeds(P);
 
@@ -237,6 +238,31 @@ __global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, co
         }
         __syncthreads();
     }
+}
+
+template <int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlockP) void k_bin_windows(Params P, BinGeom G, const uint32_t *set_ids,
+                                                         const uint64_t *offsets, uint64_t n_seqs,
+                                                         const uint8_t *chars, uint64_t n_chars, uint64_t p_begin,
+                                                         uint64_t p_end, uint32_t steps, uint32_t rounds)
+{
+    bin_generic<R_T, ETA_T, WindowWalker>(P, G, set_ids, p_begin, p_end, steps, rounds,
+                                          [&](WindowWalker &w, uint64_t first, uint64_t end) {
+                                              w.init(offsets, n_seqs, chars, n_chars, first, end, P.k, P.kmask);
+                                          });
+}
+
+// Stage A from codes or raw keys for every shape (run-time R and eta).
+__global__ __launch_bounds__(kBlockP) void k_bin_codes(Params P, BinGeom G, const uint32_t *set_ids,
+                                                       const uint64_t *offsets, uint64_t n_sets,
+                                                       const uint64_t *codes, uint64_t p_begin, uint64_t p_end,
+                                                       uint32_t steps, uint32_t rounds)
+{
+    bin_generic<0, 0, CodeWalker>(P, G, set_ids, p_begin, p_end, steps, rounds,
+                                  [&](CodeWalker &w, uint64_t first, uint64_t end) {
+                                      w.init(offsets, n_sets, codes, first, end, P.k, P.kmask, P.raw_keys != 0,
+                                             P.err);
+                                  });
 }
 
 // Stage A for compile-time shapes: the targets of a round stay in registers

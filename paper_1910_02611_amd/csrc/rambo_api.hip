@@ -349,6 +349,22 @@ BinCodesFn pick_bin_codes_hold(uint32_t R, uint32_t eta)
     return nullptr;
 }
 
+using BinCodesGenFn = void (*)(Params, BinGeom, const uint32_t *, const uint64_t *, uint64_t, const uint64_t *,
+                               uint64_t, uint64_t, uint32_t, uint32_t);
+
+// The stage-A kernel from codes of a shape: held targets where compiled,
+// else the run-time kernel; its steps per round and LDS bytes.
+struct StageACodes {
+    BinCodesFn hold = nullptr;
+    BinCodesGenFn generic = nullptr;
+    uint32_t steps = 0;
+    size_t lds = 0;
+    const void *fn() const
+    {
+        return hold ? reinterpret_cast<const void *>(hold) : reinterpret_cast<const void *>(generic);
+    }
+};
+
 // The stage-A kernel of a shape, its steps per round and its LDS bytes.
 struct StageA {
     BinWindowsFn generic = nullptr;
@@ -367,6 +383,22 @@ StageA stage_a(const rambo *h)
         a.lds = lds_bytes_stage_a_hold(RE, h->bin.na);
     } else {
         a.generic = pick_shape<BinWindowsFn, BinWindowsK>(h->cfg.R, h->cfg.eta);
+        a.steps = kTileA / (kBlockP * RE);
+        a.lds = lds_bytes_stage_a(h->bin.na);
+    }
+    return a;
+}
+
+StageACodes stage_a_codes(const rambo *h)
+{
+    const uint32_t RE = h->cfg.R * h->cfg.eta;
+    StageACodes a;
+    a.hold = h->bin.na <= kHoldBucketsPerThread * kBlockP ? pick_bin_codes_hold(h->cfg.R, h->cfg.eta) : nullptr;
+    if (a.hold) {
+        a.steps = hold_steps(RE);
+        a.lds = lds_bytes_stage_a_hold(RE, h->bin.na);
+    } else {
+        a.generic = k_bin_codes;
         a.steps = kTileA / (kBlockP * RE);
         a.lds = lds_bytes_stage_a(h->bin.na);
     }
@@ -544,12 +576,9 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     // stages A and B use more than the default 64 KiB of dynamic LDS
     const StageA A = stage_a(h);
     const void *binA = A.hold ? reinterpret_cast<const void *>(A.hold) : reinterpret_cast<const void *>(A.generic);
-    const BinCodesFn codesA = G.na <= kHoldBucketsPerThread * kBlockP ? pick_bin_codes_hold(h->cfg.R, h->cfg.eta)
-                                                                      : nullptr;
+    const StageACodes AC = stage_a_codes(h);
     if (hipFuncSetAttribute(binA, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds) != hipSuccess ||
-        (codesA && hipFuncSetAttribute(reinterpret_cast<const void *>(codesA),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_bytes_stage_a_hold(h->cfg.R * h->cfg.eta, G.na)) != hipSuccess) ||
+        hipFuncSetAttribute(AC.fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)AC.lds) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void *>(k_bin_regions),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_b(G.nf)) != hipSuccess) {
         (void)hipFree(h->bin_mem);
@@ -586,20 +615,19 @@ bool use_partitioned(const rambo *h, uint64_t n_chars)
     return t_part < t_direct;
 }
 
-// Stages A to C for codes or raw keys (the shape has a held-target kernel:
-// pick_bin_codes_hold), in batches of the scratch's capacity.
-int insert_kmers_partitioned(rambo *h, BinCodesFn binA, const uint32_t *set_ids, const uint64_t *offsets,
-                             uint64_t n_sets, const uint64_t *codes, uint64_t n_codes, hipStream_t stream)
+// Stages A to C for codes or raw keys, in batches of the scratch's capacity.
+int insert_kmers_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_sets,
+                             const uint64_t *codes, uint64_t n_codes, hipStream_t stream)
 {
     const uint64_t RE = (uint64_t)h->cfg.R * h->cfg.eta;
     int rc = ensure_scratch(h, n_codes * RE);
     if (rc)
         return rc;
     BinGeom &G = h->bin;
-    const size_t ldsA = lds_bytes_stage_a_hold((uint32_t)RE, G.na), ldsB = lds_bytes_stage_b(G.nf),
-                 ldsC = (1ull << (G.rb - 5)) * 4;
+    const StageACodes A = stage_a_codes(h);
+    const size_t ldsA = A.lds, ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     const uint64_t batch = h->bin_targets / RE;
-    const uint32_t steps = hold_steps((uint32_t)RE);
+    const uint32_t steps = A.steps;
     const uint32_t rounds = (uint32_t)div_up(kStageAWindowsPerWave, (uint64_t)steps * kWave);
     const uint64_t block_codes = (uint64_t)kWavesP * rounds * steps * kWave;
     const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
@@ -613,8 +641,13 @@ int insert_kmers_partitioned(rambo *h, BinCodesFn binA, const uint32_t *set_ids,
         hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
                            (uint64_t)G.na + 2ull * G.na * G.nf); }   // fillA, fillB, dirty
         { StageScope sc(h, "k_bin_codes", stream);
-        hipLaunchKernelGGL(binA, dim3((uint32_t)div_up(pe - p, block_codes)), dim3(kBlockP), ldsA, stream, h->P, G,
-                           set_ids, offsets, n_sets, codes, p, pe, rounds); }
+        const dim3 grid((uint32_t)div_up(pe - p, block_codes));
+        if (A.hold)
+            hipLaunchKernelGGL(A.hold, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_sets, codes, p,
+                               pe, rounds);
+        else
+            hipLaunchKernelGGL(A.generic, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_sets, codes,
+                               p, pe, steps, rounds); }
         { StageScope sc(h, "k_bin_regions", stream);
         hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
         { StageScope sc(h, "k_apply_regions", stream);
@@ -949,9 +982,8 @@ extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uin
         return RAMBO_OK;
     if (!set_ids || !offsets || !codes)
         return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
-    if (use_partitioned(h, n_codes) && h->bin.na <= kHoldBucketsPerThread * kBlockP)
-        if (const BinCodesFn binA = pick_bin_codes_hold(h->cfg.R, h->cfg.eta))
-            return insert_kmers_partitioned(h, binA, set_ids, offsets, n_sets, codes, n_codes, stream);
+    if (use_partitioned(h, n_codes))
+        return insert_kmers_partitioned(h, set_ids, offsets, n_sets, codes, n_codes, stream);
     note_insert(h, stream);
     StageScope sc(h, "k_insert_kmers", stream);
     hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,

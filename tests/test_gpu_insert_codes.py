@@ -49,7 +49,8 @@ CASES = [
     (dict(K=200, B=50, R=3, eta=2, k=21, m=20_000), False),
     (dict(K=2000, B=300, R=2, eta=4, k=31, m=50_000), True),    # the documents shape
     (dict(K=500, B=100, R=6, eta=2, k=31, m=9000), True),
-    (dict(K=400, B=64, R=4, eta=3, k=31, m=1 << 14), True),     # no code kernel: always direct
+    (dict(K=400, B=64, R=4, eta=3, k=31, m=1 << 14), True),     # run-time shape: the generic stage A
+    (dict(K=150, B=30, R=1, eta=5, k=25, m=1 << 13), False),
 ]
 
 
