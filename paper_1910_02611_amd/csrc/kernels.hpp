@@ -891,6 +891,133 @@ __device__ __forceinline__ void expand_answer_wave(const Params &P, const uint32
     wave_sync_lds();   // the list is the next answer's
 }
 
+// ---------------------------------------- transposed deferred answers
+
+// A wave of k_query_kmers with rows of 32 or 64 words holds QPW = 256 / SW
+// terms.  Those of its terms whose answers come from the partition can be
+// tested together: their group masks, transposed so that each cell of each
+// repetition holds one bit per term (QPW bits: a nibble for SW = 64, a byte
+// for SW = 32), take exactly the space of the masks themselves, so the
+// planes overwrite them in the wave's LDS region.  One phi load and R plane
+// reads per set then serve every deferred term.
+
+// Bit j of the 8-bit b to bit 4 j.
+__device__ __forceinline__ uint32_t spread8_nibbles(uint32_t b)
+{
+    uint32_t x = b & 0xFFu;
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    return (x | (x << 3)) & 0x11111111u;
+}
+
+// Bit j of the 4-bit b to bit 8 j (the four shifted copies occupy disjoint
+// bit fields, so the product has no carry).
+__device__ __forceinline__ uint32_t spread4_bytes(uint32_t b) { return ((b & 0xFu) * 0x204081u) & 0x01010101u; }
+
+// Rewrites the wave's group masks gw (term qi's R_T x SW words at
+// gw + qi R_T SW) as planes: the element of cell c in repetition r (EB =
+// 256 / SW bits, at element index r 32 SW + c) has bit s set iff cell c is
+// positive for the s-th term of `deferred` (ascending qi).  Mask word w of
+// repetition r covers cells 32 w .. 32 w + 31, whose elements fill plane
+// words (r SW + w) EB .. + EB - 1.
+template <int SW, int R_T>
+__device__ __forceinline__ void transpose_deferred(uint32_t *gw, uint64_t deferred, uint32_t lane)
+{
+    constexpr uint32_t EB = 256 / SW;
+    constexpr uint32_t PAIRS = R_T * SW;
+    constexpr uint32_t PPL = (PAIRS + kWave - 1) / kWave;
+    static_assert(EB == 4 || EB == 8, "nibble or byte planes");
+    uint32_t pl[PPL][EB];
+#pragma unroll
+    for (uint32_t p = 0; p < PPL; ++p) {
+        const uint32_t pair = lane + p * kWave;
+#pragma unroll
+        for (uint32_t t = 0; t < EB; ++t)
+            pl[p][t] = 0u;
+        if (pair < PAIRS) {
+            uint32_t s = 0;
+            for (uint64_t d = deferred; d; d &= d - 1, ++s) {
+                const uint32_t g = gw[(uint32_t)__builtin_ctzll(d) * PAIRS + pair];
+#pragma unroll
+                for (uint32_t t = 0; t < EB; ++t)
+                    pl[p][t] |= (EB == 4 ? spread8_nibbles(g >> (8 * t)) : spread4_bytes(g >> (4 * t))) << s;
+            }
+        }
+    }
+    wave_sync_lds();   // every mask is read before any plane word is written
+#pragma unroll
+    for (uint32_t p = 0; p < PPL; ++p) {
+        const uint32_t pair = lane + p * kWave;
+        if (pair < PAIRS) {
+#pragma unroll
+            for (uint32_t t = 0; t < EB; ++t)
+                gw[pair * EB + t] = pl[p][t];
+        }
+    }
+    wave_sync_lds();
+}
+
+// The answers of the n deferred terms from the planes (transpose_deferred):
+// set i is in the answer of the s-th term iff bit s of its cell's element is
+// set in every repetition (the membership test of expand_by_partition).  The
+// s-th term's answer goes to out + ((ids >> 8 s) & 0xFF) W.  Lane l keeps
+// word l of each 2048-set stripe of every answer.
+template <int SW, int R_T>
+__device__ __forceinline__ void expand_planes_wave(const Params &P, const uint32_t *planes, uint32_t n, uint64_t ids,
+                                                   uint32_t *out, uint32_t lane)
+{
+    constexpr uint32_t EB = 256 / SW;
+    constexpr uint32_t C = 32 * SW;
+    constexpr uint32_t ALL = EB == 4 ? 0xFu : 0xFFu;
+    constexpr int TB = 8;
+    const uint8_t *pb = reinterpret_cast<const uint8_t *>(planes);
+    for (uint32_t base = 0; base < P.K; base += 64 * 32) {
+        uint32_t mine[EB];
+#pragma unroll
+        for (uint32_t s = 0; s < EB; ++s)
+            mine[s] = 0u;
+        const uint32_t tmax = min(32u, (P.K - base + 63) / 64);
+        for (uint32_t t0 = 0; t0 < tmax; t0 += TB) {
+            bool valid[TB];
+            uint32_t cell[TB][R_T];
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                const uint32_t i = base + (t0 + u) * 64 + lane;
+                valid[u] = t0 + u < tmax && i < P.K;
+#pragma unroll
+                for (int r = 0; r < R_T; ++r)
+                    cell[u][r] = valid[u] ? P.phi[(uint64_t)r * P.K + i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                if (t0 + u >= tmax)
+                    break;
+                uint32_t x = valid[u] ? ALL : 0u;
+#pragma unroll
+                for (int r = 0; r < R_T; ++r) {
+                    const uint32_t e = r * C + cell[u][r];
+                    x &= EB == 4 ? (uint32_t)(pb[e >> 1] >> ((e & 1u) * 4u)) : (uint32_t)pb[e];
+                }
+                const bool lo = lane == 2 * (t0 + u), hi = lane == 2 * (t0 + u) + 1;
+#pragma unroll
+                for (uint32_t s = 0; s < EB; ++s) {
+                    if (s >= n)
+                        break;
+                    const uint64_t m = __ballot((x >> s) & 1u);
+                    mine[s] = lo ? (uint32_t)m : hi ? (uint32_t)(m >> 32) : mine[s];
+                }
+            }
+        }
+        const uint32_t w = base / 32 + lane;
+        if (w < P.W) {
+#pragma unroll
+            for (uint32_t s = 0; s < EB; ++s)
+                if (s < n)
+                    out[((ids >> (8 * s)) & 0xFFu) * P.W + w] = mine[s];
+        }
+    }
+}
+
 // ---------------------------------------------------------- term queries
 
 // Alg. 2 for a batch of codes.  G lanes share one query when a row is wider
@@ -975,6 +1102,19 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
                                     lst + wv * kListCap, seg + wv * kSegs, &d);
             if (d)
                 deferred |= 1ull << qi;
+        }
+        if constexpr (R_T > 0 && (SW == 32 || SW == 64)) {
+            // all the wave's deferred terms at once, from transposed planes
+            if (deferred) {
+                uint64_t ids = 0;
+                uint32_t nd = 0;
+                for (uint64_t d = deferred; d; d &= d - 1, ++nd)
+                    ids |= (uint64_t)__builtin_ctzll(d) << (8 * nd);
+                uint32_t *gw = gs + wv * QPW * RMAX * SW;
+                transpose_deferred<SW, R_T>(gw, deferred, lane);
+                expand_planes_wave<SW, R_T>(P, gw, nd, ids, out + qbase * P.W, lane);
+            }
+            return;
         }
         constexpr int NQ = 4;
         while (deferred) {
