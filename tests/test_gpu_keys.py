@@ -107,6 +107,8 @@ WIDE_BUSY = [
     dict(K=3000, B=250, R=6, eta=2, k=31, m=16_000),
     dict(K=6000, B=600, R=4, eta=2, k=31, m=20_000),
     dict(K=5000, B=1000, R=3, eta=2, k=31, m=12_000),
+    dict(K=4000, B=700, R=5, eta=2, k=31, m=12_000),
+    dict(K=4000, B=520, R=6, eta=2, k=31, m=12_000),
 ]
 
 
