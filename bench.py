@@ -363,18 +363,21 @@ def documents(n_queries: int, steps: int = 3):
     t = time.time()
     docs = synth.config_wiki()
     q = synth.word_queries(3006, docs, n_queries)
+    ws = synth.word_sets(3007, docs, n_queries, min_words=1, max_words=4)
     log("documents: %d docs, %d keys, %d queries (%.1f s to generate)" % (docs.n, docs.keys.size, q.size,
                                                                          time.time() - t))
     g = Rambo(cfg["K"], cfg["B"], cfg["R"], cfg["eta"], cfg["k"], cfg["m"], seed=2006, flags=FLAG_RAW_KEYS)
     d = (to_dev(docs.set_ids, np.int32), to_dev(docs.offsets, np.int64), to_dev(docs.keys, np.int64))
     dq = to_dev(q, np.int64)
+    dws = (to_dev(ws.offsets, np.int64), to_dev(ws.keys, np.int64))
     out = torch.empty((q.size, g.W), dtype=torch.int32, device="cuda")
     g.insert_kmers(*d)
     g.query_kmers(dq, out=out)
+    g.query_termsets(*dws, out=out[: ws.n])
     torch.cuda.synchronize()
     g.set_timing(True)
     g.stage_times()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     for e in ev:
         g.clear()
         e[0].record()
@@ -382,6 +385,8 @@ def documents(n_queries: int, steps: int = 3):
         e[1].record()
         g.query_kmers(dq, out=out)
         e[2].record()
+        g.query_termsets(*dws, out=out[: ws.n])
+        e[3].record()
     torch.cuda.synchronize()
     kernels = {k: v / steps for k, v in g.stage_times().items()}
     g.set_timing(False)
@@ -389,6 +394,7 @@ def documents(n_queries: int, steps: int = 3):
         raise SystemExit("device error flag set (documents)")
     t_ins = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     t_q = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    t_ws = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
     n_keys, RE, S, W = int(docs.keys.size), cfg["R"] * cfg["eta"], g.row_bits, g.W
     # every timed insert follows a clear: stage C writes without reading back
     roofs = kernel_rooflines(kernels, n_keys, q.size, cfg["R"], cfg["eta"], S, W, g.index_bytes, fresh=True,
@@ -409,9 +415,15 @@ def documents(n_queries: int, steps: int = 3):
     res = {"workload": "word unigrams: K=17618 documents, B=2000, R=2, m=200000, eta=4 (raw 64-bit keys)",
            "keys": n_keys, "queries": int(q.size), "index_bytes": g.index_bytes,
            "insert_ms": t_ins, "keys_inserted_per_s": n_keys / t_ins * 1e3,
-           "query_ms": t_q, "word_queries_per_s": q.size / t_q * 1e3, "kernel_ms": kernels, "rooflines": roofs}
-    log("documents: insert %.2f ms (%.3g keys/s), query %.2f ms (%.3g queries/s)"
-        % (t_ins, res["keys_inserted_per_s"], t_q, res["word_queries_per_s"]))
+           "query_ms": t_q, "word_queries_per_s": q.size / t_q * 1e3,
+           "word_sets": {"sets": ws.n, "words": int(ws.keys.size), "query_ms": t_ws,
+                         "sets_per_s": ws.n / t_ws * 1e3,
+                         "what": "1-4 words per query, half of them from one document, answered by "
+                                 "rambo_query_termsets (the documents holding every word)"},
+           "kernel_ms": kernels, "rooflines": roofs}
+    log("documents: insert %.2f ms (%.3g keys/s), query %.2f ms (%.3g queries/s), %d word sets %.2f ms "
+        "(%.3g sets/s)" % (t_ins, res["keys_inserted_per_s"], t_q, res["word_queries_per_s"], ws.n, t_ws,
+                           res["word_sets"]["sets_per_s"]))
     for r in roofs:
         log("  %-16s %8.3f ms  %-6s %.3g %s (%.1f%%)" % (r["kernel"], r["ms"], r["bound"], r["achieved"], r["unit"],
                                                       100 * r["frac"]))

@@ -141,6 +141,18 @@ int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint64_t *offse
 int rambo_query_kmers(rambo_t *h, const uint64_t *codes, uint64_t n,
                       uint32_t *out_masks, hipStream_t stream);
 
+/* Sec. 3.2.1 for n_sets sets of terms given as codes (or raw keys with
+ * RAMBO_FLAG_RAW_KEYS): term set q is codes[offsets[q] .. offsets[q+1]) and
+ * its answer, out_masks[q*W .. q*W+W), is the intersection of the answers
+ * of its terms (Alg. 2 per term) - for a document index, the documents that
+ * hold every word of a multi-word query.  offsets: n_sets+1 device entries,
+ * non-decreasing, offsets[n_sets] <= n_codes.  An empty term set answers the
+ * empty set.  A code >= 4^k (k-mer indexes) empties its set's answer and
+ * raises RAMBO_ECODE.  codes may be NULL when n_codes is 0. */
+int rambo_query_termsets(rambo_t *h, const uint64_t *offsets, uint64_t n_sets,
+                         const uint64_t *codes, uint64_t n_codes, uint32_t *out_masks,
+                         hipStream_t stream);
+
 /* Sec. 3.2.1 for n_reads sequences (bytes chars[offsets[q] .. offsets[q+1])):
  * the answer is the intersection of the answers of all valid k-windows of
  * the read.  A read with no valid window answers the empty set.

@@ -1345,6 +1345,77 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
     dead = any_rep_empty(G, R_T, SW);
 }
 
+// One step of Sec. 3.2.1: the group masks of the wave's terms (one per lane,
+// mixed: hx; valid where the lane holds a term) ANDed over the lanes and into
+// the running masks G (R x SW words of LDS, wave-private); dead once some
+// repetition is empty (the first conclusive FALSE).  Repetition 0 first:
+// once its running AND has no cell left the answer is empty (the
+// intersection of Alg. 2), so the rows of the other repetitions are read
+// only while it has one.
+template <int SW, int R_T, int ETA_T>
+__device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, bool valid, uint32_t *G, bool &dead,
+                                               uint32_t lane)
+{
+    constexpr int L = SW < 4 ? SW : 4;
+    constexpr int NSL = SW / L;
+    if constexpr (R_T > 0 && SW >= 8) {
+        probe_step_wide<SW, R_T, ETA_T>(P, hx, valid, G, dead, lane);
+    } else if constexpr (R_T > 0) {
+#pragma unroll 1
+        for (int sl = 0; sl < NSL; ++sl) {
+            uint32_t g0[1][L];
+            Probe<SW, L, 1, ETA_T>::run(P, hx, sl * L, valid, g0);
+#pragma unroll
+            for (int w = 0; w < L; ++w) {
+                const uint32_t a = wave_and(valid ? g0[0][w] : ~0u);
+                if (lane == 0)
+                    G[sl * L + w] &= a;
+            }
+        }
+        wave_sync_lds();
+        uint32_t left = 0;
+        for (int w = 0; w < SW; ++w)
+            left |= G[w];
+        if (left == 0) {
+            dead = true;
+            return;
+        }
+        if constexpr (R_T > 1) {
+#pragma unroll 1
+            for (int sl = 0; sl < NSL; ++sl) {
+                uint32_t g[R_T - 1][L];
+                Probe<SW, L, R_T - 1, ETA_T>::run(P, hx, sl * L, valid, g, 1);
+#pragma unroll
+                for (int r = 1; r < R_T; ++r)
+#pragma unroll
+                    for (int w = 0; w < L; ++w) {
+                        const uint32_t a = wave_and(valid ? g[r - 1][w] : ~0u);
+                        if (lane == 0)
+                            G[r * SW + sl * L + w] &= a;
+                    }
+            }
+        }
+        wave_sync_lds();
+        dead = any_rep_empty(G, R_T, SW);
+    } else {
+#pragma unroll 1
+        for (int sl = 0; sl < NSL; ++sl) {
+            for (uint32_t r = 0; r < P.R; ++r) {
+                uint32_t acc[L];
+                probe_rep<SW, L>(P, hx, r, sl * L, valid, acc);
+#pragma unroll
+                for (int w = 0; w < L; ++w) {
+                    const uint32_t a = wave_and(valid ? acc[w] : ~0u);
+                    if (lane == 0)
+                        G[r * SW + sl * L + w] &= a;
+                }
+            }
+        }
+        wave_sync_lds();
+        dead = any_rep_empty(G, P.R, SW);
+    }
+}
+
 // Sec. 3.2.1 for the windows of one read (bytes end at pe) that start in
 // [p_start, p_stop): each step takes 64 windows (one per lane), gathers their
 // rows, ANDs the group masks over the lanes and into the running masks G
@@ -1356,9 +1427,6 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
                                                  uint64_t p_start, uint64_t p_stop, uint32_t *G, uint32_t &nk,
                                                  bool &dead)
 {
-    constexpr int L = SW < 4 ? SW : 4;
-    constexpr int NSL = SW / L;
-    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
     const uint32_t lane = lane_id();
     const uint64_t kmask = P.kmask;
     auto read_byte = [&](uint64_t p, uint32_t &v, bool &bad) {
@@ -1375,73 +1443,8 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
         uint64_t x = 0;
         const bool valid = (p + lane < p_stop) && window_code(A, Bg, lane, P.k, kmask, x);
         nk += (uint32_t)__popcll(__ballot(valid));
-        const uint64_t hx = mix64(x);
-        if constexpr (R_T > 0 && SW >= 8) {
-            if (!dead)
-                probe_step_wide<SW, R_T, ETA_T>(P, hx, valid, G, dead, lane);
-            A = Bg;
-            continue;
-        }
-        if (!dead) {
-            if constexpr (R_T > 0) {
-                // Repetition 0 first: once its running AND has no cell left the
-                // read's answer is empty (the intersection of Alg. 2), so the
-                // rows of the other repetitions are read only while it has one.
-#pragma unroll 1
-                for (int sl = 0; sl < NSL; ++sl) {
-                    uint32_t g0[1][L];
-                    Probe<SW, L, 1, ETA_T>::run(P, hx, sl * L, valid, g0);
-#pragma unroll
-                    for (int w = 0; w < L; ++w) {
-                        const uint32_t a = wave_and(valid ? g0[0][w] : ~0u);
-                        if (lane == 0)
-                            G[sl * L + w] &= a;
-                    }
-                }
-                wave_sync_lds();
-                uint32_t left = 0;
-                for (int w = 0; w < SW; ++w)
-                    left |= G[w];
-                if (left == 0) {
-                    dead = true;
-                    A = Bg;
-                    continue;
-                }
-                if constexpr (R_T > 1) {
-#pragma unroll 1
-                    for (int sl = 0; sl < NSL; ++sl) {
-                        uint32_t g[R_T - 1][L];
-                        Probe<SW, L, R_T - 1, ETA_T>::run(P, hx, sl * L, valid, g, 1);
-#pragma unroll
-                        for (int r = 1; r < R_T; ++r)
-#pragma unroll
-                            for (int w = 0; w < L; ++w) {
-                                const uint32_t a = wave_and(valid ? g[r - 1][w] : ~0u);
-                                if (lane == 0)
-                                    G[r * SW + sl * L + w] &= a;
-                            }
-                    }
-                }
-            } else {
-#pragma unroll 1
-            for (int sl = 0; sl < NSL; ++sl) {
-                {
-                    for (uint32_t r = 0; r < R; ++r) {
-                        uint32_t acc[L];
-                        probe_rep<SW, L>(P, hx, r, sl * L, valid, acc);
-#pragma unroll
-                        for (int w = 0; w < L; ++w) {
-                            const uint32_t a = wave_and(valid ? acc[w] : ~0u);
-                            if (lane == 0)
-                                G[r * SW + sl * L + w] &= a;
-                        }
-                    }
-                }
-            }
-            }
-            wave_sync_lds();
-            dead = any_rep_empty(G, R, SW);
-        }
+        if (!dead)
+            and_terms_step<SW, R_T, ETA_T>(P, mix64(x), valid, G, dead, lane);
         A = Bg;
     }
 }
@@ -1490,6 +1493,53 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
     __shared__ uint16_t lst[kWavesPerBlock * kListCap];
     __shared__ uint16_t seg[kWavesPerBlock * kSegs];
     expand_answer_wave<R_T>(P, G, R, SW, dead || nk == 0, out + q * P.W, lane, lst + wv * kListCap,
+                            seg + wv * kSegs);
+}
+
+// Sec. 3.2.1 for sets of terms given as codes (or raw keys): the answer of
+// term set q, the codes codes[offsets[q] .. offsets[q+1]), holds the sets
+// that hold every one of its terms.  One wave per term set, 64 terms per
+// step: the group masks are ANDed over the terms (stopping at the first
+// empty repetition) and expanded once.  An empty term set gets an empty
+// answer; a k-mer code >= 4^k raises kErrCode and empties its set's answer
+// (its own answer is empty).
+template <int SW, int R_T, int ETA_T>
+__global__ __launch_bounds__(kBlock) void k_query_termsets(Params P, const uint64_t *offsets, uint64_t n_sets,
+                                                           const uint64_t *codes, uint64_t n_codes, uint32_t *out)
+{
+    constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
+    __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
+    __shared__ uint16_t lst[kWavesPerBlock * kListCap];
+    __shared__ uint16_t seg[kWavesPerBlock * kSegs];
+
+    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (q >= n_sets)
+        return;
+    uint32_t *G = Gs[wv];
+    for (uint32_t i = lane; i < R * SW; i += kWave)
+        G[i] = ~0u;
+    wave_sync_lds();
+
+    uint64_t p0 = offsets[q];
+    const uint64_t pe = min(offsets[q + 1], n_codes);
+    if (p0 > pe)
+        p0 = pe;
+    bool dead = false;
+    for (uint64_t p = p0; p < pe; p += kWave) {
+        const bool live = p + lane < pe;
+        const uint64_t code = live ? codes[p + lane] : 0;
+        const bool bad = live && code > P.kmask;
+        if (bad)
+            atomicOr(P.err, kErrCode);
+        dead = dead || __ballot(bad) != 0;
+        if (!dead)
+            and_terms_step<SW, R_T, ETA_T>(P, mix64(P.raw_keys ? code : canonical(code & P.kmask, P.k)), live, G,
+                                           dead, lane);
+    }
+    expand_answer_wave<R_T>(P, G, R, SW, dead || pe == p0, out + q * P.W, lane, lst + wv * kListCap,
                             seg + wv * kSegs);
 }
 

@@ -227,6 +227,27 @@ struct QueryKmersLaunch {
     void operator()() const { launch_query_kmers_t<SW, R_T, ETA_T>(h, codes, n, out, st); }
 };
 
+template <int SW, int R_T, int ETA_T>
+void launch_query_termsets_t(const rambo *h, const uint64_t *offsets, uint64_t n_sets, const uint64_t *codes,
+                             uint64_t n_codes, uint32_t *out, hipStream_t st)
+{
+    StageScope sc(h, "k_query_termsets", st);
+    hipLaunchKernelGGL((k_query_termsets<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_sets, kWavesPerBlock)),
+                       dim3(kBlock), 0, st, h->P, offsets, n_sets, codes, n_codes, out);
+}
+
+struct QueryTermsetsLaunch {
+    const rambo *h;
+    const uint64_t *offsets;
+    uint64_t n_sets;
+    const uint64_t *codes;
+    uint64_t n_codes;
+    uint32_t *out;
+    hipStream_t st;
+    template <int SW, int R_T, int ETA_T>
+    void operator()() const { launch_query_termsets_t<SW, R_T, ETA_T>(h, offsets, n_sets, codes, n_codes, out, st); }
+};
+
 struct QuerySeqsLaunch {
     const rambo *h;
     const uint64_t *offsets;
@@ -1018,6 +1039,19 @@ extern "C" int rambo_query_kmers(rambo_t *h, const uint64_t *codes, uint64_t n, 
         return fail(h, RAMBO_EINVAL, "rambo_query_kmers: NULL array");
     with_row_words(h, QueryKmersLaunch{h, codes, n, out_masks, stream});
     return launch_check(h, "rambo_query_kmers");
+}
+
+extern "C" int rambo_query_termsets(rambo_t *h, const uint64_t *offsets, uint64_t n_sets, const uint64_t *codes,
+                                    uint64_t n_codes, uint32_t *out_masks, hipStream_t stream)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    if (n_sets == 0)
+        return RAMBO_OK;
+    if (!offsets || !out_masks || (n_codes > 0 && !codes))
+        return fail(h, RAMBO_EINVAL, "rambo_query_termsets: NULL array");
+    with_row_words(h, QueryTermsetsLaunch{h, offsets, n_sets, codes, n_codes, out_masks, stream});
+    return launch_check(h, "rambo_query_termsets");
 }
 
 extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,

@@ -66,6 +66,8 @@ EXPORTS = {
                                          ctypes.c_void_p]),
     "rambo_query_seqs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                         ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_query_termsets": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                            ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_extract_kmers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                            ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_query_seqs_ids": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
@@ -243,6 +245,19 @@ class Rambo:
         fn = lib().rambo_query_kmers_plain if plain else lib().rambo_query_kmers
         self._check(fn(self._h, _dptr(codes, _U64, "codes"), n, _dptr(out, _U32, "out"), _stream(stream)),
                     "rambo_query_kmers")
+        return out
+
+    def query_termsets(self, offsets, codes, out=None, stream=None):
+        """Sec. 3.2.1 for term sets: set q is codes[offsets[q]:offsets[q+1]];
+        its answer holds the sets that hold every term (int64 device
+        tensors in, [n_sets, W] int32 masks out)."""
+        n = offsets.numel() - 1
+        if out is None:
+            out = torch.empty((n, self.W), dtype=torch.int32, device=offsets.device)
+        self._check(lib().rambo_query_termsets(self._h, _dptr(offsets, _U64, "offsets"), n,
+                                               _dptr(codes, _U64, "codes") if codes.numel() else None,
+                                               codes.numel(), _dptr(out, _U32, "out"), _stream(stream)),
+                    "rambo_query_termsets")
         return out
 
     def query_seqs(self, offsets, chars, out=None, nkmers=None, stream=None, plain=False, want_nkmers=True):

@@ -238,6 +238,31 @@ def word_queries(seed: int, docs: KeyBatch, n: int, present_frac: float = 0.5) -
     return rng.permutation(q).astype(np.uint64)
 
 
+def word_sets(seed: int, docs: KeyBatch, n: int, min_words: int = 1, max_words: int = 4,
+              from_doc_frac: float = 0.5) -> KeyBatch:
+    """n multi-word queries (term sets, Sec. 3.2.1 applied to words): each
+    has a uniform number of words in [min_words, max_words]; a share
+    from_doc_frac of them take their words from one random document (so it
+    answers them), the rest draw vocabulary words by the Zipf law of the
+    text.  Words may repeat within a query."""
+    rng = rng_for(seed)
+    vocab = docs.meta["vocab"]
+    lens = rng.integers(min_words, max_words + 1, size=n)
+    offsets = np.zeros(n + 1, np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    owner = np.repeat(np.arange(n), lens)
+    dl = docs.lengths().astype(np.int64)
+    nonempty = np.nonzero(dl > 0)[0]
+    from_doc = (rng.random(n) < from_doc_frac) & (nonempty.size > 0)
+    doc = nonempty[rng.integers(0, max(1, nonempty.size), size=n)] if nonempty.size else np.zeros(n, np.int64)
+    kd = from_doc[owner]
+    keys = vocab[zipf_ranks(rng, owner.size, vocab.size, docs.meta["zipf_s"])].astype(np.uint64)
+    dk = doc[owner[kd]]
+    pos = docs.offsets[dk].astype(np.int64) + (rng.random(dk.size) * dl[dk]).astype(np.int64)
+    keys[kd] = docs.keys[pos]
+    return KeyBatch(keys, offsets)
+
+
 # ---------------------------------------------------------------- workloads
 
 def config_tiny(seed: int = 1001) -> SeqBatch:

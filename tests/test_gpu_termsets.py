@@ -1,0 +1,107 @@
+"""GPU parity of term-set queries (Sec. 3.2.1 applied to sets of codes or
+keys, rambo_query_termsets): the answer of a term set equals the
+intersection of the oracle's answers of its terms (the definition of the
+conjunction), on multi-word document queries over raw-key indexes and on the
+k-mer codes of reads, where it also equals the oracle's read answer.  Empty
+sets answer the empty set; a bad code empties its set and is reported."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_02611_amd import rambo as rb
+from paper_1910_02611_amd import synth
+from gpu_util import dev, host_u32, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _conjunction(o, batch):
+    """AND over each set of the oracle's per-term answers; empty sets and
+    sets with a term the oracle rejects get zeros."""
+    per = o.query_kmers(batch.keys, nthreads=8) if batch.keys.size else None
+    out = np.zeros((batch.n, (o.K + 31) // 32), np.uint32)
+    for i in range(batch.n):
+        a, b = int(batch.offsets[i]), int(batch.offsets[i + 1])
+        if b > a:
+            out[i] = np.bitwise_and.reduce(per[a:b], axis=0)
+    return out
+
+
+def _gpu(g, batch):
+    return host_u32(g.query_termsets(dev(batch.offsets, np.int64), dev(batch.keys, np.int64)))
+
+
+SHAPES = [
+    dict(K=300, B=50, R=4, eta=2, k=31, m=1 << 14),      # 64-bit rows, compiled shape
+    dict(K=400, B=200, R=3, eta=2, k=31, m=20_000),      # 256-bit rows, compiled shape
+    dict(K=500, B=60, R=2, eta=3, k=31, m=1 << 14),      # run-time shape
+    dict(K=3000, B=2000, R=2, eta=4, k=31, m=4096),      # 2048-bit rows (the document-index shape)
+]
+
+
+@pytest.mark.parametrize("cfg", SHAPES, ids=lambda c: "B%(B)d-R%(R)d-e%(eta)d" % c)
+def test_word_sets_match_conjunction(cfg):
+    seed = cfg["B"] + 41
+    docs = synth.documents(seed, cfg["K"], vocab=4000, median_len=120, min_len=0, max_len=600)
+    o, g = make_pair(cfg, seed=seed, flags=oracle.FLAG_RAW_KEYS)
+    assert o.insert_kmers(docs.set_ids, docs.offsets, docs.keys, 8) == 0
+    g.insert_kmers(dev(docs.set_ids, np.int32), dev(docs.offsets, np.int64), dev(docs.keys, np.int64))
+    q = synth.word_sets(seed + 1, docs, 3000, min_words=0, max_words=5)
+    want = _conjunction(o, q)
+    got = _gpu(g, q)
+    assert np.array_equal(got, want)
+    assert not got[np.diff(q.offsets) == 0].any()         # empty sets answer nothing
+    # long sets: several 64-term steps, and a set made of one document's
+    # whole vocabulary (the document must be in its answer)
+    lq = synth.word_sets(seed + 2, docs, 200, min_words=60, max_words=200, from_doc_frac=1.0)
+    assert np.array_equal(_gpu(g, lq), _conjunction(o, lq))
+    d = int(np.argmax(docs.lengths()))
+    whole = synth.KeyBatch(docs.keys[int(docs.offsets[d]):int(docs.offsets[d + 1])].copy(),
+                           np.array([0, int(docs.lengths()[d])], np.uint64))
+    ans = _gpu(g, whole)[0]
+    assert (ans[d // 32] >> (d % 32)) & 1
+    assert np.array_equal(ans, _conjunction(o, whole)[0])
+    assert g.sync_status() == rb.OK
+    g.close()
+
+
+def test_kmer_sets_equal_read_answers():
+    # the term set of a read's valid k-mer codes answers as the read does
+    cfg = dict(K=200, B=40, R=4, eta=2, k=21, m=1 << 15)
+    sets = synth.genome_sets(51, K=200, n_ancestors=6, ancestor_len=2000)
+    o, g = make_pair(cfg, seed=51)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    g.insert_seqs(dev(sets.set_ids, np.int32), dev(sets.offsets, np.int64), dev(sets.chars, np.uint8))
+    rd = synth.reads(52, sets, 400, median_len=150, min_len=10, max_len=600, substr_frac=0.7)
+    want, wk = o.query_seqs(rd.offsets, rd.chars, nthreads=8)
+    codes = oracle.extract(rd.offsets, rd.chars, cfg["k"])
+    keep = codes != oracle.NO_KMER
+    seg = np.searchsorted(rd.offsets[1:], np.arange(codes.size), side="right")
+    offs = np.zeros(rd.n + 1, np.uint64)
+    offs[1:] = np.cumsum(np.bincount(seg[keep], minlength=rd.n))
+    kc = codes[keep].copy()
+    kc[1::2] = np.array([oracle.revcomp(int(c), cfg["k"]) for c in kc[1::2]], np.uint64)
+    got = _gpu(g, synth.KeyBatch(kc, offs))
+    assert np.array_equal(got, want)
+    assert np.array_equal(np.diff(offs).astype(np.int64), wk.astype(np.int64))
+    g.close()
+
+
+def test_bad_code_empties_its_set():
+    cfg = dict(K=64, B=8, R=3, eta=2, k=11, m=1 << 12)
+    sets = synth.genome_sets(53, K=64, n_ancestors=4, ancestor_len=500)
+    o, g = make_pair(cfg, seed=53)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 4)
+    g.insert_seqs(dev(sets.set_ids, np.int32), dev(sets.offsets, np.int64), dev(sets.chars, np.uint8))
+    codes = oracle.extract(sets.offsets[:2], sets.chars[: int(sets.offsets[1])], cfg["k"])
+    codes = codes[codes != oracle.NO_KMER][:100]
+    bad = codes.copy()
+    bad[70] = 1 << 22                                    # 4^11
+    keys = np.concatenate([codes, bad])
+    offs = np.array([0, 100, 200, 200], np.uint64)       # good, bad, empty
+    got = _gpu(g, synth.KeyBatch(keys, offs))
+    assert g.sync_status() == rb.ECODE
+    assert np.array_equal(got[0], _conjunction(o, synth.KeyBatch(codes, np.array([0, 100], np.uint64)))[0])
+    assert got[0].any()
+    assert not got[1].any() and not got[2].any()
+    g.close()
