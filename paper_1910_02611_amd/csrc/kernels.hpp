@@ -1248,10 +1248,11 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
 // finished); then the other repetitions, all rows of a round in flight.
 // The per-slice ANDs are reduced over the lanes of the same slice and
 // folded into G (R x SW words of LDS); dead is set when some repetition is
-// empty.
+// empty.  Only the first n_it rounds run: a caller whose valid lanes are
+// the first WPI n_it ones (a short term set) skips the empty rounds.
 template <int SW, int R_T, int ETA_T>
 __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bool valid, uint32_t *G, bool &dead,
-                                                uint32_t lane)
+                                                uint32_t lane, int n_it = SW / 4)
 {
     constexpr int GL = SW / 4, WPI = kWave / GL;
     static_assert(GL >= 2 && GL * 4 == SW, "wide rows");
@@ -1278,7 +1279,7 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
     const u32x4 ones = {~0u, ~0u, ~0u, ~0u};
     u32x4 acc0 = ones;
 #pragma unroll 4
-    for (int it = 0; it < GL; ++it) {
+    for (int it = 0; it < n_it; ++it) {
         uint64_t h;
         bool ok;
         window(it, h, ok);
@@ -1311,7 +1312,7 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
         for (int r = 0; r < R_T - 1; ++r)
             acc[r] = ones;
 #pragma unroll 2
-        for (int it = 0; it < GL; ++it) {
+        for (int it = 0; it < n_it; ++it) {
             uint64_t h;
             bool ok;
             window(it, h, ok);
@@ -1354,12 +1355,14 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
 // only while it has one.
 template <int SW, int R_T, int ETA_T>
 __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, bool valid, uint32_t *G, bool &dead,
-                                               uint32_t lane)
+                                               uint32_t lane, uint32_t n_valid = kWave)
 {
     constexpr int L = SW < 4 ? SW : 4;
     constexpr int NSL = SW / L;
     if constexpr (R_T > 0 && SW >= 8) {
-        probe_step_wide<SW, R_T, ETA_T>(P, hx, valid, G, dead, lane);
+        // n_valid: the valid lanes are among the first n_valid
+        constexpr uint32_t WPI = kWave / (SW / 4);
+        probe_step_wide<SW, R_T, ETA_T>(P, hx, valid, G, dead, lane, (int)((n_valid + WPI - 1) / WPI));
     } else if constexpr (R_T > 0) {
 #pragma unroll 1
         for (int sl = 0; sl < NSL; ++sl) {
@@ -1537,7 +1540,7 @@ __global__ __launch_bounds__(kBlock) void k_query_termsets(Params P, const uint6
         dead = dead || __ballot(bad) != 0;
         if (!dead)
             and_terms_step<SW, R_T, ETA_T>(P, mix64(P.raw_keys ? code : canonical(code & P.kmask, P.k)), live, G,
-                                           dead, lane);
+                                           dead, lane, (uint32_t)min(pe - p, (uint64_t)kWave));
     }
     expand_answer_wave<R_T>(P, G, R, SW, dead || pe == p0, out + q * P.W, lane, lst + wv * kListCap,
                             seg + wv * kSegs);
