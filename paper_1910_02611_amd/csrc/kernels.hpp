@@ -1499,51 +1499,89 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
                             seg + wv * kSegs);
 }
 
+// Term sets per wave of k_query_termsets: one, or for rows of 32 and 64
+// words with compile-time R as many as a wave of k_query_kmers holds, so that
+// the sets whose answers come from the partition are tested together
+// (transpose_deferred, expand_planes_wave).
+template <int SW, int R_T>
+__host__ __device__ constexpr uint32_t termsets_per_wave()
+{
+    return (R_T > 0 && (SW == 32 || SW == 64)) ? 256u / SW : 1u;
+}
+
 // Sec. 3.2.1 for sets of terms given as codes (or raw keys): the answer of
 // term set q, the codes codes[offsets[q] .. offsets[q+1]), holds the sets
-// that hold every one of its terms.  One wave per term set, 64 terms per
-// step: the group masks are ANDed over the terms (stopping at the first
-// empty repetition) and expanded once.  An empty term set gets an empty
-// answer; a k-mer code >= 4^k raises kErrCode and empties its set's answer
-// (its own answer is empty).
+// that hold every one of its terms.  A wave takes termsets_per_wave sets one
+// after the other, 64 terms per step: the group masks are ANDed over the
+// terms (stopping at the first empty repetition), then each set is expanded
+// once.  An empty term set gets an empty answer; a k-mer code >= 4^k raises
+// kErrCode and empties its set's answer (its own answer is empty).
 template <int SW, int R_T, int ETA_T>
 __global__ __launch_bounds__(kBlock) void k_query_termsets(Params P, const uint64_t *offsets, uint64_t n_sets,
                                                            const uint64_t *codes, uint64_t n_codes, uint32_t *out)
 {
     constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
-    __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
+    constexpr uint32_t SPW = termsets_per_wave<SW, R_T>();
+    __shared__ uint32_t Gs[kWavesPerBlock * SPW * RMAX * SW];
     __shared__ uint16_t lst[kWavesPerBlock * kListCap];
     __shared__ uint16_t seg[kWavesPerBlock * kSegs];
 
     const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
-    if (q >= n_sets)
+    const uint64_t qbase = ((uint64_t)blockIdx.x * kWavesPerBlock + wv) * SPW;
+    if (qbase >= n_sets)
         return;
-    uint32_t *G = Gs[wv];
-    for (uint32_t i = lane; i < R * SW; i += kWave)
-        G[i] = ~0u;
-    wave_sync_lds();
-
-    uint64_t p0 = offsets[q];
-    const uint64_t pe = min(offsets[q + 1], n_codes);
-    if (p0 > pe)
-        p0 = pe;
-    bool dead = false;
-    for (uint64_t p = p0; p < pe; p += kWave) {
-        const bool live = p + lane < pe;
-        const uint64_t code = live ? codes[p + lane] : 0;
-        const bool bad = live && code > P.kmask;
-        if (bad)
-            atomicOr(P.err, kErrCode);
-        dead = dead || __ballot(bad) != 0;
-        if (!dead)
-            and_terms_step<SW, R_T, ETA_T>(P, mix64(P.raw_keys ? code : canonical(code & P.kmask, P.k)), live, G,
-                                           dead, lane, (uint32_t)min(pe - p, (uint64_t)kWave));
+    uint32_t *gw = Gs + wv * SPW * RMAX * SW;
+    uint32_t empty = 0;   // bit qi: set qbase + qi answers the empty set
+    for (uint32_t qi = 0; qi < SPW; ++qi) {
+        const uint64_t q = qbase + qi;
+        if (q >= n_sets)
+            break;
+        uint32_t *G = gw + qi * RMAX * SW;
+        for (uint32_t i = lane; i < R * SW; i += kWave)
+            G[i] = ~0u;
+        wave_sync_lds();
+        uint64_t p0 = offsets[q];
+        const uint64_t pe = min(offsets[q + 1], n_codes);
+        if (p0 > pe)
+            p0 = pe;
+        bool dead = false;
+        for (uint64_t p = p0; p < pe; p += kWave) {
+            const bool live = p + lane < pe;
+            const uint64_t code = live ? codes[p + lane] : 0;
+            const bool bad = live && code > P.kmask;
+            if (bad)
+                atomicOr(P.err, kErrCode);
+            dead = dead || __ballot(bad) != 0;
+            if (!dead)
+                and_terms_step<SW, R_T, ETA_T>(P, mix64(P.raw_keys ? code : canonical(code & P.kmask, P.k)), live,
+                                               G, dead, lane, (uint32_t)min(pe - p, (uint64_t)kWave));
+        }
+        if (dead || pe == p0)
+            empty |= 1u << qi;
     }
-    expand_answer_wave<R_T>(P, G, R, SW, dead || pe == p0, out + q * P.W, lane, lst + wv * kListCap,
-                            seg + wv * kSegs);
+    uint64_t deferred = 0;
+    for (uint32_t qi = 0; qi < SPW; ++qi) {
+        const uint64_t q = qbase + qi;
+        if (q >= n_sets)
+            break;
+        bool d = false;
+        expand_answer_wave<R_T>(P, gw + qi * RMAX * SW, R, SW, (empty >> qi) & 1u, out + q * P.W, lane,
+                                lst + wv * kListCap, seg + wv * kSegs, SPW > 1 ? &d : nullptr);
+        if (d)
+            deferred |= 1ull << qi;
+    }
+    if constexpr (SPW > 1) {
+        if (deferred) {
+            uint64_t ids = 0;
+            uint32_t nd = 0;
+            for (uint64_t d = deferred; d; d &= d - 1, ++nd)
+                ids |= (uint64_t)__builtin_ctzll(d) << (8 * nd);
+            transpose_deferred<SW, R_T>(gw, deferred, lane);
+            expand_planes_wave<SW, R_T>(P, gw, nd, ids, out + qbase * P.W, lane);
+        }
+    }
 }
 
 }  // namespace rambo_dev

@@ -232,8 +232,9 @@ void launch_query_termsets_t(const rambo *h, const uint64_t *offsets, uint64_t n
                              uint64_t n_codes, uint32_t *out, hipStream_t st)
 {
     StageScope sc(h, "k_query_termsets", st);
-    hipLaunchKernelGGL((k_query_termsets<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_sets, kWavesPerBlock)),
-                       dim3(kBlock), 0, st, h->P, offsets, n_sets, codes, n_codes, out);
+    constexpr uint64_t SPB = (uint64_t)kWavesPerBlock * termsets_per_wave<SW, R_T>();
+    hipLaunchKernelGGL((k_query_termsets<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_sets, SPB)), dim3(kBlock), 0, st,
+                       h->P, offsets, n_sets, codes, n_codes, out);
 }
 
 struct QueryTermsetsLaunch {

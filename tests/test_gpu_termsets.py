@@ -36,6 +36,7 @@ SHAPES = [
     dict(K=400, B=200, R=3, eta=2, k=31, m=20_000),      # 256-bit rows, compiled shape
     dict(K=500, B=60, R=2, eta=3, k=31, m=1 << 14),      # run-time shape
     dict(K=3000, B=2000, R=2, eta=4, k=31, m=4096),      # 2048-bit rows (the document-index shape)
+    dict(K=3000, B=600, R=3, eta=2, k=31, m=12_000),     # 1024-bit rows: eight sets per wave
 ]
 
 
@@ -46,14 +47,14 @@ def test_word_sets_match_conjunction(cfg):
     o, g = make_pair(cfg, seed=seed, flags=oracle.FLAG_RAW_KEYS)
     assert o.insert_kmers(docs.set_ids, docs.offsets, docs.keys, 8) == 0
     g.insert_kmers(dev(docs.set_ids, np.int32), dev(docs.offsets, np.int64), dev(docs.keys, np.int64))
-    q = synth.word_sets(seed + 1, docs, 3000, min_words=0, max_words=5)
+    q = synth.word_sets(seed + 1, docs, 2997, min_words=0, max_words=5)   # ragged in the sets per wave
     want = _conjunction(o, q)
     got = _gpu(g, q)
     assert np.array_equal(got, want)
     assert not got[np.diff(q.offsets) == 0].any()         # empty sets answer nothing
     # long sets: several 64-term steps, and a set made of one document's
     # whole vocabulary (the document must be in its answer)
-    lq = synth.word_sets(seed + 2, docs, 200, min_words=60, max_words=200, from_doc_frac=1.0)
+    lq = synth.word_sets(seed + 2, docs, 203, min_words=60, max_words=200, from_doc_frac=1.0)
     assert np.array_equal(_gpu(g, lq), _conjunction(o, lq))
     d = int(np.argmax(docs.lengths()))
     whole = synth.KeyBatch(docs.keys[int(docs.offsets[d]):int(docs.offsets[d + 1])].copy(),
