@@ -55,5 +55,7 @@ def test_null_handle_calls(lib):
     assert lib.rambo_create(None, None) == rambo.EINVAL
     assert lib.rambo_query_kmers(None, None, 0, None, None) == rambo.EINVAL
     assert lib.rambo_insert_seqs(None, None, None, 0, None, 0, None) == rambo.EINVAL
+    assert lib.rambo_insert_kmers(None, None, None, 0, None, 0, None) == rambo.EINVAL
+    assert lib.rambo_query_termsets(None, None, 0, None, 0, None, None) == rambo.EINVAL
     assert lib.rambo_sync_status(None, None) == rambo.EINVAL
     lib.rambo_destroy(None)
