@@ -893,13 +893,31 @@ __device__ __forceinline__ void expand_answer_wave(const Params &P, const uint32
 
 // ---------------------------------------- transposed deferred answers
 
-// A wave of k_query_kmers with rows of 32 or 64 words holds QPW = 256 / SW
+// A wave of k_query_kmers with rows of 8, 32 or 64 words holds QPW = 256 / SW
 // terms.  Those of its terms whose answers come from the partition can be
 // tested together: their group masks, transposed so that each cell of each
 // repetition holds one bit per term (QPW bits: a nibble for SW = 64, a byte
-// for SW = 32), take exactly the space of the masks themselves, so the
-// planes overwrite them in the wave's LDS region.  One phi load and R plane
-// reads per set then serve every deferred term.
+// for SW = 32, a word for SW = 8), take exactly the space of the masks
+// themselves, so the planes overwrite them in the wave's LDS region.  One phi
+// load and R plane reads per set then serve up to eight deferred terms.
+
+// The shapes with transposed planes: compile-time R and rows of 8, 32 or 64
+// words (a word, a byte or a nibble per cell).
+template <int SW, int R_T>
+__host__ __device__ constexpr bool transposed_planes()
+{
+    return R_T > 0 && (SW == 8 || SW == 32 || SW == 64);
+}
+
+// ids[s] = the index of the s-th set bit of deferred (ascending), for the
+// wave; returns the number of bits.
+__device__ __forceinline__ uint32_t deferred_ids(uint64_t deferred, uint8_t *ids, uint32_t lane)
+{
+    if (lane < 64 && ((deferred >> lane) & 1ull))
+        ids[__popcll(deferred & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+    wave_sync_lds();
+    return (uint32_t)__popcll(deferred);
+}
 
 // Bit j of the 8-bit b to bit 4 j.
 __device__ __forceinline__ uint32_t spread8_nibbles(uint32_t b)
@@ -926,7 +944,7 @@ __device__ __forceinline__ void transpose_deferred(uint32_t *gw, uint64_t deferr
     constexpr uint32_t EB = 256 / SW;
     constexpr uint32_t PAIRS = R_T * SW;
     constexpr uint32_t PPL = (PAIRS + kWave - 1) / kWave;
-    static_assert(EB == 4 || EB == 8, "nibble or byte planes");
+    static_assert(EB == 4 || EB == 8 || EB == 32, "nibble, byte or word planes");
     uint32_t pl[PPL][EB];
 #pragma unroll
     for (uint32_t p = 0; p < PPL; ++p) {
@@ -940,7 +958,10 @@ __device__ __forceinline__ void transpose_deferred(uint32_t *gw, uint64_t deferr
                 const uint32_t g = gw[(uint32_t)__builtin_ctzll(d) * PAIRS + pair];
 #pragma unroll
                 for (uint32_t t = 0; t < EB; ++t)
-                    pl[p][t] |= (EB == 4 ? spread8_nibbles(g >> (8 * t)) : spread4_bytes(g >> (4 * t))) << s;
+                    pl[p][t] |= (EB == 4 ? spread8_nibbles(g >> (8 * t))
+                                 : EB == 8 ? spread4_bytes(g >> (4 * t))
+                                           : (g >> t) & 1u)
+                                << s;
             }
         }
     }
@@ -960,60 +981,66 @@ __device__ __forceinline__ void transpose_deferred(uint32_t *gw, uint64_t deferr
 // The answers of the n deferred terms from the planes (transpose_deferred):
 // set i is in the answer of the s-th term iff bit s of its cell's element is
 // set in every repetition (the membership test of expand_by_partition).  The
-// s-th term's answer goes to out + ((ids >> 8 s) & 0xFF) W.  Lane l keeps
-// word l of each 2048-set stripe of every answer.
+// s-th term's answer goes to out + ids[s] W.  Eight answers per pass over the
+// sets; lane l keeps word l of each 2048-set stripe of each of them.
 template <int SW, int R_T>
-__device__ __forceinline__ void expand_planes_wave(const Params &P, const uint32_t *planes, uint32_t n, uint64_t ids,
+__device__ __forceinline__ void expand_planes_wave(const Params &P, const uint32_t *planes, uint32_t n, const uint8_t *ids,
                                                    uint32_t *out, uint32_t lane)
 {
     constexpr uint32_t EB = 256 / SW;
     constexpr uint32_t C = 32 * SW;
-    constexpr uint32_t ALL = EB == 4 ? 0xFu : 0xFFu;
+    constexpr uint32_t NS = EB < 8 ? EB : 8;   // answers kept per pass
     constexpr int TB = 8;
     const uint8_t *pb = reinterpret_cast<const uint8_t *>(planes);
-    for (uint32_t base = 0; base < P.K; base += 64 * 32) {
-        uint32_t mine[EB];
+    for (uint32_t s0 = 0; s0 < n; s0 += NS) {
+        const uint32_t ns = min(NS, n - s0);
+        for (uint32_t base = 0; base < P.K; base += 64 * 32) {
+            uint32_t mine[NS];
 #pragma unroll
-        for (uint32_t s = 0; s < EB; ++s)
-            mine[s] = 0u;
-        const uint32_t tmax = min(32u, (P.K - base + 63) / 64);
-        for (uint32_t t0 = 0; t0 < tmax; t0 += TB) {
-            bool valid[TB];
-            uint32_t cell[TB][R_T];
+            for (uint32_t s = 0; s < NS; ++s)
+                mine[s] = 0u;
+            const uint32_t tmax = min(32u, (P.K - base + 63) / 64);
+            for (uint32_t t0 = 0; t0 < tmax; t0 += TB) {
+                bool valid[TB];
+                uint32_t cell[TB][R_T];
 #pragma unroll
-            for (int u = 0; u < TB; ++u) {
-                const uint32_t i = base + (t0 + u) * 64 + lane;
-                valid[u] = t0 + u < tmax && i < P.K;
+                for (int u = 0; u < TB; ++u) {
+                    const uint32_t i = base + (t0 + u) * 64 + lane;
+                    valid[u] = t0 + u < tmax && i < P.K;
 #pragma unroll
-                for (int r = 0; r < R_T; ++r)
-                    cell[u][r] = valid[u] ? P.phi[(uint64_t)r * P.K + i] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < TB; ++u) {
-                if (t0 + u >= tmax)
-                    break;
-                uint32_t x = valid[u] ? ALL : 0u;
-#pragma unroll
-                for (int r = 0; r < R_T; ++r) {
-                    const uint32_t e = r * C + cell[u][r];
-                    x &= EB == 4 ? (uint32_t)(pb[e >> 1] >> ((e & 1u) * 4u)) : (uint32_t)pb[e];
+                    for (int r = 0; r < R_T; ++r)
+                        cell[u][r] = valid[u] ? P.phi[(uint64_t)r * P.K + i] : 0u;
                 }
-                const bool lo = lane == 2 * (t0 + u), hi = lane == 2 * (t0 + u) + 1;
 #pragma unroll
-                for (uint32_t s = 0; s < EB; ++s) {
-                    if (s >= n)
+                for (int u = 0; u < TB; ++u) {
+                    if (t0 + u >= tmax)
                         break;
-                    const uint64_t m = __ballot((x >> s) & 1u);
-                    mine[s] = lo ? (uint32_t)m : hi ? (uint32_t)(m >> 32) : mine[s];
+                    uint32_t x = valid[u] ? ~0u : 0u;
+#pragma unroll
+                    for (int r = 0; r < R_T; ++r) {
+                        const uint32_t e = r * C + cell[u][r];
+                        x &= EB == 4 ? (uint32_t)(pb[e >> 1] >> ((e & 1u) * 4u)) | 0xFFFFFFF0u
+                             : EB == 8 ? (uint32_t)pb[e] | 0xFFFFFF00u
+                                       : planes[e];
+                    }
+                    x >>= s0;
+                    const bool lo = lane == 2 * (t0 + u), hi = lane == 2 * (t0 + u) + 1;
+#pragma unroll
+                    for (uint32_t s = 0; s < NS; ++s) {
+                        if (s >= ns)
+                            break;
+                        const uint64_t m = __ballot((x >> s) & 1u);
+                        mine[s] = lo ? (uint32_t)m : hi ? (uint32_t)(m >> 32) : mine[s];
+                    }
                 }
             }
-        }
-        const uint32_t w = base / 32 + lane;
-        if (w < P.W) {
+            const uint32_t w = base / 32 + lane;
+            if (w < P.W) {
 #pragma unroll
-            for (uint32_t s = 0; s < EB; ++s)
-                if (s < n)
-                    out[((ids >> (8 * s)) & 0xFFu) * P.W + w] = mine[s];
+                for (uint32_t s = 0; s < NS; ++s)
+                    if (s < ns)
+                        out[(uint64_t)ids[s0 + s] * P.W + w] = mine[s];
+            }
         }
     }
 }
@@ -1103,16 +1130,14 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
             if (d)
                 deferred |= 1ull << qi;
         }
-        if constexpr (R_T > 0 && (SW == 32 || SW == 64)) {
-            // all the wave's deferred terms at once, from transposed planes
+        if constexpr (transposed_planes<SW, R_T>()) {
+            // all the wave's deferred terms together, from transposed planes
             if (deferred) {
-                uint64_t ids = 0;
-                uint32_t nd = 0;
-                for (uint64_t d = deferred; d; d &= d - 1, ++nd)
-                    ids |= (uint64_t)__builtin_ctzll(d) << (8 * nd);
+                __shared__ uint8_t dids[kWavesPerBlock][QPW];
+                const uint32_t nd = deferred_ids(deferred, dids[wv], lane);
                 uint32_t *gw = gs + wv * QPW * RMAX * SW;
                 transpose_deferred<SW, R_T>(gw, deferred, lane);
-                expand_planes_wave<SW, R_T>(P, gw, nd, ids, out + qbase * P.W, lane);
+                expand_planes_wave<SW, R_T>(P, gw, nd, dids[wv], out + qbase * P.W, lane);
             }
             return;
         }
@@ -1506,7 +1531,7 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
 template <int SW, int R_T>
 __host__ __device__ constexpr uint32_t termsets_per_wave()
 {
-    return (R_T > 0 && (SW == 32 || SW == 64)) ? 256u / SW : 1u;
+    return transposed_planes<SW, R_T>() ? 256u / SW : 1u;
 }
 
 // Sec. 3.2.1 for sets of terms given as codes (or raw keys): the answer of
@@ -1574,12 +1599,10 @@ __global__ __launch_bounds__(kBlock) void k_query_termsets(Params P, const uint6
     }
     if constexpr (SPW > 1) {
         if (deferred) {
-            uint64_t ids = 0;
-            uint32_t nd = 0;
-            for (uint64_t d = deferred; d; d &= d - 1, ++nd)
-                ids |= (uint64_t)__builtin_ctzll(d) << (8 * nd);
+            __shared__ uint8_t dids[kWavesPerBlock][SPW];
+            const uint32_t nd = deferred_ids(deferred, dids[wv], lane);
             transpose_deferred<SW, R_T>(gw, deferred, lane);
-            expand_planes_wave<SW, R_T>(P, gw, nd, ids, out + qbase * P.W, lane);
+            expand_planes_wave<SW, R_T>(P, gw, nd, dids[wv], out + qbase * P.W, lane);
         }
     }
 }
