@@ -913,7 +913,7 @@ __host__ __device__ constexpr bool transposed_planes()
 // wave; returns the number of bits.
 __device__ __forceinline__ uint32_t deferred_ids(uint64_t deferred, uint8_t *ids, uint32_t lane)
 {
-    if (lane < 64 && ((deferred >> lane) & 1ull))
+    if ((deferred >> lane) & 1ull)
         ids[__popcll(deferred & ((1ull << lane) - 1ull))] = (uint8_t)lane;
     wave_sync_lds();
     return (uint32_t)__popcll(deferred);
@@ -1015,6 +1015,8 @@ __device__ __forceinline__ void expand_planes_wave(const Params &P, const uint32
                 for (int u = 0; u < TB; ++u) {
                     if (t0 + u >= tmax)
                         break;
+                    // bits above an element's own stay set: only bits s0 ..
+                    // s0 + ns - 1 are tested
                     uint32_t x = valid[u] ? ~0u : 0u;
 #pragma unroll
                     for (int r = 0; r < R_T; ++r) {
