@@ -119,7 +119,8 @@ def measured_traffic(names: dict, path: str = TRAFFIC_JSON) -> dict:
     return {stage: t["kernels"][k]["bytes"] for stage, k in names.items() if k in t["kernels"]}
 
 
-def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh=True, traffic_json=TRAFFIC_JSON):
+def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh=True, traffic_json=TRAFFIC_JSON,
+                     term_sets=0, set_terms=0):
     """Roofline entry of each timed kernel: algorithmic work per launch over
     its measured duration.  fresh: the insert went into an all-zero index,
     so stage C writes the index without reading it.  traffic_json: the
@@ -140,13 +141,18 @@ def kernel_rooflines(kernels, n_ins, n_queries, R, eta, S, W, index_bytes, fresh
         "k_insert_kmers": ("hbm", n_ins * RE * 2 * SECTOR, "GB/s", "one 64-B sector read-modify-write per target"),
         "k_query_kmers": ("hbm", n_queries * (RE * max(SECTOR, S // 8) + 4 * W + 8), "GB/s",
                           "R*eta row sectors + K-bit answer + code per query"),
+        "k_query_termsets": ("hbm", set_terms * (RE * max(SECTOR, S // 8) + 8) + term_sets * (4 * W + 8), "GB/s",
+                             "R*eta row sectors + code per term (no early exit subtracted), K-bit answer + "
+                             "offset per set"),
     }
     launch_bytes = measured_traffic({"k_bin_windows": "k_bin_windows_hold<%d, %d>" % (R, eta),
                                      "k_bin_codes": "k_bin_codes_hold<%d, %d>" % (R, eta),
                                      "k_insert_kmers": "k_insert_kmers",
                                      "k_bin_regions": "k_bin_regions", "k_apply_regions": "k_apply_regions",
                                      "k_insert_seqs": "k_insert_seqs<%d, %d>" % (R, eta),
-                                     "k_query_kmers": "k_query_kmers<%d, %d, %d>" % (SW, R, eta)}, traffic_json)
+                                     "k_query_kmers": "k_query_kmers<%d, %d, %d>" % (SW, R, eta),
+                                     "k_query_termsets": "k_query_termsets<%d, %d, %d>" % (SW, R, eta)},
+                                    traffic_json)
     out = []
     for name, ms in kernels.items():
         if name not in work:
@@ -398,7 +404,7 @@ def documents(n_queries: int, steps: int = 3):
     n_keys, RE, S, W = int(docs.keys.size), cfg["R"] * cfg["eta"], g.row_bits, g.W
     # every timed insert follows a clear: stage C writes without reading back
     roofs = kernel_rooflines(kernels, n_keys, q.size, cfg["R"], cfg["eta"], S, W, g.index_bytes, fresh=True,
-                             traffic_json=TRAFFIC_DOCS_JSON)
+                             traffic_json=TRAFFIC_DOCS_JSON, term_sets=ws.n, set_terms=int(ws.keys.size))
     ins_ms = kernels.get("k_insert_kmers")
     if ins_ms:
         # the direct insert (chosen for small batches): the 100 MB index sits
