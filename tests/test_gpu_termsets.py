@@ -66,10 +66,14 @@ def test_word_sets_match_conjunction(cfg):
     g.close()
 
 
-def test_kmer_sets_equal_read_answers():
-    # the term set of a read's valid k-mer codes answers as the read does
-    cfg = dict(K=200, B=40, R=4, eta=2, k=21, m=1 << 15)
-    sets = synth.genome_sets(51, K=200, n_ancestors=6, ancestor_len=2000)
+@pytest.mark.parametrize("cfg,n_anc", [(dict(K=200, B=40, R=4, eta=2, k=21, m=1 << 15), 6),
+                                       (dict(K=300, B=200, R=3, eta=2, k=21, m=1 << 15), 6),   # 32 sets per wave
+                                       (dict(K=700, B=600, R=3, eta=2, k=21, m=1 << 14), 2)],  # 8 per wave, busy
+                         ids=["B40", "B200", "B600"])
+def test_kmer_sets_equal_read_answers(cfg, n_anc):
+    # the term set of a read's valid k-mer codes answers as the read does;
+    # with two ancestors many answers hold hundreds of sets
+    sets = synth.genome_sets(51, K=cfg["K"], n_ancestors=n_anc, ancestor_len=2000)
     o, g = make_pair(cfg, seed=51)
     o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
     g.insert_seqs(dev(sets.set_ids, np.int32), dev(sets.offsets, np.int64), dev(sets.chars, np.uint8))
