@@ -40,7 +40,15 @@
  *  - Array arguments are DEVICE pointers owned by the caller; they must stay
  *    valid until the work on `stream` has finished.  Sizes are host values.
  *  - Calls are asynchronous and ordered on `stream` (0 = the null stream).
- *    One handle serves one host thread at a time.
+ *    One handle serves one host thread at a time.  The handle's own device
+ *    scratch (the partitioned insert's slabs, the per-read state of batched
+ *    read queries) is shared by its calls whatever their stream: a call that
+ *    uses it on a stream other than the previous user's first waits for
+ *    that user's work, so calls on different streams never share it at
+ *    once.  The index itself is the caller's to order: an insert and a query
+ *    on two streams with no dependency between them may see each other's
+ *    bits or not.  Scratch that a captured graph may still replay on is
+ *    kept until rambo_destroy when a later call grows it.
  *  - Return 0 on success or a negative RAMBO_E* code.  Errors found on the
  *    host return at once and enqueue nothing.  Errors found on the device
  *    (a set id >= K, a code >= 4^k) skip the item (insert) or give it an
@@ -199,14 +207,20 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
  * sorts the targets by address into regions of the index and ORs each region
  * in on-chip memory, which avoids the device's atomic-rate limit on bulk
  * inserts; AUTO picks by the number of targets.  scratch_bytes caps the
- * device scratch of the partitioned path (0 = half of the free memory, at
- * most 128 GiB); larger inserts are processed in batches, each of which
- * reads and writes the index regions it touches.  The scratch is sized for
+ * device scratch of the partitioned path (0 = 85% of the free memory left
+ * after keeping 8 GiB free, at most 192 GiB; the scratch takes about 8.5
+ * bytes per bit target of a batch); larger inserts are processed in
+ * batches, each of which reads and writes the index regions it touches.  The scratch is sized for
  * the first partitioned insert, kept by the handle, and released by the
  * next call of this function that changes scratch_bytes. */
 #define RAMBO_INSERT_AUTO 0
 #define RAMBO_INSERT_DIRECT 1
 #define RAMBO_INSERT_PARTITIONED 2
+/* PARTITIONED, with sequence input binned by the window-walker kernel (a
+ * wave walks 64 consecutive bytes per step, whatever the sequence) instead
+ * of the piece kernel (a wave walks pieces of one sequence, a lane a run of
+ * windows); the same index bits, for comparing the two. */
+#define RAMBO_INSERT_PARTITIONED_WALKER 3
 int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
 
 /* How rambo_query_seqs and rambo_query_seqs_ids schedule a batch of reads
@@ -232,10 +246,11 @@ int rambo_set_query_policy(rambo_t *h, int mode, uint32_t chunk_bytes, uint32_t 
  * events and reports, for the kernels launched since the last call to it,
  * the total milliseconds per kernel name: names receives up to max_stages
  * NUL-terminated names of at most 47 characters in 48-byte slots, ms their
- * times; the return value is the number of distinct kernels (or a negative
- * error). */
+ * times and calls (host memory, nullable) the number of launches behind
+ * each total; the return value is the number of distinct kernels (or a
+ * negative error). */
 int rambo_set_timing(rambo_t *h, int enable);
-int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max_stages);
+int rambo_get_stage_times(rambo_t *h, char *names, float *ms, uint32_t *calls, int max_stages);
 
 /* Folding over (Sec. 5.2 and the appendix's parallel-indexing experiment):
  * B -> B/2 by OR-ing the filter of cell b + B/2 into the filter of cell b
@@ -288,7 +303,7 @@ int rambo_get_partition(rambo_t *h, uint32_t *out);
 
 /* Number of set bits of every Bloom filter: out[r*B + b] (R*B uint64,
  * device memory) = ones of cell b of repetition r, the n_b of the filter's
- * fill (Sec. 2.1), as the false-positive expression of Lemma 4.1 uses it.
+ * fill (Sec. 2), as the false-positive expression of Lemma 4.1 uses it.
  * Asynchronous on `stream`. */
 int rambo_fill_counts(rambo_t *h, uint64_t *out, hipStream_t stream);
 

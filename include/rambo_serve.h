@@ -94,6 +94,14 @@ int rambo_serve_wait(rambo_server_t *s, int64_t id, uint32_t *masks, uint32_t *n
 int rambo_serve_replay(rambo_server_t *s, uint64_t n_req, const uint64_t *req_reads, const uint64_t *read_offsets,
                        const uint8_t *chars, const double *arrival_s, double *latency_ms, uint64_t *checksum);
 
+/* Test hook of the worker's error path: the next n_batches batches fail on
+ * the host before they are launched, exactly as a failed copy or launch
+ * would: every request in them is answered with RAMBO_EHIP (zero masks)
+ * instead of leaving its waiter blocked, and the server goes on with later
+ * batches.  A batch whose completion event reports an error is handled the
+ * same way. */
+int rambo_serve_inject_failures(rambo_server_t *s, uint32_t n_batches);
+
 /* Counters since creation: batches run, requests and reads answered, and the
  * number of slots. */
 int rambo_serve_stats(rambo_server_t *s, uint64_t *batches, uint64_t *requests, uint64_t *reads, uint32_t *slots);

@@ -632,7 +632,7 @@ int orc_scan_rows(const orc_index *h, const uint32_t *set_ids, const uint64_t *o
     /* which positions are asked for: one bit per (r, p), behind a small
      * cache-resident bitmap of the keys' low bits that turns most misses
      * away before the large one is touched */
-    const uint64_t small_bits = 1ULL << 26;
+    const uint64_t small_bits = 1ULL << 30;
     uint64_t *want = NULL, *want_small = NULL;
     if (n_keys > 0) {
         want = calloc(((uint64_t)h->R * h->m + 63) / 64, sizeof(uint64_t));

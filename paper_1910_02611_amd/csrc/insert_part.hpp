@@ -39,19 +39,26 @@ constexpr uint32_t kTileA = 8192;               // targets per round in stage A
 constexpr uint32_t kTileB = 8192;               // slab entries per tile in stage B
 constexpr uint32_t kMaxTargetsPerWindow = kTileA / kBlockP;   // R*eta the partitioned path supports
 
+// Slab A holds na * nwg chunks of capA entries: chunk (b, g) at
+// slabA + (b * nwg + g) * capA, filled by producer g with entries of coarse
+// bucket b; fillA[b * nwg + g] counts them.  The stage-A kernels that
+// reserve runs with global atomics use one chunk per bucket (nwg = 1).
 struct BinGeom {
     uint32_t rb;          // log2 of the bits in one region
     uint32_t fb;          // log2 of the regions in one coarse bucket
     uint32_t na;          // coarse buckets
     uint32_t nf;          // regions per coarse bucket (1 << fb)
-    uint64_t capA;        // slab entries per coarse bucket
+    uint32_t nwg;         // chunks per coarse bucket (stage-A producers)
+    uint64_t capA;        // slab entries per chunk
     uint64_t capB;        // slab entries per region
-    uint32_t *slabA;      // na * capA
-    uint32_t *fillA;      // na
-    uint32_t *slabB;      // n_regions * capB
-    uint32_t *fillB;      // na * nf
+    uint32_t *slabA;      // na * nwg * capA
+    uint32_t *fillA;      // na * nwg
+    uint32_t *slabB;      // capB per region of one group of coarse buckets (at most
+    uint32_t *fillB;      //   ncb * nf regions, fewer where the index ends)
     uint32_t *dirty;      // na * nf: a fallback atomic wrote into this region
     uint64_t total_words; // words of the index (all repetitions)
+    uint32_t c0;          // stages B and C take the coarse buckets c0 .. c0 + ncb - 1;
+    uint32_t ncb;         //   slab B and fillB hold just their regions
 };
 
 __host__ __device__ constexpr size_t lds_bytes_stage_a(uint32_t na) { return kTileA * 12ull + na * 12ull + 64; }
@@ -390,10 +397,12 @@ void k_bin_codes_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64
                                      });
 }
 
-// Stage B: block = (coarse bucket, tile of its slab).  The tile's entries
-// stay in registers; the counting atomic gives each its rank inside its
-// region, so after the scan it goes straight to its sorted LDS slot (4 bytes
-// of LDS per entry).
+// Stage B: block = (coarse bucket, tile of kTileB slots of its nwg chunks,
+// which lie one after the other).  A slot holds an entry when it is below
+// its chunk's fill count (and is not a sentinel).  The tile's entries stay
+// in registers; the counting atomic gives each its rank inside its region,
+// so after the scan it goes straight to its sorted LDS slot (4 bytes of LDS
+// per entry).
 __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
 {
     extern __shared__ uint32_t lds[];
@@ -403,14 +412,25 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     uint32_t *gbase = lbase + G.nf;     // nf first slab entries of the runs
     uint32_t *wsum = gbase + G.nf;      // kWavesP
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    const uint32_t c = blockIdx.x / tiles_per_bucket;
+    const uint32_t c = G.c0 + blockIdx.x / tiles_per_bucket;
     const uint32_t tile = blockIdx.x % tiles_per_bucket;
-    const uint64_t n_c = min((uint64_t)G.fillA[c], G.capA);
+    const uint64_t span = (uint64_t)G.nwg * G.capA;   // slots of bucket c
     const uint64_t t0 = (uint64_t)tile * kTileB;
-    if (t0 >= n_c)
+    if (t0 >= span)
         return;
-    const uint32_t n = (uint32_t)min((uint64_t)kTileB, n_c - t0);
-    const uint32_t *src = G.slabA + (uint64_t)c * G.capA + t0;   // 16-byte aligned: capA, t0 are multiples of 4
+    const uint32_t n = (uint32_t)min((uint64_t)kTileB, span - t0);
+    const uint32_t *cfill = G.fillA + (uint64_t)c * G.nwg;
+    {
+        // leave at once when no chunk holds an entry in [t0, t0 + n)
+        const uint64_t g0 = t0 / G.capA, g1 = (t0 + n - 1) / G.capA;
+        bool any = false;
+        for (uint64_t g = g0; g <= g1 && !any; ++g)
+            any = g * G.capA + min((uint64_t)cfill[g], G.capA) > t0;
+        if (!any)
+            return;
+    }
+    const uint32_t *src = G.slabA + (uint64_t)c * span + t0;   // 16-byte aligned: capA, t0 are multiples of 4
+    const double inv_cap = 1.0 / (double)G.capA;
     for (uint32_t b = threadIdx.x; b < G.nf; b += kBlockP)
         cnt[b] = 0;
     // unconditional loads (clamped to the last vector) so none waits for
@@ -428,16 +448,29 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     for (int i = 0; i < kV; ++i) {
         const uint32_t j = (uint32_t)(i * kBlockP) + threadIdx.x;
         const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+        // the vector's chunk (its 4 slots share one: capA is a multiple of 4)
+        // and how many of its slots hold entries
+        const uint64_t p = t0 + 4ull * j;
+        uint64_t g = 0;
+        if (G.nwg > 1) {
+            g = (uint64_t)((double)p * inv_cap);
+            if (g * G.capA > p)
+                --g;
+            else if ((g + 1) * G.capA <= p)
+                ++g;
+        }
+        const uint64_t gs = g * G.capA;
+        const uint64_t lim = j * 4 < n ? min((uint64_t)cfill[min(g, (uint64_t)G.nwg - 1)], G.capA) : 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const bool ok = j * 4 + q < n && e[q] != kSentinel;
+            const bool ok = j * 4 + q < n && p + q - gs < lim && e[q] != kSentinel;
             rk[i * 4 + q] = ok ? atomicAdd(&cnt[e[q] >> G.rb], 1u) : kNone;
         }
     }
     __syncthreads();
     const uint32_t total = block_exclusive_scan(cnt, lbase, G.nf, wsum);
-    uint32_t *fill = G.fillB + (uint64_t)c * G.nf;
-    uint32_t *slab = G.slabB + (uint64_t)c * G.nf * G.capB;
+    uint32_t *fill = G.fillB + (uint64_t)(c - G.c0) * G.nf;
+    uint32_t *slab = G.slabB + (uint64_t)(c - G.c0) * G.nf * G.capB;
     RunReservation res;
     res.issue(cnt, G.nf, fill);
 #pragma unroll
@@ -463,20 +496,22 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     }
 }
 
-// Stage C: block = region.  Regions no target reached are left untouched.
-// With `fresh` the index is known to have been all zero before this batch
-// (nothing inserted since it was created or cleared): a region that no
-// fallback atomic touched starts from zero in LDS instead of being read.
+// Stage C: block = region of the group (global region G.c0 * nf + block).
+// Regions no target reached are left untouched.  With `fresh` the index is
+// known to have been all zero before this batch (nothing inserted since it
+// was created or cleared): a region that no fallback atomic touched starts
+// from zero in LDS instead of being read.
 __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, uint32_t fresh)
 {
     extern __shared__ uint32_t lds[];   // 2^rb / 32 words
-    const uint64_t g = blockIdx.x;
-    const uint64_t n = min((uint64_t)G.fillB[g], G.capB);
-    if (n == 0)
-        return;
+    const uint64_t gl = blockIdx.x;                       // in the group's slab B
+    const uint64_t g = (uint64_t)G.c0 * G.nf + gl;        // in the index
     const uint32_t rwords = 1u << (G.rb - 5);
     const uint64_t w0 = g * rwords;
     if (w0 >= G.total_words)
+        return;
+    const uint64_t n = min((uint64_t)G.fillB[gl], G.capB);
+    if (n == 0)
         return;
     const uint32_t nw = (uint32_t)min((uint64_t)rwords, G.total_words - w0);   // a multiple of 4
     u32x4 *l4 = reinterpret_cast<u32x4 *>(lds);
@@ -484,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, u
     const uint32_t nw4 = nw / 4;
     constexpr int kRegion4PerThread = (1u << (kRegionLog2Max - 5)) / 4 / kBlock;
     constexpr int kBatch = 8;
-    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(G.slabB + g * G.capB);   // capB is a multiple of 4
+    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(G.slabB + gl * G.capB);   // capB is a multiple of 4
     const uint64_t n4 = (n + 3) / 4;
     // The region and the first batch of its targets are loaded together:
     // every load is unconditional (clamped to an in-bounds vector) so all of
@@ -542,6 +577,15 @@ __global__ __launch_bounds__(kBlock) void k_zero_u32(uint32_t *p, uint64_t n)
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
         p[i] = 0;
+}
+
+// Fill n words with v: a kernel, so that a call recorded into a graph holds
+// no memset node.
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        p[i] = v;
 }
 
 }  // namespace rambo_dev

@@ -14,7 +14,7 @@
 // the sticky overflow bit is raised; id_offsets is always complete.
 //
 // k_fill_counts counts the set bits of each cell (r, b): the n_b of the
-// fill 1 - (1 - 1/m)^(eta n) of Sec. 2.1, per BFU.
+// fill 1 - (1 - 1/m)^(eta n) of Sec. 2, per BFU.
 #pragma once
 
 #include "query_queue.hpp"

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "insert_part.hpp"
+#include "insert_pieces.hpp"
 #include "query_ids.hpp"
 #include "query_queue.hpp"
 #include "kernels.hpp"
@@ -41,6 +42,10 @@ struct rambo {
     BinGeom bin{};
     uint64_t bin_targets = 0;        // targets per batch the scratch holds
     void *bin_mem = nullptr;
+    uint32_t piece_nwg = 0;          // workgroups of the piece kernel (stage A for sequences)
+    uint64_t piece_capA = 0;         // entries of each of its chunks the scratch holds
+    uint32_t *piece_mem = nullptr;   // first piece of each sequence (n_seqs + 1 words)
+    uint64_t piece_cap = 0;
     // batched sequence queries
     int query_mode = RAMBO_QUERY_AUTO;
     uint32_t query_chunk = 512;        // bytes per work item
@@ -52,6 +57,13 @@ struct rambo {
     bool recorded_insert = false;      // an insert was recorded into a graph: index_zero is never trusted again
     ReadQueue rq{};
     uint64_t *scan_part = nullptr;     // tile totals of the ID-list scan (in rq_mem)
+    bool rq_recorded = false;          // a captured graph holds rq_mem: retire it instead of freeing it
+    std::vector<void *> retired;       // scratch buffers captured graphs may still use; freed by rambo_destroy
+    // ordering of the handle's scratch across streams: the last call that
+    // used it recorded scratch_ev on scratch_stream
+    hipEvent_t scratch_ev = nullptr;
+    hipStream_t scratch_stream = nullptr;
+    bool scratch_pending = false;
     // kernel timing (rambo_set_timing)
     bool timing = false;
     mutable std::vector<hipEvent_t> ev_pool;
@@ -83,6 +95,32 @@ void note_insert(rambo *h, hipStream_t stream)
     if (capturing(stream))
         h->recorded_insert = true;
 }
+
+// The handle's scratch (insert slabs, read-queue state) is shared by every
+// call, whatever its stream: a call on a stream other than the previous
+// scratch user's first waits for that user's work (an event recorded at the
+// end of each such call), so calls on different streams never overlap in the
+// scratch.  Work recorded into a graph is ordered by the graph instead.
+struct ScratchUse {
+    rambo *h;
+    hipStream_t st;
+    ScratchUse(rambo *h_, hipStream_t st_) : h(h_), st(st_)
+    {
+        if (h->scratch_pending && st != h->scratch_stream && h->scratch_ev && !capturing(st))
+            (void)hipStreamWaitEvent(st, h->scratch_ev, 0);
+    }
+    ~ScratchUse()
+    {
+        if (!h->scratch_ev || capturing(st))
+            return;
+        if (hipEventRecord(h->scratch_ev, st) == hipSuccess) {
+            h->scratch_stream = st;
+            h->scratch_pending = true;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+};
 
 struct StageScope {
     const rambo *h;
@@ -467,9 +505,13 @@ int ensure_read_queue(rambo *h, uint64_t n_reads)
         const int rc = hip_check(h, hipDeviceSynchronize(), "read queue resize");
         if (rc)
             return rc;
-        (void)hipFree(h->rq_mem);
+        if (h->rq_recorded)
+            h->retired.push_back(h->rq_mem);   // a captured graph may still replay on it
+        else
+            (void)hipFree(h->rq_mem);
         h->rq_mem = nullptr;
         h->rq_cap = 0;
+        h->rq_recorded = false;
     }
     const uint64_t qb = div_up(read_queue_bytes(h, cap), 256) * 256;
     if (hipMalloc(&h->rq_mem, qb + 8 * (div_up(cap, kScanTile) + 1)) != hipSuccess) {
@@ -530,6 +572,13 @@ constexpr uint32_t kStageAWindowsPerWave = 2048;
 // Regions of 2^rb bits that hold index bits (the last may be partial).
 uint64_t n_regions(const BinGeom &G) { return div_up(G.total_words * 32, 1ull << G.rb); }
 
+// Regions of the group of coarse buckets that starts at c0.
+uint64_t group_regions(const BinGeom &G, uint32_t c0, uint32_t ncb)
+{
+    const uint64_t first = (uint64_t)c0 * G.nf, all = n_regions(G);
+    return first >= all ? 0 : std::min((uint64_t)ncb * G.nf, all - first);
+}
+
 void plan_partition(rambo *h)
 {
     const uint64_t total_words = (uint64_t)h->cfg.R * h->words_per_rep;
@@ -543,28 +592,100 @@ void plan_partition(rambo *h)
     G.nf = 1u << G.fb;
     const uint64_t na = div_up(total_bits, 1ull << (G.rb + G.fb));
     G.na = (uint32_t)na;
+    G.nwg = 1;
+    G.c0 = 0;
+    G.ncb = G.na;
     G.total_words = total_words;
     h->part_ok = na <= kMaxCoarse && (uint64_t)h->cfg.R * h->cfg.eta <= kMaxTargetsPerWindow &&
                  lds_bytes_stage_a(G.na) <= kMaxLds && lds_bytes_stage_b(G.nf) <= kMaxLds;
 }
 
+// Stage A over sequence pieces for the compiled shapes: the kernel, its LDS
+// bytes and how many of its workgroups fit a CU (at most two); it runs as
+// that many persistent workgroups per CU.
+using BinPiecesFn = void (*)(Params, BinGeom, PieceArgs);
+struct StageAPieces {
+    BinPiecesFn fn = nullptr;
+    size_t lds = 0;
+    uint32_t per_cu = 0;
+};
+
+template <int R_T, int ETA_T, int ST>
+StageAPieces make_pieces(uint32_t na, bool fast)
+{
+    StageAPieces a;
+    a.lds = lds_bytes_pieces<R_T, ETA_T, ST>(na);
+    // one persistent workgroup per CU: measured faster than two on the
+    // 8 GiB index (fewer chunks written at once)
+    a.per_cu = a.lds <= kMaxLds ? 1u : 0u;
+    a.lds = std::max<size_t>(a.lds, kMaxLds / 2 + 1024);
+    if (a.per_cu)
+        a.fn = fast ? k_bin_pieces<R_T, ETA_T, ST, true> : k_bin_pieces<R_T, ETA_T, ST, false>;
+    return a;
+}
+
+StageAPieces stage_a_pieces(const rambo *h)
+{
+    const BinGeom &G = h->bin;
+    const uint32_t shA = G.rb + G.fb;
+    const uint64_t rep_bits = h->words_per_rep * 32;
+    // 32-bit positions and buckets: m a power of two <= 2^32, repetitions
+    // made of whole coarse buckets, and a row no wider than a coarse bucket
+    const bool fast = h->P.m_log2 > 0 && h->P.m_log2 <= 32 && shA <= 31 && rep_bits % (1ull << shA) == 0 &&
+                      h->P.S_log2 <= shA;
+    if (h->cfg.eta == 2 && G.na <= kMaxCoarse) {
+        switch (h->cfg.R) {
+        case 3: return make_pieces<3, 2, 2>(G.na, fast);
+        case 4: return make_pieces<4, 2, 2>(G.na, fast);
+        case 5: return make_pieces<5, 2, 2>(G.na, fast);
+        case 6: return make_pieces<6, 2, 1>(G.na, fast);
+        default: break;
+        }
+    }
+    return StageAPieces{};
+}
+
 // Slab capacities for T targets per batch spread evenly over the index (the
 // index may hold fewer bits than na coarse buckets of nf regions), with
 // margins for the statistical spread; skewed inputs overflow into the
-// fallback atomics.
-uint64_t scratch_bytes_for(const BinGeom &G, uint64_t T, uint64_t &capA, uint64_t &capB)
+// fallback atomics.  capA1: one chunk per coarse bucket (the stage-A kernels
+// that reserve runs with atomics); capAn: each of nwg producers' chunk of a
+// bucket (the piece kernel); capB: per region.  Stages B and C run over
+// groups of ncb coarse buckets, so slab B holds only one group's regions.
+struct ScratchPlan {
+    uint64_t capA1 = 0, capAn = 0, capB = 0, bytes = 0;
+};
+
+uint64_t chunk_cap(const BinGeom &G, uint64_t T, uint32_t nwg)
+{
+    const double coarse = (double)G.total_words * 32.0 / (double)(1ull << (G.rb + G.fb));
+    return div_up((uint64_t)((double)T / (coarse < 1.0 ? 1.0 : coarse) / nwg * 1.04) + 64, 16) * 16;
+}
+
+ScratchPlan scratch_plan(const BinGeom &G, uint64_t T, uint32_t nwg, uint32_t ncb)
 {
     const double bits = (double)G.total_words * 32.0;
     const double coarse = bits / (double)(1ull << (G.rb + G.fb)), regions = bits / (double)(1ull << G.rb);
-    capA = (uint64_t)((double)T / (coarse < 1.0 ? 1.0 : coarse) * 1.04) + 4096;
-    capB = (uint64_t)((double)T / (regions < 1.0 ? 1.0 : regions) * 1.08) + 512;
-    capA = div_up(capA, 4) * 4;
-    capB = div_up(capB, 4) * 4;
-    return 4 * ((uint64_t)G.na * capA + n_regions(G) * capB + G.na + 2ull * G.na * G.nf);
+    ScratchPlan s;
+    s.capA1 = div_up((uint64_t)((double)T / (coarse < 1.0 ? 1.0 : coarse) * 1.04) + 4096, 4) * 4;
+    s.capAn = nwg ? chunk_cap(G, T, nwg) : 0;
+    s.capB = div_up((uint64_t)((double)T / (regions < 1.0 ? 1.0 : regions) * 1.08) + 512, 4) * 4;
+    const uint64_t slabA = std::max((uint64_t)G.na * s.capA1, (uint64_t)G.na * nwg * s.capAn);
+    const uint64_t gr = group_regions(G, 0, ncb);
+    s.bytes = 4 * (slabA + gr * s.capB + gr + (uint64_t)G.na * G.nf +
+                   (uint64_t)G.na * std::max(nwg, 1u));
+    return s;
 }
 
 // Allocate the scratch of the partitioned path once: as many targets per
-// batch as fit the limit (default: half of free memory, at most 128 GiB).
+// batch as fit the limit.  Each batch's stage C rewrites every region it
+// touches, so an insert larger than one batch sweeps the index once per
+// batch: the default limit is most of the free memory (85% of what is left
+// after keeping kScratchKeepFree free for the caller's query buffers), at
+// most kScratchMax.
+constexpr uint64_t kScratchKeepFree = 8ull << 30;
+constexpr uint64_t kScratchMax = 192ull << 30;
+
 int ensure_scratch(rambo *h, uint64_t want_targets)
 {
     if (h->bin_mem)
@@ -574,22 +695,48 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
             return fail(h, RAMBO_EHIP, "hipMemGetInfo failed");
-        limit = free_b / 2;
-        if (limit > (128ull << 30))
-            limit = 128ull << 30;
+        limit = free_b > 2 * kScratchKeepFree ? (free_b - kScratchKeepFree) / 20 * 17 : free_b / 2;
+        if (limit > kScratchMax)
+            limit = kScratchMax;
     }
-    uint64_t capA = 0, capB = 0;
-    uint64_t T = want_targets > (1ull << 24) ? want_targets : (1ull << 24);
-    if (T > (1ull << 35))
-        T = 1ull << 35;
-    // slab positions and fill counters are 32-bit
-    while (T > 4096 && (scratch_bytes_for(h->bin, T, capA, capB) > limit || capA >= (1ull << 31) ||
-                        capB >= (1ull << 31)))
-        T = T / 4 * 3;
-    const uint64_t bytes = scratch_bytes_for(h->bin, T, capA, capB);
-    if (bytes > limit)
+    const StageAPieces AP = stage_a_pieces(h);
+    h->piece_nwg = AP.fn ? AP.per_cu * (uint32_t)h->num_cus : 0u;
+    const uint64_t want = std::max<uint64_t>(want_targets, 1ull << 24);
+    const uint64_t t_max = std::min<uint64_t>(want, 1ull << 35);
+    // For 1, 2, 4, 8 groups of coarse buckets in stages B and C: the most
+    // targets per batch that fit the limit (slab positions and fill
+    // counters are 32-bit).  Take the fewest groups that need the fewest
+    // batches: every batch rewrites the index regions it touches once.
+    const BinGeom &G0 = h->bin;
+    uint64_t best_T = 0, best_batches = ~0ull;
+    uint32_t best_ncb = G0.na;
+    for (uint32_t ng = 1; ng <= 8 && ng <= G0.na; ng *= 2) {
+        const uint32_t ncb = (G0.na + ng - 1) / ng;
+        auto fits = [&](uint64_t T) {
+            const ScratchPlan p = scratch_plan(G0, T, h->piece_nwg, ncb);
+            return p.bytes <= limit && p.capA1 < (1ull << 31) && p.capB < (1ull << 31);
+        };
+        if (!fits(4096))
+            continue;
+        uint64_t lo = 4096, hi = t_max;   // fits(lo); find the largest T that fits
+        if (fits(hi))
+            lo = hi;
+        while (hi - lo > 4096) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            (fits(mid) ? lo : hi) = mid;
+        }
+        const uint64_t batches = div_up(want, lo);
+        if (batches < best_batches) {
+            best_batches = batches;
+            best_T = lo;
+            best_ncb = ncb;
+        }
+    }
+    if (best_T == 0)
         return fail(h, RAMBO_ENOMEM, "insert scratch limit too small");
-    if (hipMalloc(&h->bin_mem, bytes) != hipSuccess) {
+    const uint64_t T = best_T;
+    const ScratchPlan sp = scratch_plan(G0, T, h->piece_nwg, best_ncb);
+    if (hipMalloc(&h->bin_mem, sp.bytes) != hipSuccess) {
         (void)hipGetLastError();
         h->bin_mem = nullptr;
         return fail(h, RAMBO_ENOMEM, "insert scratch allocation failed");
@@ -601,25 +748,61 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     const StageACodes AC = stage_a_codes(h);
     if (hipFuncSetAttribute(binA, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds) != hipSuccess ||
         hipFuncSetAttribute(AC.fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)AC.lds) != hipSuccess ||
+        (AP.fn && hipFuncSetAttribute(reinterpret_cast<const void *>(AP.fn),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)AP.lds) != hipSuccess) ||
         hipFuncSetAttribute(reinterpret_cast<const void *>(k_bin_regions),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_stage_b(G.nf)) != hipSuccess) {
         (void)hipFree(h->bin_mem);
         h->bin_mem = nullptr;
         return fail(h, RAMBO_EHIP, "cannot raise the LDS limit of the insert kernels");
     }
-    G.capA = capA;
-    G.capB = capB;
+    G.capA = sp.capA1;
+    G.capB = sp.capB;
+    G.nwg = 1;
+    G.c0 = 0;
+    G.ncb = best_ncb;
+    const uint64_t slabA = std::max((uint64_t)G.na * sp.capA1, (uint64_t)G.na * h->piece_nwg * sp.capAn);
     uint32_t *p = static_cast<uint32_t *>(h->bin_mem);
     G.slabA = p;
-    p += (uint64_t)G.na * capA;
+    p += slabA;
     G.slabB = p;
-    p += n_regions(G) * capB;
-    G.fillA = p;
-    p += G.na;
+    p += group_regions(G, 0, G.ncb) * sp.capB;
     G.fillB = p;
-    p += (uint64_t)G.na * G.nf;
+    p += group_regions(G, 0, G.ncb);
     G.dirty = p;
+    p += (uint64_t)G.na * G.nf;
+    G.fillA = p;   // na * max(nwg, 1); the first na follow dirty, so one fill kernel clears all three
     h->bin_targets = T;
+    h->piece_capA = sp.capAn;
+    return RAMBO_OK;
+}
+
+// Per-sequence piece starts of the piece kernel: n_seqs + 1 words, grown on
+// demand (a buffer a captured insert may still replay on is kept).
+int ensure_pieces(rambo *h, uint64_t n_seqs)
+{
+    if (n_seqs + 1 <= h->piece_cap && h->piece_mem)
+        return RAMBO_OK;
+    uint64_t cap = std::max<uint64_t>(h->piece_cap * 2, 1024);
+    while (cap < n_seqs + 1)
+        cap *= 2;
+    if (h->piece_mem) {
+        const int rc = hip_check(h, hipDeviceSynchronize(), "piece table resize");
+        if (rc)
+            return rc;
+        if (h->recorded_insert)
+            h->retired.push_back(h->piece_mem);
+        else
+            (void)hipFree(h->piece_mem);
+        h->piece_mem = nullptr;
+        h->piece_cap = 0;
+    }
+    if (hipMalloc(&h->piece_mem, cap * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        h->piece_mem = nullptr;
+        return fail(h, RAMBO_ENOMEM, "piece table allocation failed");
+    }
+    h->piece_cap = cap;
     return RAMBO_OK;
 }
 
@@ -627,7 +810,7 @@ bool use_partitioned(const rambo *h, uint64_t n_chars)
 {
     if (!h->part_ok || h->insert_mode == RAMBO_INSERT_DIRECT)
         return false;
-    if (h->insert_mode == RAMBO_INSERT_PARTITIONED)
+    if (h->insert_mode == RAMBO_INSERT_PARTITIONED || h->insert_mode == RAMBO_INSERT_PARTITIONED_WALKER)
         return true;
     const double T = (double)n_chars * h->cfg.R * h->cfg.eta;
     const double regions = (double)h->bin.na * h->bin.nf;
@@ -635,6 +818,36 @@ bool use_partitioned(const rambo *h, uint64_t n_chars)
     const double t_part = (T * 20.0 + (T < regions ? T : regions) * 2.0 * (1u << (kRegionLog2 - 3))) / kStreamRate +
                           100e-6;
     return t_part < t_direct;
+}
+
+// Stages B and C of one batch, after its stage A filled slab A as G says:
+// one pair of launches per group of G.ncb coarse buckets (slab B holds one
+// group's regions; its fill counters are cleared between groups).
+void launch_stages_bc(rambo *h, const BinGeom &G, uint32_t fresh, hipStream_t stream)
+{
+    const uint32_t tpb = (uint32_t)div_up((uint64_t)G.nwg * G.capA, kTileB);
+    const size_t ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
+    for (uint32_t c0 = 0; c0 < G.na; c0 += G.ncb) {
+        BinGeom Gg = G;
+        Gg.c0 = c0;
+        const uint32_t ncb = std::min(G.ncb, G.na - c0);
+        const uint64_t regions = group_regions(G, c0, ncb);
+        if (c0 > 0) {
+            StageScope sc(h, "k_zero_u32", stream);
+            hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(kBlock), 0, stream, G.fillB, regions);
+        }
+        { StageScope sc(h, "k_bin_regions", stream);
+        hipLaunchKernelGGL(k_bin_regions, dim3(ncb * tpb), dim3(kBlockP), ldsB, stream, h->P, Gg, tpb); }
+        { StageScope sc(h, "k_apply_regions", stream);
+        hipLaunchKernelGGL(k_apply_regions, dim3((uint32_t)regions), dim3(kBlock), ldsC, stream, h->P, Gg, fresh); }
+    }
+}
+
+void clear_fill_counters(rambo *h, const BinGeom &G, hipStream_t stream)
+{
+    StageScope sc(h, "k_zero_u32", stream);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillB,
+                       group_regions(G, 0, G.ncb) + (uint64_t)G.na * G.nf + G.na);   // fillB, dirty, fillA[0..na)
 }
 
 // Stages A to C for codes or raw keys, in batches of the scratch's capacity.
@@ -645,36 +858,76 @@ int insert_kmers_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *
     int rc = ensure_scratch(h, n_codes * RE);
     if (rc)
         return rc;
-    BinGeom &G = h->bin;
+    const BinGeom &G = h->bin;
     const StageACodes A = stage_a_codes(h);
-    const size_t ldsA = A.lds, ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     const uint64_t batch = h->bin_targets / RE;
     const uint32_t steps = A.steps;
     const uint32_t rounds = (uint32_t)div_up(kStageAWindowsPerWave, (uint64_t)steps * kWave);
     const uint64_t block_codes = (uint64_t)kWavesP * rounds * steps * kWave;
-    const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
     // as for sequences: only the first batch into an index known to be all
     // zero skips reading the regions back
     uint32_t fresh = h->index_zero && !h->recorded_insert && !capturing(stream) ? 1u : 0u;
     note_insert(h, stream);
     for (uint64_t p = 0; p < n_codes; p += batch, fresh = 0) {
         const uint64_t pe = p + batch < n_codes ? p + batch : n_codes;
-        { StageScope sc(h, "k_zero_u32", stream);
-        hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
-                           (uint64_t)G.na + 2ull * G.na * G.nf); }   // fillA, fillB, dirty
+        clear_fill_counters(h, G, stream);
         { StageScope sc(h, "k_bin_codes", stream);
         const dim3 grid((uint32_t)div_up(pe - p, block_codes));
         if (A.hold)
-            hipLaunchKernelGGL(A.hold, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_sets, codes, p,
-                               pe, rounds);
+            hipLaunchKernelGGL(A.hold, grid, dim3(kBlockP), A.lds, stream, h->P, G, set_ids, offsets, n_sets, codes,
+                               p, pe, rounds);
         else
-            hipLaunchKernelGGL(A.generic, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_sets, codes,
-                               p, pe, steps, rounds); }
-        { StageScope sc(h, "k_bin_regions", stream);
-        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
-        { StageScope sc(h, "k_apply_regions", stream);
-        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G, fresh); }
+            hipLaunchKernelGGL(A.generic, grid, dim3(kBlockP), A.lds, stream, h->P, G, set_ids, offsets, n_sets,
+                               codes, p, pe, steps, rounds); }
+        launch_stages_bc(h, G, fresh, stream);
         if ((rc = launch_check(h, "rambo_insert_kmers (partitioned)")))
+            return rc;
+    }
+    return RAMBO_OK;
+}
+
+// Stages A to C for sequences with the piece kernel: pieces are counted and
+// numbered on the device, then taken in batches of the scratch's capacity
+// (the host knows only an upper bound of the number of pieces; batches past
+// the real end find nothing to do).
+int insert_seqs_pieces(rambo *h, const StageAPieces &AP, const uint32_t *set_ids, const uint64_t *offsets,
+                       uint64_t n_seqs, const uint8_t *chars, uint64_t n_chars, hipStream_t stream)
+{
+    const uint64_t RE = (uint64_t)h->cfg.R * h->cfg.eta;
+    const uint64_t q_up = n_chars / kPieceWindows + n_seqs + 1;
+    int rc = ensure_scratch(h, q_up * kPieceWindows * RE);
+    if (rc)
+        return rc;
+    if ((rc = ensure_pieces(h, n_seqs)))
+        return rc;
+    const uint32_t nwg = h->piece_nwg;
+    uint64_t bp = std::max<uint64_t>(1, h->bin_targets / (kPieceWindows * RE));
+    const uint64_t nb = div_up(q_up, bp);
+    bp = div_up(q_up, nb);
+    BinGeom G = h->bin;
+    G.nwg = nwg;
+    // a batch of at least one piece may hold more targets than the scratch
+    // was sized for: its chunks keep their allocated size and the excess
+    // goes to the fallback atomics
+    G.capA = std::min(chunk_cap(h->bin, bp * kPieceWindows * RE, nwg), h->piece_capA);
+    const uint32_t mis = (uint32_t)(reinterpret_cast<uintptr_t>(chars) & 3u);
+    PieceArgs pa{set_ids, offsets, n_seqs, chars - mis, n_chars + mis, mis, h->piece_mem, 0, 0};
+    {
+        StageScope sc(h, "k_piece_counts", stream);
+        hipLaunchKernelGGL(k_piece_counts, dim3((uint32_t)div_up(n_seqs, kBlock)), dim3(kBlock), 0, stream, offsets,
+                           n_seqs, n_chars, h->cfg.k, h->piece_mem);
+        hipLaunchKernelGGL(k_rq_scan, dim3(1), dim3(1024), 0, stream, h->piece_mem, n_seqs, nullptr);
+    }
+    uint32_t fresh = h->index_zero && !h->recorded_insert && !capturing(stream) ? 1u : 0u;
+    note_insert(h, stream);
+    for (uint64_t q = 0; q < q_up; q += bp, fresh = 0) {
+        pa.q_begin = q;
+        pa.q_end = std::min(q + bp, q_up);
+        clear_fill_counters(h, G, stream);
+        { StageScope sc(h, "k_bin_windows", stream);
+        hipLaunchKernelGGL(AP.fn, dim3(nwg), dim3(kBlockP), AP.lds, stream, h->P, G, pa); }
+        launch_stages_bc(h, G, fresh, stream);
+        if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
             return rc;
     }
     return RAMBO_OK;
@@ -683,19 +936,20 @@ int insert_kmers_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *
 int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *offsets, uint64_t n_seqs,
                             const uint8_t *chars, uint64_t n_chars, hipStream_t stream)
 {
+    const StageAPieces AP = stage_a_pieces(h);
+    if (AP.fn && h->insert_mode != RAMBO_INSERT_PARTITIONED_WALKER)
+        return insert_seqs_pieces(h, AP, set_ids, offsets, n_seqs, chars, n_chars, stream);
     const uint64_t RE = (uint64_t)h->cfg.R * h->cfg.eta;
     int rc = ensure_scratch(h, n_chars * RE);
     if (rc)
         return rc;
-    BinGeom &G = h->bin;
+    const BinGeom &G = h->bin;
     const uint64_t batch_windows = h->bin_targets / RE;
     // stage A: each round takes `steps` steps of every wave
     const StageA A = stage_a(h);
     const uint32_t steps = A.steps;
     const uint32_t rounds = (uint32_t)div_up(kStageAWindowsPerWave, (uint64_t)steps * kWave);
     const uint64_t block_windows = (uint64_t)kWavesP * rounds * steps * kWave;
-    const uint32_t tpb = (uint32_t)div_up(G.capA, kTileB);
-    const size_t ldsA = A.lds, ldsB = lds_bytes_stage_b(G.nf), ldsC = (1ull << (G.rb - 5)) * 4;
     // the first batch into an all-zero index need not read the regions back
     // (never in a captured graph: a replay may find the index holding bits;
     // and never once a recorded insert may have run unseen by the host)
@@ -703,21 +957,16 @@ int insert_seqs_partitioned(rambo *h, const uint32_t *set_ids, const uint64_t *o
     note_insert(h, stream);
     for (uint64_t p = 0; p < n_chars; p += batch_windows, fresh = 0) {
         const uint64_t pe = p + batch_windows < n_chars ? p + batch_windows : n_chars;
-        { StageScope sc(h, "k_zero_u32", stream);
-        hipLaunchKernelGGL(k_zero_u32, dim3(1024), dim3(kBlock), 0, stream, G.fillA,
-                           (uint64_t)G.na + 2ull * G.na * G.nf); }   // fillA, fillB, dirty
+        clear_fill_counters(h, G, stream);
         { StageScope sc(h, "k_bin_windows", stream);
         const dim3 grid((uint32_t)div_up(pe - p, block_windows));
         if (A.hold)
-            hipLaunchKernelGGL(A.hold, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_seqs, chars,
+            hipLaunchKernelGGL(A.hold, grid, dim3(kBlockP), A.lds, stream, h->P, G, set_ids, offsets, n_seqs, chars,
                                n_chars, p, pe, rounds);
         else
-            hipLaunchKernelGGL(A.generic, grid, dim3(kBlockP), ldsA, stream, h->P, G, set_ids, offsets, n_seqs,
+            hipLaunchKernelGGL(A.generic, grid, dim3(kBlockP), A.lds, stream, h->P, G, set_ids, offsets, n_seqs,
                                chars, n_chars, p, pe, steps, rounds); }
-        { StageScope sc(h, "k_bin_regions", stream);
-        hipLaunchKernelGGL(k_bin_regions, dim3(G.na * tpb), dim3(kBlockP), ldsB, stream, h->P, G, tpb); }
-        { StageScope sc(h, "k_apply_regions", stream);
-        hipLaunchKernelGGL(k_apply_regions, dim3(G.na * G.nf), dim3(kBlock), ldsC, stream, h->P, G, fresh); }
+        launch_stages_bc(h, G, fresh, stream);
         if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
             return rc;
     }
@@ -854,6 +1103,13 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
         rambo_destroy(h);
         return RAMBO_ENOMEM;
     }
+    if (hipEventCreateWithFlags(&h->scratch_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        h->scratch_ev = nullptr;
+        g_create_error = "rambo_create: event creation failed";
+        rambo_destroy(h);
+        return RAMBO_EHIP;
+    }
     P.index = h->index;
     P.phi = h->phi;
     P.cellmask = h->cellmask;
@@ -902,6 +1158,12 @@ extern "C" void rambo_destroy(rambo_t *h)
         (void)hipFree(h->bin_mem);
     if (h->rq_mem)
         (void)hipFree(h->rq_mem);
+    if (h->piece_mem)
+        (void)hipFree(h->piece_mem);
+    for (void *p : h->retired)
+        (void)hipFree(p);
+    if (h->scratch_ev)
+        (void)hipEventDestroy(h->scratch_ev);
     for (hipEvent_t e : h->ev_pool)
         (void)hipEventDestroy(e);
     delete h;
@@ -915,12 +1177,17 @@ extern "C" int rambo_set_timing(rambo_t *h, int enable)
     return RAMBO_OK;
 }
 
-extern "C" int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max_stages)
+extern "C" int rambo_get_stage_times(rambo_t *h, char *names, float *ms, uint32_t *calls, int max_stages)
 {
     if (!h || max_stages < 0 || (max_stages > 0 && (!names || !ms)))
         return RAMBO_EINVAL;
     constexpr int kSlot = 48;
-    std::vector<std::pair<std::string, float>> acc;
+    struct Acc {
+        std::string name;
+        float ms;
+        uint32_t calls;
+    };
+    std::vector<Acc> acc;
     int rc = RAMBO_OK;
     for (const auto &s : h->stages) {
         float t = 0.f;
@@ -928,11 +1195,13 @@ extern "C" int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max
             rc = hip_check(h, hipEventElapsedTime(&t, s.a, s.b), "rambo_get_stage_times");
         if (rc)
             break;
-        auto it = std::find_if(acc.begin(), acc.end(), [&](const auto &e) { return e.first == s.name; });
-        if (it == acc.end())
-            acc.emplace_back(s.name, t);
-        else
-            it->second += t;
+        auto it = std::find_if(acc.begin(), acc.end(), [&](const Acc &e) { return e.name == s.name; });
+        if (it == acc.end()) {
+            acc.push_back({s.name, t, 1u});
+        } else {
+            it->ms += t;
+            it->calls += 1;
+        }
     }
     h->stages.clear();
     h->ev_used = 0;
@@ -941,8 +1210,10 @@ extern "C" int rambo_get_stage_times(rambo_t *h, char *names, float *ms, int max
     const int n = (int)acc.size() < max_stages ? (int)acc.size() : max_stages;
     for (int i = 0; i < n; ++i) {
         std::memset(names + (size_t)i * kSlot, 0, kSlot);
-        std::strncpy(names + (size_t)i * kSlot, acc[i].first.c_str(), kSlot - 1);
-        ms[i] = acc[i].second;
+        std::strncpy(names + (size_t)i * kSlot, acc[i].name.c_str(), kSlot - 1);
+        ms[i] = acc[i].ms;
+        if (calls)
+            calls[i] = acc[i].calls;
     }
     return (int)acc.size();
 }
@@ -960,13 +1231,16 @@ extern "C" int rambo_set_query_policy(rambo_t *h, int mode, uint32_t chunk_bytes
 
 extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes)
 {
-    if (!h || mode < RAMBO_INSERT_AUTO || mode > RAMBO_INSERT_PARTITIONED)
+    if (!h || mode < RAMBO_INSERT_AUTO || mode > RAMBO_INSERT_PARTITIONED_WALKER)
         return RAMBO_EINVAL;
     if (scratch_bytes != h->scratch_limit && h->bin_mem) {
         const int rc = hip_check(h, hipDeviceSynchronize(), "rambo_set_insert_policy");
         if (rc)
             return rc;
-        (void)hipFree(h->bin_mem);
+        if (h->recorded_insert)
+            h->retired.push_back(h->bin_mem);   // a captured insert may still replay on it
+        else
+            (void)hipFree(h->bin_mem);
         h->bin_mem = nullptr;
     }
     h->insert_mode = mode;
@@ -1004,8 +1278,10 @@ extern "C" int rambo_insert_kmers(rambo_t *h, const uint32_t *set_ids, const uin
         return RAMBO_OK;
     if (!set_ids || !offsets || !codes)
         return fail(h, RAMBO_EINVAL, "rambo_insert_kmers: NULL array");
-    if (use_partitioned(h, n_codes))
+    if (use_partitioned(h, n_codes)) {
+        ScratchUse su(h, stream);
         return insert_kmers_partitioned(h, set_ids, offsets, n_sets, codes, n_codes, stream);
+    }
     note_insert(h, stream);
     StageScope sc(h, "k_insert_kmers", stream);
     hipLaunchKernelGGL(k_insert_kmers, dim3((uint32_t)div_up(n_codes, kBlock)), dim3(kBlock), 0, stream, h->P,
@@ -1024,8 +1300,10 @@ extern "C" int rambo_insert_seqs(rambo_t *h, const uint32_t *set_ids, const uint
         return RAMBO_OK;
     if (!set_ids || !offsets || !chars)
         return fail(h, RAMBO_EINVAL, "rambo_insert_seqs: NULL array");
-    if (use_partitioned(h, n_chars))
+    if (use_partitioned(h, n_chars)) {
+        ScratchUse su(h, stream);
         return insert_seqs_partitioned(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
+    }
     return insert_seqs_direct(h, set_ids, offsets, n_seqs, chars, n_chars, stream);
 }
 
@@ -1070,9 +1348,12 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
         with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream});
         return launch_check(h, "rambo_query_seqs");
     }
+    ScratchUse su(h, stream);
     int rc = ensure_read_queue(h, n_reads);
     if (rc)
         return rc;
+    if (capturing(stream))
+        h->rq_recorded = true;
     launch_read_queue(h, h->rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, out_masks, out_nkmers, stream);
     return launch_check(h, "rambo_query_seqs");
 }
@@ -1087,11 +1368,18 @@ extern "C" int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_
         return rr;
     if (!id_offsets || (n_reads > 0 && !offsets) || (n_chars > 0 && !chars) || (cap > 0 && !ids))
         return fail(h, RAMBO_EINVAL, "rambo_query_seqs_ids: NULL array");
-    if (n_reads == 0)
-        return hip_check(h, hipMemsetAsync(id_offsets, 0, 8, stream), "rambo_query_seqs_ids");
+    if (n_reads == 0) {
+        // id_offsets[0] = 0 by a fill kernel (no memset node if recorded)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, stream, reinterpret_cast<uint32_t *>(id_offsets),
+                           (uint64_t)2, 0u);
+        return launch_check(h, "rambo_query_seqs_ids");
+    }
+    ScratchUse su(h, stream);
     int rc = ensure_read_queue(h, n_reads);
     if (rc)
         return rc;
+    if (capturing(stream))
+        h->rq_recorded = true;
     // group masks and window counts only: the answers stay in the per-read state
     if (wave_per_read(h, n_reads, n_chars))
         with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, nullptr, out_nkmers, stream});
@@ -1149,8 +1437,13 @@ extern "C" int rambo_extract_kmers(rambo_t *h, const uint64_t *offsets, uint64_t
         return RAMBO_OK;
     if (!chars || !out_codes || (n_seqs > 0 && !offsets))
         return fail(h, RAMBO_EINVAL, "rambo_extract_kmers: NULL array");
-    if (n_seqs == 0)
-        return hip_check(h, hipMemsetAsync(out_codes, 0xFF, n_chars * 8, stream), "rambo_extract_kmers");
+    if (n_seqs == 0) {
+        // no sequence holds any byte: every entry is "no window" (a fill
+        // kernel, so that a recorded call holds no memset node)
+        hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)std::min<uint64_t>(div_up(2 * n_chars, kBlock), 4096)),
+                           dim3(kBlock), 0, stream, reinterpret_cast<uint32_t *>(out_codes), 2 * n_chars, ~0u);
+        return launch_check(h, "rambo_extract_kmers");
+    }
     const uint64_t waves = div_up(n_chars, kChunk);
     StageScope sc(h, "k_extract", stream);
     hipLaunchKernelGGL(k_extract, dim3((uint32_t)div_up(waves, kWavesPerBlock)), dim3(kBlock), 0, stream, h->cfg.k,

@@ -74,7 +74,8 @@ struct rambo_server {
     int64_t next_id = 0;
     bool stop = false;
     std::thread worker;
-    uint64_t n_batches = 0, n_requests = 0, n_reads = 0;
+    uint64_t n_batches = 0, n_requests = 0, n_reads = 0, n_failed = 0;
+    uint32_t inject_failures = 0;     // test hook: batches to fail on the host before they launch
     void *ins_mem = nullptr;          // device staging of insert requests (grown on demand)
     uint64_t ins_cap = 0;
     int device = 0;
@@ -155,8 +156,31 @@ int init_slot(rambo *h, const rambo_serve_config &c, ServeSlot &s)
     return RAMBO_OK;
 }
 
+// Hand every request of slot s back with `status` (a failed batch: no
+// answers), and free the slot.
+void fail_batch(rambo_server *sv, ServeSlot &s, int status)
+{
+    const auto t = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (const auto &r : s.reqs) {
+            r->masks.assign(r->n_reads * sv->h->W, 0u);
+            r->nk.assign(r->n_reads, 0u);
+            r->status = status;
+            r->t_done = t;
+            r->done = true;
+        }
+        sv->n_failed += 1;
+        sv->n_requests += s.reqs.size();
+    }
+    sv->cv_done.notify_all();
+    s.reqs.clear();
+    s.busy = false;
+}
+
 // Pack queued requests into slot s and start its batch.  Called by the
-// worker with the lock not held; returns whether a batch was started.
+// worker with the lock not held; returns whether a batch was taken (started,
+// or failed at once: then its requests are answered with RAMBO_EHIP).
 bool start_batch(rambo_server *sv, ServeSlot &s)
 {
     const rambo_serve_config &c = sv->cfg;
@@ -189,17 +213,43 @@ bool start_batch(rambo_server *sv, ServeSlot &s)
     s.h_hdr[0] = reads;
     s.h_hdr[1 + reads] = bytes;
     s.n_reads = reads;
-    (void)hipMemcpyAsync(s.d_hdr, s.h_hdr, 8 * (reads + 2), hipMemcpyHostToDevice, s.stream);
-    if (bytes)
-        (void)hipMemcpyAsync(s.d_chars, s.h_chars, bytes, hipMemcpyHostToDevice, s.stream);
-    if (s.exec)
-        (void)hipGraphLaunch(s.exec, s.stream);
-    else
-        launch_read_queue(sv->h, s.rq, s.d_hdr + 1, reads, nullptr, reads, s.d_chars, bytes, s.d_masks, s.d_nk,
-                          s.stream);
-    (void)hipMemcpyAsync(s.h_masks, s.d_masks, 4ull * reads * sv->h->W, hipMemcpyDeviceToHost, s.stream);
-    (void)hipMemcpyAsync(s.h_nk, s.d_nk, 4 * reads, hipMemcpyDeviceToHost, s.stream);
-    (void)hipEventRecord(s.done_ev, s.stream);
+    bool injected = false;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->inject_failures) {
+            --sv->inject_failures;
+            injected = true;
+        }
+    }
+    hipError_t e = injected ? hipErrorUnknown : hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.d_hdr, s.h_hdr, 8 * (reads + 2), hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess && bytes)
+        e = hipMemcpyAsync(s.d_chars, s.h_chars, bytes, hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess) {
+        if (s.exec)
+            e = hipGraphLaunch(s.exec, s.stream);
+        else {
+            launch_read_queue(sv->h, s.rq, s.d_hdr + 1, reads, nullptr, reads, s.d_chars, bytes, s.d_masks, s.d_nk,
+                              s.stream);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.h_masks, s.d_masks, 4ull * reads * sv->h->W, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.h_nk, s.d_nk, 4 * reads, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(s.done_ev, s.stream);
+    if (e != hipSuccess) {
+        if (!injected)
+            (void)hipGetLastError();
+        // whatever was enqueued before the failure must finish before the
+        // slot's buffers are reused
+        (void)hipStreamSynchronize(s.stream);
+        fail_batch(sv, s, RAMBO_EHIP);
+        return true;
+    }
     s.busy = true;
     return true;
 }
@@ -282,8 +332,17 @@ void serve_loop(rambo_server *sv)
     for (;;) {
         bool progress = false, any_busy = false;
         for (ServeSlot &s : sv->slots) {
-            if (s.busy && hipEventQuery(s.done_ev) == hipSuccess) {
+            if (!s.busy)
+                continue;
+            const hipError_t q = hipEventQuery(s.done_ev);
+            if (q == hipSuccess) {
                 finish_batch(sv, s);
+                progress = true;
+            } else if (q != hipErrorNotReady) {
+                // the batch failed on the device: its requests get the error
+                // instead of waiting for an event that will not complete
+                (void)hipGetLastError();
+                fail_batch(sv, s, RAMBO_EHIP);
                 progress = true;
             }
         }
@@ -547,6 +606,15 @@ extern "C" int rambo_serve_replay(rambo_server_t *sv, uint64_t n_req, const uint
     if (checksum)
         *checksum = sum;
     return rc;
+}
+
+extern "C" int rambo_serve_inject_failures(rambo_server_t *sv, uint32_t n_batches)
+{
+    if (!sv)
+        return RAMBO_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->inject_failures = n_batches;
+    return RAMBO_OK;
 }
 
 extern "C" int rambo_serve_stats(rambo_server_t *sv, uint64_t *batches, uint64_t *requests, uint64_t *reads,

@@ -25,7 +25,7 @@ ECODE = -1001
 ETIMEDOUT = -110
 FLAG_IDENTITY_PARTITION = 1
 FLAG_RAW_KEYS = 4   # terms are 64-bit keys (documents and word unigrams) passed as the k-mer codes
-INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED = 0, 1, 2
+INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED, INSERT_PARTITIONED_WALKER = 0, 1, 2, 3
 QUERY_AUTO, QUERY_WAVE_PER_READ, QUERY_QUEUE = 0, 1, 2
 NO_KMER = -1   # UINT64_MAX viewed as int64
 
@@ -82,7 +82,8 @@ EXPORTS = {
     "rambo_set_insert_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]),
     "rambo_set_query_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
     "rambo_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
-    "rambo_get_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "rambo_get_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int]),
     "rambo_clear": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_fold": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p]),
@@ -111,6 +112,7 @@ EXPORTS = {
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "rambo_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
+    "rambo_serve_inject_failures": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "rambo_serve_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(ctypes.c_uint32)]),
@@ -316,7 +318,7 @@ class Rambo:
         return out
 
     def set_insert_policy(self, mode: int = 0, scratch_bytes: int = 0):
-        """INSERT_AUTO / INSERT_DIRECT / INSERT_PARTITIONED; same index bits."""
+        """INSERT_AUTO / INSERT_DIRECT / INSERT_PARTITIONED / INSERT_PARTITIONED_WALKER; same index bits."""
         self._check(lib().rambo_set_insert_policy(self._h, mode, scratch_bytes), "rambo_set_insert_policy")
 
     def set_query_policy(self, mode: int = 0, chunk_bytes: int = 0, waves_per_cu: int = 0):
@@ -327,15 +329,21 @@ class Rambo:
     def set_timing(self, enable: bool = True):
         self._check(lib().rambo_set_timing(self._h, int(enable)), "rambo_set_timing")
 
-    def stage_times(self, max_stages: int = 32) -> dict:
-        """Milliseconds per kernel name since the last call (HIP events)."""
+    def stage_times(self, max_stages: int = 32, calls: bool = False) -> dict:
+        """Milliseconds per kernel name since the last call (HIP events);
+        with calls, (milliseconds, launches) per name."""
         names = ctypes.create_string_buffer(48 * max_stages)
         ms = (ctypes.c_float * max_stages)()
-        n = lib().rambo_get_stage_times(self._h, names, ms, max_stages)
+        cnt = (ctypes.c_uint32 * max_stages)()
+        n = lib().rambo_get_stage_times(self._h, names, ms, cnt, max_stages)
         if n < 0:
             self._check(n, "rambo_get_stage_times")
         raw = names.raw
-        return {raw[48 * i:48 * (i + 1)].split(b"\0")[0].decode(): float(ms[i]) for i in range(min(n, max_stages))}
+        out = {}
+        for i in range(min(n, max_stages)):
+            name = raw[48 * i:48 * (i + 1)].split(b"\0")[0].decode()
+            out[name] = (float(ms[i]), int(cnt[i])) if calls else float(ms[i])
+        return out
 
     def _refresh_info(self):
         info = Info()
@@ -474,6 +482,13 @@ class Server:
         if rc != OK:
             raise RamboError(rc, "rambo_serve_replay")
         return lat, ck.value
+
+    def inject_failures(self, n_batches: int):
+        """Test hook: the next n_batches batches fail before launch (their
+        requests are answered with RAMBO_EHIP)."""
+        rc = lib().rambo_serve_inject_failures(self._s, n_batches)
+        if rc != OK:
+            raise RamboError(rc, "rambo_serve_inject_failures")
 
     def stats(self) -> dict:
         b, q, r = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

@@ -52,8 +52,14 @@ def _csr(parts: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray]:
 
 
 def random_bases(rng: np.random.Generator, n: int) -> np.ndarray:
-    """n uniform random bases as base indices 0..3."""
-    return rng.integers(0, 4, size=n, dtype=np.uint8)
+    """n uniform random bases as base indices 0..3 (the 2-bit digits of
+    uniform 64-bit words)."""
+    words = rng.integers(0, 2**64, size=(n + 31) // 32, dtype=np.uint64)
+    out = np.empty(((n + 31) // 32) * 32, np.uint8)
+    w8 = words.view(np.uint8)                       # little-endian bytes, 4 digits each
+    for d in range(4):
+        out[d::4] = (w8 >> np.uint8(2 * d)) & np.uint8(3)
+    return out[:n]
 
 
 def substitute(rng: np.random.Generator, idx: np.ndarray, rate: float) -> np.ndarray:
@@ -61,16 +67,9 @@ def substitute(rng: np.random.Generator, idx: np.ndarray, rate: float) -> np.nda
     the other three bases, uniformly (a Bernoulli process drawn as geometric
     gaps)."""
     out = idx.copy()
-    L = out.size
-    if rate <= 0 or L == 0:
+    if rate <= 0 or out.size == 0:
         return out
-    mean = L * rate
-    draw = int(mean + 10 * math.sqrt(mean) + 16)
-    pos = np.cumsum(rng.geometric(rate, size=draw)) - 1
-    while pos[-1] < L:
-        more = np.cumsum(rng.geometric(rate, size=draw)) + pos[-1]
-        pos = np.concatenate([pos, more])
-    pos = pos[pos < L]
+    pos = _bernoulli_positions(rng, out.size, rate)
     out[pos] = (out[pos] + rng.integers(1, 4, size=pos.size, dtype=np.uint8)) & 3
     return out
 
@@ -91,25 +90,55 @@ def genome_sets(seed: int, K: int, n_ancestors: int, ancestor_len: int, *,
                 min_len: int | None = None, max_len: int | None = None) -> SeqBatch:
     """K genomes: set i is a window of ancestor (i mod n_ancestors) with
     independent substitutions.  With median_len None every set is the whole
-    ancestor; otherwise the window length is lognormal (clipped)."""
+    ancestor; otherwise the window length is lognormal (clipped).  The
+    ancestors are drawn at once, the windows copied into place, and the
+    substitutions drawn as one Bernoulli process over all genomes (the same
+    law as per genome: every base independently)."""
     rng = rng_for(seed)
-    anc = [random_bases(rng, ancestor_len) for _ in range(n_ancestors)]
+    anc = _LUT[random_bases(rng, n_ancestors * ancestor_len)].reshape(n_ancestors, ancestor_len)
     if median_len is None:
         lens = np.full(K, ancestor_len, dtype=np.int64)
     else:
         lens = lognormal_lengths(rng, K, median_len, min_len, min(max_len, ancestor_len))
+    starts = (rng.random(K) * (ancestor_len - lens + 1)).astype(np.int64)
     offsets = np.zeros(K + 1, dtype=np.uint64)
     np.cumsum(lens.astype(np.uint64), out=offsets[1:])
     chars = np.empty(int(offsets[-1]), dtype=np.uint8)   # filled in place: no second copy of the genomes
     for i in range(K):
-        a = anc[i % n_ancestors]
-        L = int(lens[i])
-        start = int(rng.integers(0, ancestor_len - L + 1))
-        o = int(offsets[i])
-        chars[o:o + L] = _LUT[substitute(rng, a[start:start + L], sub_rate)]
+        o, L, st = int(offsets[i]), int(lens[i]), int(starts[i])
+        chars[o:o + L] = anc[i % n_ancestors, st:st + L]
+    del anc
+    _substitute_bytes(rng, chars, sub_rate)
     return SeqBatch(chars, offsets, np.arange(K, dtype=np.uint32),
                     meta=dict(K=K, n_ancestors=n_ancestors, ancestor_len=ancestor_len,
                               sub_rate=sub_rate, median_len=median_len))
+
+
+def _substitute_bytes(rng: np.random.Generator, chars: np.ndarray, rate: float, chunk: int = 1 << 28) -> None:
+    """In place, on ACGT bytes: every position independently, with
+    probability `rate`, becomes one of the other three bases, uniformly
+    (drawn chunk by chunk so that memory stays bounded)."""
+    if rate <= 0:
+        return
+    back = np.zeros(256, np.uint8)
+    back[_LUT] = np.arange(4, dtype=np.uint8)
+    for a in range(0, chars.size, chunk):
+        seg = chars[a:a + chunk]
+        pos = _bernoulli_positions(rng, seg.size, rate)
+        seg[pos] = _LUT[(back[seg[pos]] + rng.integers(1, 4, size=pos.size, dtype=np.uint8)) & 3]
+
+
+def _bernoulli_positions(rng: np.random.Generator, L: int, rate: float) -> np.ndarray:
+    """Positions in [0, L) of a Bernoulli(rate) process, drawn as geometric gaps."""
+    if L == 0:
+        return np.zeros(0, np.int64)
+    mean = L * rate
+    draw = int(mean + 10 * math.sqrt(mean) + 16)
+    pos = np.cumsum(rng.geometric(rate, size=draw)) - 1
+    while pos[-1] < L:
+        more = np.cumsum(rng.geometric(rate, size=draw)) + pos[-1]
+        pos = np.concatenate([pos, more])
+    return pos[pos < L]
 
 
 # ------------------------------------------------------------------ queries
@@ -145,30 +174,54 @@ def reads(seed: int, sets: SeqBatch, n: int, *, median_len: int, min_len: int, m
     """n reads.  A fraction substr_frac are substrings of a uniformly chosen
     set genome (cut to the genome's length), optionally with further
     substitutions; the rest are uniform random ACGT.  Lengths are lognormal
-    (clipped) unless given."""
+    (clipped) unless given.  meta['source_set']: the genome of each
+    substring read, -1 for random reads."""
     rng = rng_for(seed)
     if lengths is None:
         lengths = lognormal_lengths(rng, n, median_len, min_len, max_len)
+    lengths = np.asarray(lengths, np.int64).copy()
     kind = rng.random(n) < substr_frac
     glens = sets.lengths().astype(np.int64)
-    parts = []
-    src = np.full(n, -1, dtype=np.int64)
-    for q in range(n):
-        L = int(lengths[q])
-        if kind[q]:
-            g = int(rng.integers(0, sets.n))
-            L = min(L, int(glens[g]))
-            st = int(sets.offsets[g]) + int(rng.integers(0, int(glens[g]) - L + 1))
-            seq = sets.chars[st:st + L]
-            if read_sub_rate > 0:
-                back = np.searchsorted(_LUT, seq)  # bytes are exactly ACGT here
-                seq = to_bytes(substitute(rng, back.astype(np.uint8), read_sub_rate))
-            parts.append(np.ascontiguousarray(seq))
-            src[q] = g
-        else:
-            parts.append(to_bytes(random_bases(rng, L)))
-    chars, offsets = _csr(parts)
-    return SeqBatch(chars, offsets, None, meta=dict(source_set=src))
+    n_sub = int(kind.sum())
+    g = rng.integers(0, sets.n, size=n_sub)
+    sub = np.nonzero(kind)[0]
+    lengths[sub] = np.minimum(lengths[sub], glens[g])
+    st = sets.offsets[g].astype(np.int64) + (rng.random(n_sub) * (glens[g] - lengths[sub] + 1)).astype(np.int64)
+    offsets = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lengths.astype(np.uint64), out=offsets[1:])
+    chars = np.empty(int(offsets[-1]), dtype=np.uint8)
+    # substring reads: one gather of every byte (start of the read's source
+    # + position in the read), in chunks of reads
+    o64 = offsets.astype(np.int64)
+    for a in range(0, n_sub, 1 << 18):
+        q = sub[a:a + (1 << 18)]
+        L = lengths[q]
+        dst = np.repeat(o64[q], L) + _ranges(L)
+        src = np.repeat(st[a:a + (1 << 18)], L) + _ranges(L)
+        chars[dst] = sets.chars[src]
+        if read_sub_rate > 0:
+            seg = chars[dst]
+            _substitute_bytes(rng, seg, read_sub_rate)
+            chars[dst] = seg
+    rnd = np.nonzero(~kind)[0]
+    for a in range(0, rnd.size, 1 << 18):
+        q = rnd[a:a + (1 << 18)]
+        L = lengths[q]
+        dst = np.repeat(o64[q], L) + _ranges(L)
+        chars[dst] = _LUT[random_bases(rng, int(L.sum()))]
+    src_set = np.full(n, -1, dtype=np.int64)
+    src_set[sub] = g
+    return SeqBatch(chars, offsets, None, meta=dict(source_set=src_set))
+
+
+def _ranges(L: np.ndarray) -> np.ndarray:
+    """Concatenation of arange(l) for every l in L."""
+    L = np.asarray(L, np.int64)
+    total = int(L.sum())
+    if total == 0:
+        return np.zeros(0, np.int64)
+    starts = np.cumsum(L) - L
+    return np.arange(total, dtype=np.int64) - np.repeat(starts, L)
 
 
 # ---------------------------------------------------------------- documents

@@ -2,8 +2,9 @@
 R = 4, m = 2^28, eta = 2; ~2.7e8 inserts), in the launch configuration
 bench.py times (rambo_insert_seqs with the automatic policy, batched
 rambo_query_kmers).  The oracle builds the whole index on the host; the GPU
-index is compared through per-cell fill counts over every bit, sampled rows,
-and sampled queries and reads."""
+index is compared with the oracle's filters bit for bit (every row of every
+repetition), through per-cell fill counts, and on sampled queries and
+reads."""
 import os
 
 import numpy as np
@@ -52,12 +53,31 @@ def test_mid_fill_counts_every_cell(mid):
     assert np.array_equal(g.fill_counts().cpu().numpy(), want)   # the library's own counting kernel
 
 
-def test_mid_sampled_rows(mid):
+def _cell_bytes(rows: torch.Tensor, b: int) -> np.ndarray:
+    """Bit b of every row (an [m, S/32] int32 device view of one repetition),
+    packed little-endian into m/8 bytes on the device: the layout of one
+    oracle filter's words."""
+    col = torch.bitwise_and(torch.bitwise_right_shift(rows[:, b // 32], b % 32), 1).to(torch.uint8)
+    weights = torch.tensor([1, 2, 4, 8, 16, 32, 64, 128], dtype=torch.uint8, device=rows.device)
+    packed = (col.view(-1, 8) * weights).sum(dim=1, dtype=torch.uint8)
+    return packed.cpu().numpy()
+
+
+def test_mid_every_row(mid):
+    # the whole index, cell by cell: all m bits of every filter (r, b) equal
+    # the oracle's separate filter, and the row padding (bits B..S-1) is zero
     cfg, sets, o, g, _ = mid
-    rng = np.random.default_rng(7)
+    S = g.row_bits
     for r in range(cfg["R"]):
-        rows = np.sort(rng.choice(cfg["m"], size=20_000, replace=False)).astype(np.uint64)
-        assert np.array_equal(gpu_rows(g, r, rows), o.bits_at(r, rows)), r
+        rows = g.index_words(r * g.words_per_rep, g.m * S // 32).view(g.m, S // 32)
+        for b in range(cfg["B"]):
+            want = o.bfu_words(r, b).view(np.uint8)
+            assert np.array_equal(_cell_bytes(rows, b), want), (r, b)
+        pad = torch.zeros_like(rows[:, 0])
+        for b in range(cfg["B"], S):
+            pad = torch.bitwise_or(pad, torch.bitwise_and(torch.bitwise_right_shift(rows[:, b // 32], b % 32), 1))
+        assert int(pad.max()) == 0, r
+        del rows
 
 
 def test_mid_sampled_queries(mid):

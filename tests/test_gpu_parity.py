@@ -280,6 +280,7 @@ def test_partitioned_insert_in_many_batches(tiny):
     _, g = _partitioned_pair(cfg, 2001, scratch=1 << 20)   # ~50k targets per batch
     gpu_insert_seqs(g, sets)
     assert g.sync_status() == 0
+    assert np.array_equal(gpu_index_bits(g), oracle_index_bits(o))
     assert torch.equal(g.index_words(), g_direct.index_words())
 
 
@@ -328,14 +329,46 @@ def test_partitioned_insert_overflow_falls_back():
 
 
 @pytest.mark.parametrize("cfg", SHAPES, ids=lambda c: "K%(K)d-B%(B)d-R%(R)d-e%(eta)d-k%(k)d-m%(m)d" % c)
-def test_partitioned_shapes_match_direct(cfg):
+def test_partitioned_shapes_match_oracle(cfg):
+    # the partitioned insert (stage A with the targets held in registers for
+    # R = 3..6 at eta = 2, the run-time kernel otherwise) against the oracle's
+    # separate filters, and against the direct insert
     K = cfg["K"]
     sets = synth.genome_sets(K + cfg["B"] + 1, K=K, n_ancestors=5, ancestor_len=400, sub_rate=0.02)
-    _, gd = make_pair(cfg, seed=cfg["B"] * 3 + 1)
+    o, gd = make_pair(cfg, seed=cfg["B"] * 3 + 1)
+    assert o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8) == 0
     gd.set_insert_policy(rb.INSERT_DIRECT)
     _, gp = _partitioned_pair(cfg, cfg["B"] * 3 + 1, scratch=4 << 20)
     gpu_insert_seqs(gd, sets)
     gpu_insert_seqs(gp, sets)
-    gpu_insert_seqs(gp, sets)   # a second call ORs into the same regions
     assert gd.sync_status() == 0 and gp.sync_status() == 0
-    assert torch.equal(gp.index_words(), gd.index_words())
+    want = oracle_index_bits(o)
+    assert np.array_equal(gpu_index_bits(gp), want)
+    gpu_insert_seqs(gp, sets)   # a second call ORs into the same regions (read back): no change
+    assert gp.sync_status() == 0
+    assert np.array_equal(gpu_index_bits(gp), want)
+    assert np.array_equal(gpu_index_bits(gd), want)
+
+
+@pytest.mark.parametrize("mis", [0, 1, 3])
+@pytest.mark.parametrize("m", [1 << 16, 50_000])
+def test_piece_insert_edges(mis, m):
+    # the sequence binning kernel's edge cases: sequences shorter than k, of
+    # exactly k, around the piece length (8 192 windows) and a lane's span
+    # (128 windows), N runs and lower case inside windows, empty sequences,
+    # and byte buffers that do not start on a 4-byte boundary; against the
+    # oracle, for a power-of-two m (32-bit positions) and another m
+    P = 8192
+    lengths = [0, 1, 30, 31, 32, 158, 159, 160, P + 29, P + 30, P + 31, 3 * P + 95, 20000, 3, 0, 100_000, 777]
+    b = _seqs_with_noise(40 + mis, lengths, 31)
+    b.set_ids = (np.arange(b.n) % 40).astype(np.uint32)
+    cfg = dict(K=40, B=8, R=4, eta=2, k=31, m=m)
+    o, g = _partitioned_pair(cfg, 77 + mis)
+    assert o.insert_seqs(b.set_ids, b.offsets, b.chars, 8) == 0
+    pad = torch.zeros(b.chars.size + 8, dtype=torch.uint8, device="cuda")
+    pad[mis:mis + b.chars.size] = dev(b.chars, np.uint8)
+    chars = pad[mis:mis + b.chars.size]
+    assert chars.data_ptr() % 4 == mis
+    g.insert_seqs(dev(b.set_ids, np.int32), dev(b.offsets, np.int64), chars)
+    assert g.sync_status() == 0
+    assert np.array_equal(gpu_index_bits(g), oracle_index_bits(o))

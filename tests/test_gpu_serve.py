@@ -209,3 +209,29 @@ def test_native_replay_driver(served):
         bad[1] = bad[0]            # a request without reads
         with pytest.raises(rb.RamboError):
             srv.replay(bad, batch.offsets, batch.chars, np.zeros(ro.size - 1))
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_failed_batches_answer_with_an_error(served, graphs):
+    # the worker's error path, forced from the host (no device fault): the
+    # requests of a failed batch are answered with RAMBO_EHIP instead of
+    # blocking their waiters, and the server goes on answering later ones
+    g, reqs, want = served
+    with rb.Server(g, max_slots=2, use_graphs=graphs) as srv:
+        srv.inject_failures(1)
+        rid = srv.submit(*reqs[0])
+        with pytest.raises(rb.RamboError) as e:
+            srv.wait(rid, len(reqs[0][0]) - 1, timeout_us=TIMEOUT_US)
+        assert e.value.code == rb.EHIP
+        check(alone(srv, reqs[:10]), want[:10])
+        srv.inject_failures(3)
+        ids = [srv.submit(off, ch) for off, ch in reqs[:20]]
+        codes = []
+        for rid, (off, _) in zip(ids, reqs[:20]):
+            try:
+                srv.wait(rid, len(off) - 1, timeout_us=TIMEOUT_US)
+                codes.append(rb.OK)
+            except rb.RamboError as err:
+                codes.append(err.code)
+        assert set(codes) <= {rb.OK, rb.EHIP} and rb.EHIP in codes
+        check(alone(srv, reqs[:10]), want[:10])
