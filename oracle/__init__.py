@@ -81,6 +81,7 @@ def lib():
             "orc_set_partition": (i32, [vp, vp]),
             "orc_scan_rows": (i32, [vp, vp, vp, vp, u64, u64, vp, vp, u64, vp, i32, i32]),
             "orc_window_keys": (u64, [vp, vp, vp, u64, vp, u64]),
+            "orc_cell_bits": (i32, [vp, u32, u32, vp, vp, vp, u64, vp, i32]),
             "orc_query_seqs_rows": (i32, [vp, vp, vp, u64, vp, u64, vp, vp, vp, i32]),
         }
         for name, (res, args) in sig.items():
@@ -313,6 +314,46 @@ class OracleIndex:
         if rc != 0:
             raise ValueError("orc_scan_rows failed (%d)" % rc)
         return sampled, rows
+
+    def cell_bits(self, r: int, b: int, set_ids, offsets, chars, nthreads=0) -> np.ndarray:
+        """The BFU of cell (r, b) built from the given sequences (Alg. 1 for
+        that one cell): ceil(m/64) uint64 words, bit p of word p/64."""
+        set_ids = np.ascontiguousarray(set_ids, np.uint32)
+        offsets = np.ascontiguousarray(offsets, np.uint64)
+        chars = np.ascontiguousarray(chars, np.uint8)
+        out = np.zeros((self.m + 63) // 64, np.uint64)
+        rc = lib().orc_cell_bits(self._h, r, b, _ptr(set_ids), _ptr(offsets), _ptr(chars), set_ids.size,
+                                 _ptr(out), nthreads)
+        if rc != 0:
+            raise ValueError("orc_cell_bits failed (%d)" % rc)
+        return out
+
+    def members_from_cells(self, offsets, chars, cells) -> np.ndarray:
+        """Whether one set s is in the Sec. 3.2.1 answer of each read, from
+        the R cells that hold it (cells[r]: the BFU words of cell
+        (r, phi_r(s))).  Alg. 2 answers the intersection over r of the union
+        of the sets of the passing cells; s lies in exactly one cell per
+        repetition, so it is in the answer of a term iff every one of its R
+        cells passes (all eta bits set), and in a read's answer iff that holds
+        for every valid window.  A read with no valid window answers the
+        empty set."""
+        offsets = np.ascontiguousarray(offsets, np.uint64)
+        chars = np.ascontiguousarray(chars, np.uint8)
+        n = offsets.size - 1
+        out = np.zeros(n, bool)
+        base = (np.arange(self.R, dtype=np.uint64) * np.uint64(self.m))[None, :, None]
+        for i in range(n):
+            o = np.array([0, offsets[i + 1] - offsets[i]], np.uint64)
+            keys = self.window_keys(o, chars[int(offsets[i]):int(offsets[i + 1])])
+            if keys.size == 0:
+                continue
+            pos = keys.reshape(-1, self.R, self.eta) - base
+            ok = True
+            for r in range(self.R):
+                p = pos[:, r, :].ravel()
+                ok = ok and bool(((cells[r][p // np.uint64(64)] >> (p % np.uint64(64))) & np.uint64(1)).all())
+            out[i] = ok
+        return out
 
     def query_seqs_rows(self, offsets, chars, keys, rows, nthreads=0):
         """Sec. 3.2.1 answers of reads with the filter bits read from rows

@@ -688,6 +688,42 @@ int orc_scan_rows(const orc_index *h, const uint32_t *set_ids, const uint64_t *o
     return ORC_OK;
 }
 
+/* The BFU of one cell (r, b) of an index too large for host memory (Alg. 1
+ * restricted to that cell): every valid window of every given sequence
+ * whose set the partition hash puts in cell b of repetition r sets bits
+ * pos_{r,j}(x), j < eta; sequences of other cells are passed over.  out:
+ * ceil(m/64) words, OR-ed into (the caller clears it), bit p of word p/64. */
+int orc_cell_bits(const orc_index *h, uint32_t r, uint32_t b, const uint32_t *set_ids, const uint64_t *offsets,
+                  const unsigned char *chars, uint64_t n_seqs, uint64_t *out, int nthreads)
+{
+    if (r >= h->R || b >= h->B || (h->flags & ORC_FLAG_RAW_KEYS))
+        return ORC_EINVAL;
+    for (uint64_t s = 0; s < n_seqs; s++)
+        if (set_ids[s] >= h->K)
+            return ORC_ERANGE;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t s = 0; s < (int64_t)n_seqs; s++) {
+        if (h->phi[(size_t)r * h->K + set_ids[s]] != b)
+            continue;
+        for (uint64_t p = offsets[s]; p + h->k <= offsets[s + 1]; p++) {
+            uint64_t code;
+            if (!orc_encode_kmer(chars + p, h->k, &code))
+                continue;
+            uint64_t x = orc_canonical(code, h->k);
+            for (uint32_t j = 0; j < h->eta; j++) {
+                uint64_t pos = orc_position(x, h->ps[(size_t)r * h->eta + j], h->m);
+                orc_atomic_or64(&out[pos / 64], 1ULL << (pos % 64));
+            }
+        }
+    }
+    (void)nthreads;
+    return ORC_OK;
+}
+
 /* Keys r*m + pos_{r,j}(x) of every valid window of every read, in window
  * order (R*eta per window); returns how many there are (at most cap are
  * written). */

@@ -147,7 +147,8 @@ def kmer_queries(seed: int, sets: SeqBatch, n: int, k: int, present_frac: float 
     """n single k-mer queries as k-byte sequences: the first round(n *
     present_frac) are windows at a uniform (set, position) of the inserted
     genomes, the rest uniform random ACGT strings.  Order is shuffled; the
-    'present' mask is kept in meta."""
+    'present' mask and 'source_set' (the sequence a present query was cut
+    from, -1 for random ones) are kept in meta."""
     rng = rng_for(seed)
     n_pres = int(round(n * present_frac))
     lens = sets.lengths().astype(np.int64)
@@ -165,8 +166,11 @@ def kmer_queries(seed: int, sets: SeqBatch, n: int, k: int, present_frac: float 
     present = np.zeros(n, dtype=bool)
     present[:n_pres] = True
     present = present[perm]
+    src = np.full(n, -1, dtype=np.int64)
+    src[:n_pres] = which
+    src = src[perm]
     offsets = np.arange(n + 1, dtype=np.uint64) * np.uint64(k)
-    return SeqBatch(out.reshape(-1), offsets, None, meta=dict(present=present, k=k))
+    return SeqBatch(out.reshape(-1), offsets, None, meta=dict(present=present, source_set=src, k=k))
 
 
 def reads(seed: int, sets: SeqBatch, n: int, *, median_len: int, min_len: int, max_len: int,

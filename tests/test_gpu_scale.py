@@ -2,17 +2,22 @@
 B = 200, R = 5, m = 2^29: an 80 GiB index; 100 000 sets, B = 1 000, R = 6,
 m = 2^27: a 96 GiB index), inserted in the launch configuration bench.py
 times (rambo_insert_seqs, automatic policy: the partitioned insert in scratch
-batches).  The oracle cannot hold these indexes, so it computes rows from
-the inserted sets directly (one pass over every window, Alg. 1):
-  - every row p = 0 mod D of every repetition, compared bit for bit with the
-    device index (D = 256 by default, 64 with RAMBO_SCALE_FULL=1);
-  - every row that a sample of reads and k-mer queries needs, from which it
-    answers them (Sec. 3.2.1, Alg. 2), compared with the device answers
-    (K-bit masks, and ID lists);
+batches).  The oracle cannot hold these indexes, so it checks outputs it can
+compute one by one:
+  - for a sample of sets s: the R cells (r, phi_r(s)) that hold s, built by
+    the oracle from the sets in them alone (Alg. 1 for one cell), compared
+    bit for bit with those columns of the device index (every row);
+  - for the same sets, the membership bit of every sampled read and k-mer
+    query (Sec. 3.2.1, Alg. 2: s is in an answer iff all its R cells pass
+    every valid window), compared with the device masks and ID lists;
 and, on many more reads, the device answers contain every read's source set
-(no false negatives).  RAMBO_SCALE (comma-separated: served, large, mini)
-chooses the workloads; both full-size ones run by default.  Progress lines
-go to gpurun_out/scale_progress.log as the long host steps advance."""
+(no false negatives).  With RAMBO_SCALE_ROWS=1 a slower check also runs: the
+oracle passes over every window of every set once and compares every row
+p = 0 mod D of every repetition, bit for bit, and the full answers of a
+sample of reads (D = 256, 64 with RAMBO_SCALE_FULL=1; 3 to 7 minutes of host
+time).  RAMBO_SCALE (comma-separated: served, large, mini) chooses the
+workloads; both full-size ones run by default.  Progress lines go to
+gpurun_out/scale_progress.log as the long host steps advance."""
 import json
 import os
 import time
@@ -28,6 +33,7 @@ from gpu_util import dev, host_u32
 
 SCALE = [s for s in os.environ.get("RAMBO_SCALE", "served,large").split(",") if s]
 FULL = os.environ.get("RAMBO_SCALE_FULL", "") == "1"
+ROWS = os.environ.get("RAMBO_SCALE_ROWS", "") == "1"
 pytestmark = pytest.mark.gpu
 D = 64 if FULL else 256   # every D-th row of every repetition is compared
 OUT = os.path.join(os.environ.get("GRAFT_REPO_ROOT", os.path.dirname(os.path.dirname(os.path.abspath(__file__)))),
@@ -135,15 +141,88 @@ def workload(request):
     torch.cuda.empty_cache()
 
 
-def test_scale_rows_and_sampled_answers(workload):
-    name, cfg, sets, g, o, rec = workload
+def device_column(g, r, b, chunk_rows=1 << 22):
+    """Bit b of every row of repetition r (the BFU of cell (r, b)) as
+    ceil(m/64) uint64 words, bit p of word p/64."""
+    spw = g.row_bits // 32
+    out = []
+    for p0 in range(0, g.m, chunk_rows):
+        n = min(chunk_rows, g.m - p0)
+        w = g.index_words(r * g.words_per_rep + p0 * spw, n * spw).view(n, spw)[:, b // 32]
+        bits = ((w >> (b % 32)) & 1).to(torch.uint8).cpu().numpy()
+        out.append(np.packbits(bits, bitorder="little"))
+        del w
+    return np.concatenate(out).view(np.uint64)
+
+
+def sampled_reads(name, sets, n_served, n_large):
     if name in ("served", "mini"):
         rq = synth.served_requests(4104, sets, 120)     # about 4 000 reads of 150-5 000 bp
-        n_rd = rq.n if FULL else 200
-        rd = synth.SeqBatch(rq.chars[: int(rq.offsets[n_rd])].copy(), rq.offsets[: n_rd + 1].copy())
-    else:
-        rd = synth.reads(3105, sets, 10_000 if FULL else 1_000, median_len=150, min_len=150, max_len=150,
-                         substr_frac=0.8, read_sub_rate=0.01)
+        n_rd = min(rq.n, n_served)
+        return synth.SeqBatch(rq.chars[: int(rq.offsets[n_rd])].copy(), rq.offsets[: n_rd + 1].copy(),
+                              meta=dict(source_set=rq.meta["source_set"][:n_rd]))
+    return synth.reads(3105, sets, n_large, median_len=150, min_len=150, max_len=150, substr_frac=0.8,
+                       read_sub_rate=0.01)
+
+
+def test_scale_cells_and_member_bits(workload):
+    name, cfg, sets, g, o, rec = workload
+    R, K = cfg["R"], cfg["K"]
+    rd = sampled_reads(name, sets, 4000 if FULL else 1000, 10_000 if FULL else 2_000)
+    q = synth.kmer_queries(3106, sets, 100_000 if FULL else 10_000, cfg["k"])
+    # sampled sets: sources of sampled reads and k-mer queries (answers that
+    # hold them), and sets drawn at random (mostly answers that do not)
+    rng = np.random.default_rng(3107)
+    src_rd, src_q = rd.meta["source_set"], q.meta["source_set"]
+    src = sets.set_ids[np.concatenate([src_rd[src_rd >= 0][:4], src_q[src_q >= 0][:2]])].astype(np.int64)
+    sample = sorted(set(src.tolist()) | set(rng.integers(0, K, size=3).tolist()))
+    phi = o.phi()
+    nthreads = min(os.cpu_count() or 1, 16)
+    m_rd, nk_rd = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    m_rd, nk_rd = host_u32(m_rd), host_u32(nk_rd)
+    id_off, ids, _ = g.query_seqs_ids(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+    id_off, ids = id_off.cpu().numpy(), ids.cpu().numpy()
+    m_q, _ = g.query_seqs(dev(q.offsets, np.int64), dev(q.chars, np.uint8))
+    m_q = host_u32(m_q)
+    codes = g.extract_kmers(dev(q.offsets, np.int64), dev(q.chars, np.uint8))
+    codes = codes[torch.from_numpy(q.offsets[:-1].astype(np.int64)).cuda()].contiguous()
+    m_k = host_u32(g.query_kmers(codes))
+    t = time.time()
+    cells_done = {}
+    n_pos_rd = n_pos_q = 0
+    for s in sample:
+        cells = []
+        for r in range(R):
+            b = int(phi[r, s])
+            if (r, b) not in cells_done:
+                want = o.cell_bits(r, b, sets.set_ids, sets.offsets, sets.chars, nthreads=nthreads)
+                assert np.array_equal(device_column(g, r, b), want), "cell (%d, %d)" % (r, b)
+                cells_done[(r, b)] = want
+            cells.append(cells_done[(r, b)])
+        bit = lambda m: ((m[:, s // 32] >> np.uint32(s % 32)) & 1).astype(bool)
+        want_rd = o.members_from_cells(rd.offsets, rd.chars, cells)
+        assert np.array_equal(bit(m_rd), want_rd), "set %d, reads" % s
+        in_ids = np.array([s in ids[id_off[i]:id_off[i + 1]] for i in range(rd.n)])
+        assert np.array_equal(in_ids, want_rd), "set %d, ID lists" % s
+        want_q = o.members_from_cells(q.offsets, q.chars, cells)
+        assert np.array_equal(bit(m_q), want_q), "set %d, k-mers as reads" % s
+        assert np.array_equal(bit(m_k), want_q), "set %d, k-mer codes" % s
+        n_pos_rd += int(want_rd.sum())
+        n_pos_q += int(want_q.sum())
+        progress("%s: set %d: %d cells equal, member bits equal (%.0f s)" % (name, s, R, time.time() - t))
+    assert n_pos_rd > 0 and n_pos_q > 0
+    for i in range(rd.n):   # ID lists and masks are one answer
+        assert ids[id_off[i]:id_off[i + 1]].tolist() == oracle.mask_to_ids(m_rd[i], K)
+    log(rec, sampled_sets=sample, cells_compared=len(cells_done), cell_bits_compared=len(cells_done) * cfg["m"],
+        member_reads=int(rd.n), member_kmers=int(q.n), positives_reads=n_pos_rd, positives_kmers=n_pos_q,
+        cells_s=round(time.time() - t, 1))
+
+
+def test_scale_rows_and_sampled_answers(workload):
+    name, cfg, sets, g, o, rec = workload
+    if not ROWS:
+        pytest.skip("the full row scan takes minutes of host time: RAMBO_SCALE_ROWS=1 runs it")
+    rd = sampled_reads(name, sets, 4000 if FULL else 200, 10_000 if FULL else 1_000)
     q = synth.kmer_queries(3106, sets, 100_000 if FULL else 10_000, cfg["k"])
     keys = np.unique(np.concatenate([o.window_keys(rd.offsets, rd.chars), o.window_keys(q.offsets, q.chars)]))
     nthreads = min(os.cpu_count() or 1, 16)

@@ -388,6 +388,40 @@ def test_read_answers_from_rows_equal_full_oracle():
         lean.query_seqs_rows(rd.offsets, rd.chars, keys[1:], rows[1:])
 
 
+def test_cell_bits_and_members_equal_full_oracle():
+    # one cell's BFU from the sets it holds equals that filter of the full
+    # oracle, and a set's membership in read answers decided from its R cells
+    # equals its bit in the full oracle's answers (reads with substitutions,
+    # random reads, reads shorter than k and reads with no valid window)
+    cfg = synth.INDEX_TINY
+    sets = synth.config_tiny()
+    full = oracle.OracleIndex(**cfg, seed=2001)
+    full.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    lean = oracle.OracleIndex(**cfg, seed=2001, flags=oracle.FLAG_NO_FILTERS)
+    for r in range(cfg["R"]):
+        for b in range(cfg["B"]):
+            got = lean.cell_bits(r, b, sets.set_ids, sets.offsets, sets.chars, nthreads=4)
+            assert np.array_equal(got, full.bfu_words(r, b)), (r, b)
+    rd = synth.reads(3022, sets, 120, median_len=100, min_len=20, max_len=300, substr_frac=0.7, read_sub_rate=0.01)
+    extra = [b"ACGTN" * 12, b"ACGT" * 5]   # a window broken every 5 bases; shorter than k
+    chars = np.concatenate([rd.chars] + [np.frombuffer(e, np.uint8) for e in extra])
+    offsets = np.concatenate([rd.offsets, rd.offsets[-1] + np.cumsum([len(e) for e in extra])]).astype(np.uint64)
+    want, _ = full.query_seqs(offsets, chars, nthreads=4)
+    phi = lean.phi()
+    n_pos = 0
+    src = rd.meta["source_set"]
+    for s in sorted(set(sets.set_ids[src[src >= 0][:4]].tolist()) | {0, cfg["K"] - 1}):
+        cells = [lean.cell_bits(r, int(phi[r, s]), sets.set_ids, sets.offsets, sets.chars) for r in range(cfg["R"])]
+        got = lean.members_from_cells(offsets, chars, cells)
+        bit = ((want[:, s // 32] >> np.uint32(s % 32)) & 1).astype(bool)
+        assert np.array_equal(got, bit), s
+        assert not got[-2:].any()
+        n_pos += int(got.sum())
+    assert n_pos > 0
+    with pytest.raises(ValueError):
+        lean.cell_bits(cfg["R"], 0, sets.set_ids, sets.offsets, sets.chars)
+
+
 # ------------------------------------------------------------ folding over
 
 @pytest.mark.parametrize("B", [8, 50])
