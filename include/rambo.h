@@ -184,6 +184,29 @@ int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
                          const uint8_t *chars, uint64_t n_chars, uint64_t *id_offsets,
                          uint32_t *ids, uint64_t cap, uint32_t *out_nkmers, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rambo_query_seqs_ids with its per-read state and scan totals in a
+ * fixed array of RAMBO_NOALLOC_SCRATCH_BYTES per GPU, reserved when the
+ * library's code is loaded on that GPU and held until the process ends.
+ * Arguments, answers, overflow and errors as in rambo_query_seqs_ids; the
+ * call allocates nothing.  A batch larger than the array holds (more than
+ * rambo_query_seqs_ids_noalloc_max_reads(h) reads; about 4*(R*S/32+5)
+ * bytes per read) is refused with RAMBO_EINVAL before any work is queued.
+ * Every call on one GPU, from any handle, uses the same array, which keeps
+ * the last call's contents (each call sets up what it reads): calls whose
+ * work may overlap on the GPU (different streams with no dependency, or
+ * several host threads) race on it and give wrong answers, so order them
+ * on one stream or with events.  RAMBO_EHIP if the array's device address
+ * could not be found when the handle was created (rambo_last_error says
+ * why). */
+#define RAMBO_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int rambo_query_seqs_ids_noalloc(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
+                                 const uint8_t *chars, uint64_t n_chars, uint64_t *id_offsets,
+                                 uint32_t *ids, uint64_t cap, uint32_t *out_nkmers,
+                                 hipStream_t stream);
+uint64_t rambo_query_seqs_ids_noalloc_max_reads(const rambo_t *h);
+
 /* ---- support ---------------------------------------------------------- */
 
 /* Canonical code of the k-window starting at every byte (the term

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -57,6 +58,8 @@ struct rambo {
     bool recorded_insert = false;      // an insert was recorded into a graph: index_zero is never trusted again
     ReadQueue rq{};
     uint64_t *scan_part = nullptr;     // tile totals of the ID-list scan (in rq_mem)
+    void *noalloc = nullptr;           // this GPU's scratch of rambo_query_seqs_ids_noalloc
+    std::string noalloc_error;         //   or why it could not be found
     bool rq_recorded = false;          // a captured graph holds rq_mem: retire it instead of freeing it
     std::vector<void *> retired;       // scratch buffers captured graphs may still use; freed by rambo_destroy
     // ordering of the handle's scratch across streams: the last call that
@@ -203,11 +206,11 @@ void launch_query_kmers_t(const rambo *h, const uint64_t *codes, uint64_t n, uin
 
 template <int SW, int R_T, int ETA_T>
 void launch_query_seqs_t(const rambo *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
-                         uint64_t n_chars, uint32_t *out, uint32_t *nk, hipStream_t st)
+                         uint64_t n_chars, uint32_t *out, uint32_t *nk, const ReadQueue &rq, hipStream_t st)
 {
     StageScope sc(h, "k_query_seqs", st);
     hipLaunchKernelGGL((k_query_seqs<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_reads, kWavesPerBlock)),
-                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk, h->rq.G, h->rq.nk);
+                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk, rq.G, rq.nk);
 }
 
 // Row widths of the workloads get kernels with compile-time R and eta (all
@@ -296,8 +299,12 @@ struct QuerySeqsLaunch {
     uint32_t *out;
     uint32_t *nk;
     hipStream_t st;
+    const ReadQueue &rq;   // per-read state, written where out is NULL
     template <int SW, int R_T, int ETA_T>
-    void operator()() const { launch_query_seqs_t<SW, R_T, ETA_T>(h, offsets, n_reads, chars, n_chars, out, nk, st); }
+    void operator()() const
+    {
+        launch_query_seqs_t<SW, R_T, ETA_T>(h, offsets, n_reads, chars, n_chars, out, nk, rq, st);
+    }
 };
 
 // The persistent work-queue launch (k_rq_persist); its per-read state is
@@ -322,6 +329,9 @@ struct QuerySeqsQueueLaunch {
                            n_reads, n_dev, chars, n_chars, h->query_chunk, out, nk);
     }
 };
+
+constexpr int kMaxDevices = 64;
+void *noalloc_scratch(int dev, std::string *err);
 
 uint32_t next_pow2(uint32_t v)
 {
@@ -1133,6 +1143,16 @@ extern "C" int rambo_create(const rambo_config *cfg, rambo_t **out)
         rambo_destroy(h);
         return rc;
     }
+    {
+        // the no-allocation entry point's scratch on this GPU: looked up here,
+        // with the handle's device current; a failure shows in that call
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            h->noalloc = noalloc_scratch(dev, &h->noalloc_error);
+        else
+            h->noalloc_error = "hipGetDevice failed";
+        (void)hipGetLastError();
+    }
     *out = h;
     return RAMBO_OK;
 }
@@ -1345,7 +1365,7 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
     if (!offsets || !out_masks || (n_chars > 0 && !chars))
         return fail(h, RAMBO_EINVAL, "rambo_query_seqs: NULL array");
     if (wave_per_read(h, n_reads, n_chars)) {
-        with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream});
+        with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, out_masks, out_nkmers, stream, h->rq});
         return launch_check(h, "rambo_query_seqs");
     }
     ScratchUse su(h, stream);
@@ -1358,56 +1378,163 @@ extern "C" int rambo_query_seqs(rambo_t *h, const uint64_t *offsets, uint64_t n_
     return launch_check(h, "rambo_query_seqs");
 }
 
+// Alg. 2 with Sec. 3.2.1 per read, then the answers as ID lists, with the
+// per-read state in rq and the scan's tile totals in scan_part (both hold
+// n_reads reads).
+int query_seqs_ids_on(rambo *h, const ReadQueue &rq, uint64_t *scan_part, const uint64_t *offsets,
+                      uint64_t n_reads, const uint8_t *chars, uint64_t n_chars, uint64_t *id_offsets, uint32_t *ids,
+                      uint64_t cap, uint32_t *out_nkmers, hipStream_t stream, const char *what)
+{
+    // group masks and window counts only: the answers stay in the per-read state
+    if (wave_per_read(h, n_reads, n_chars))
+        with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, nullptr, out_nkmers, stream, rq});
+    else
+        launch_read_queue(h, rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, nullptr, out_nkmers, stream);
+    const uint64_t waves = std::min<uint64_t>(n_reads, (uint64_t)h->num_cus * 16);
+    const dim3 grid((uint32_t)div_up(waves, kWavesPerBlock));
+    const size_t lds = (size_t)kWavesPerBlock * h->cfg.R * h->SW * 4;
+    {
+        StageScope sc(h, "k_ids_count", stream);
+        hipLaunchKernelGGL(k_ids_count, grid, dim3(kBlock), lds, stream, h->P, rq, n_reads, h->SW, id_offsets);
+    }
+    const uint64_t nb = div_up(n_reads, kScanTile);
+    {
+        StageScope sc(h, "k_scan64", stream);
+        hipLaunchKernelGGL(k_scan64_tiles, dim3((uint32_t)nb), dim3(256), 0, stream, id_offsets, n_reads, id_offsets,
+                           scan_part);
+        hipLaunchKernelGGL(k_scan64_part, dim3(1), dim3(1024), 0, stream, scan_part, nb, id_offsets, n_reads, cap,
+                           h->err);
+        hipLaunchKernelGGL(k_scan64_add, dim3((uint32_t)div_up(n_reads, 256)), dim3(256), 0, stream, id_offsets,
+                           n_reads, scan_part);
+    }
+    {
+        StageScope sc(h, "k_ids_write", stream);
+        hipLaunchKernelGGL(k_ids_write, grid, dim3(kBlock), lds + (size_t)kWavesPerBlock * kSortCap * 4, stream, h->P,
+                           rq, n_reads, h->SW, id_offsets, ids, cap);
+    }
+    return launch_check(h, what);
+}
+
+int query_seqs_ids_args(rambo *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars, uint64_t n_chars,
+                        const uint64_t *id_offsets, const uint32_t *ids, uint64_t cap, const char *what)
+{
+    if (const int rr = refuse_raw_keys(h, what))
+        return rr;
+    if (!id_offsets || (n_reads > 0 && !offsets) || (n_chars > 0 && !chars) || (cap > 0 && !ids))
+        return fail(h, RAMBO_EINVAL, std::string(what) + ": NULL array");
+    return RAMBO_OK;
+}
+
+// id_offsets[0] = 0 for an empty batch, by a fill kernel (no memset node if
+// recorded into a graph).
+int query_seqs_ids_empty(rambo *h, uint64_t *id_offsets, hipStream_t stream, const char *what)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, stream, reinterpret_cast<uint32_t *>(id_offsets),
+                       (uint64_t)2, 0u);
+    return launch_check(h, what);
+}
+
 extern "C" int rambo_query_seqs_ids(rambo_t *h, const uint64_t *offsets, uint64_t n_reads, const uint8_t *chars,
                                     uint64_t n_chars, uint64_t *id_offsets, uint32_t *ids, uint64_t cap,
                                     uint32_t *out_nkmers, hipStream_t stream)
 {
+    static const char *what = "rambo_query_seqs_ids";
     if (!h)
         return RAMBO_EINVAL;
-    if (const int rr = refuse_raw_keys(h, "rambo_query_seqs_ids"))
-        return rr;
-    if (!id_offsets || (n_reads > 0 && !offsets) || (n_chars > 0 && !chars) || (cap > 0 && !ids))
-        return fail(h, RAMBO_EINVAL, "rambo_query_seqs_ids: NULL array");
-    if (n_reads == 0) {
-        // id_offsets[0] = 0 by a fill kernel (no memset node if recorded)
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, stream, reinterpret_cast<uint32_t *>(id_offsets),
-                           (uint64_t)2, 0u);
-        return launch_check(h, "rambo_query_seqs_ids");
-    }
+    if (const int rc = query_seqs_ids_args(h, offsets, n_reads, chars, n_chars, id_offsets, ids, cap, what))
+        return rc;
+    if (n_reads == 0)
+        return query_seqs_ids_empty(h, id_offsets, stream, what);
     ScratchUse su(h, stream);
     int rc = ensure_read_queue(h, n_reads);
     if (rc)
         return rc;
     if (capturing(stream))
         h->rq_recorded = true;
-    // group masks and window counts only: the answers stay in the per-read state
-    if (wave_per_read(h, n_reads, n_chars))
-        with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, nullptr, out_nkmers, stream});
-    else
-        launch_read_queue(h, h->rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, nullptr, out_nkmers, stream);
-    const uint64_t waves = std::min<uint64_t>(n_reads, (uint64_t)h->num_cus * 16);
-    const dim3 grid((uint32_t)div_up(waves, kWavesPerBlock));
-    const size_t lds = (size_t)kWavesPerBlock * h->cfg.R * h->SW * 4;
-    {
-        StageScope sc(h, "k_ids_count", stream);
-        hipLaunchKernelGGL(k_ids_count, grid, dim3(kBlock), lds, stream, h->P, h->rq, n_reads, h->SW, id_offsets);
+    return query_seqs_ids_on(h, h->rq, h->scan_part, offsets, n_reads, chars, n_chars, id_offsets, ids, cap,
+                             out_nkmers, stream, what);
+}
+
+// ------------------------------------- ID lists without allocating memory
+
+// The per-read state and scan totals of rambo_query_seqs_ids_noalloc: one
+// array per GPU for the life of the process, shared by every handle and
+// call on that GPU.
+namespace {
+
+static __device__ __align__(256) uint8_t scratch[RAMBO_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of this GPU's copy of `scratch` (the array's name is
+// only a host-side stand-in), looked up once per device with that device
+// current; nullptr, with the reason in *err, if the lookup fails.
+void *noalloc_scratch(int dev, std::string *err)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = "device ordinal out of range";
+        return nullptr;
     }
-    const uint64_t nb = div_up(n_reads, kScanTile);
-    {
-        StageScope sc(h, "k_scan64", stream);
-        hipLaunchKernelGGL(k_scan64_tiles, dim3((uint32_t)nb), dim3(256), 0, stream, id_offsets, n_reads, id_offsets,
-                           h->scan_part);
-        hipLaunchKernelGGL(k_scan64_part, dim3(1), dim3(1024), 0, stream, h->scan_part, nb, id_offsets, n_reads, cap,
-                           h->err);
-        hipLaunchKernelGGL(k_scan64_add, dim3((uint32_t)div_up(n_reads, 256)), dim3(256), 0, stream, id_offsets,
-                           n_reads, h->scan_part);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_noalloc_ptr[dev] = ptr;
     }
-    {
-        StageScope sc(h, "k_ids_write", stream);
-        hipLaunchKernelGGL(k_ids_write, grid, dim3(kBlock), lds + (size_t)kWavesPerBlock * kSortCap * 4, stream, h->P, h->rq, n_reads, h->SW, id_offsets, ids,
-                           cap);
+    return g_noalloc_ptr[dev];
+}
+
+// Bytes of the per-read state (rounded to 256) plus the scan's tile totals
+// for n reads.
+uint64_t noalloc_bytes(const rambo *h, uint64_t n)
+{
+    return div_up(read_queue_bytes(h, n), 256) * 256 + 8 * (div_up(n, kScanTile) + 1);
+}
+
+}  // namespace
+
+extern "C" uint64_t rambo_query_seqs_ids_noalloc_max_reads(const rambo_t *h)
+{
+    if (!h)
+        return 0;
+    uint64_t lo = 0, hi = RAMBO_NOALLOC_SCRATCH_BYTES;   // noalloc_bytes(h, lo) fits
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        (noalloc_bytes(h, mid) <= RAMBO_NOALLOC_SCRATCH_BYTES ? lo : hi) = mid;
+        if (lo != mid)
+            hi = mid - 1;
     }
-    return launch_check(h, "rambo_query_seqs_ids");
+    return lo;
+}
+
+extern "C" int rambo_query_seqs_ids_noalloc(rambo_t *h, const uint64_t *offsets, uint64_t n_reads,
+                                            const uint8_t *chars, uint64_t n_chars, uint64_t *id_offsets,
+                                            uint32_t *ids, uint64_t cap, uint32_t *out_nkmers, hipStream_t stream)
+{
+    static const char *what = "rambo_query_seqs_ids_noalloc";
+    if (!h)
+        return RAMBO_EINVAL;
+    if (const int rc = query_seqs_ids_args(h, offsets, n_reads, chars, n_chars, id_offsets, ids, cap, what))
+        return rc;
+    if (!h->noalloc)
+        return fail(h, RAMBO_EHIP, std::string(what) + ": no scratch on this GPU (" + h->noalloc_error + ")");
+    if (n_reads == 0)
+        return query_seqs_ids_empty(h, id_offsets, stream, what);
+    if (noalloc_bytes(h, n_reads) > RAMBO_NOALLOC_SCRATCH_BYTES)
+        return fail(h, RAMBO_EINVAL, std::string(what) + ": " + std::to_string(n_reads) + " reads need " +
+                                         std::to_string(noalloc_bytes(h, n_reads)) + " bytes of scratch, more than " +
+                                         std::to_string((uint64_t)RAMBO_NOALLOC_SCRATCH_BYTES));
+    uint8_t *base = static_cast<uint8_t *>(h->noalloc);
+    const ReadQueue rq = carve_read_queue(h, base, n_reads);
+    uint64_t *scan_part = reinterpret_cast<uint64_t *>(base + div_up(read_queue_bytes(h, n_reads), 256) * 256);
+    return query_seqs_ids_on(h, rq, scan_part, offsets, n_reads, chars, n_chars, id_offsets, ids, cap, out_nkmers,
+                             stream, what);
 }
 
 extern "C" int rambo_fill_counts(rambo_t *h, uint64_t *out, hipStream_t stream)
@@ -1479,7 +1606,7 @@ extern "C" int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint6
         return fail(h, RAMBO_EINVAL, "rambo_query_seqs_plain: NULL array");
     for (uint64_t q = 0; q < n_reads; ++q)
         with_row_words(h, QuerySeqsLaunch{h, offsets + q, 1, chars, n_chars, out_masks + q * h->W,
-                                          out_nkmers ? out_nkmers + q : nullptr, stream});
+                                          out_nkmers ? out_nkmers + q : nullptr, stream, h->rq});
     return launch_check(h, "rambo_query_seqs_plain");
 }
 

@@ -27,6 +27,7 @@ FLAG_IDENTITY_PARTITION = 1
 FLAG_RAW_KEYS = 4   # terms are 64-bit keys (documents and word unigrams) passed as the k-mer codes
 INSERT_AUTO, INSERT_DIRECT, INSERT_PARTITIONED, INSERT_PARTITIONED_WALKER = 0, 1, 2, 3
 QUERY_AUTO, QUERY_WAVE_PER_READ, QUERY_QUEUE = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20   # RAMBO_NOALLOC_SCRATCH_BYTES
 NO_KMER = -1   # UINT64_MAX viewed as int64
 
 MAX_B = 4096
@@ -73,6 +74,11 @@ EXPORTS = {
     "rambo_query_seqs_ids": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                             ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_query_seqs_ids_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                                    ctypes.c_void_p]),
+    "rambo_query_seqs_ids_noalloc_max_reads": (ctypes.c_uint64, [ctypes.c_void_p]),
     "rambo_fill_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_query_kmers_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                ctypes.c_void_p, ctypes.c_void_p]),
@@ -300,6 +306,26 @@ class Rambo:
                 self._check(st, "rambo_query_seqs_ids")
             ids = torch.empty(need, dtype=torch.int32, device=offsets.device)
         raise RamboError(EOVERFLOW, "rambo_query_seqs_ids: capacity")
+
+    def query_seqs_ids_noalloc(self, offsets, chars, id_offsets, ids, nkmers=None, stream=None):
+        """rambo_query_seqs_ids into the caller's buffers, with the library's
+        fixed per-GPU scratch instead of allocated state: id_offsets int64
+        [n+1], ids int32 (its length is the capacity), nkmers int32 [n] or
+        None.  Asynchronous on `stream`; an answer that did not fit shows as
+        EOVERFLOW from sync_status."""
+        n = offsets.numel() - 1
+        if id_offsets.numel() < n + 1:
+            raise ValueError("id_offsets must hold n + 1 entries")
+        if nkmers is not None and nkmers.numel() < n:
+            raise ValueError("nkmers must hold n entries")
+        rc = lib().rambo_query_seqs_ids_noalloc(self._h, _dptr(offsets, _U64, "offsets"), n,
+                                                _dptr(chars, (torch.uint8,), "chars"), chars.numel(),
+                                                _dptr(id_offsets, _U64, "id_offsets"), _dptr(ids, _U32, "ids"),
+                                                ids.numel(), _dptr(nkmers, _U32, "nkmers"), _stream(stream))
+        self._check(rc, "rambo_query_seqs_ids_noalloc")
+
+    def noalloc_max_reads(self) -> int:
+        return int(lib().rambo_query_seqs_ids_noalloc_max_reads(self._h))
 
     def fill_counts(self, stream=None) -> torch.Tensor:
         """Set bits per cell, int64 [R, B] on the device."""

@@ -58,4 +58,6 @@ def test_null_handle_calls(lib):
     assert lib.rambo_insert_kmers(None, None, None, 0, None, 0, None) == rambo.EINVAL
     assert lib.rambo_query_termsets(None, None, 0, None, 0, None, None) == rambo.EINVAL
     assert lib.rambo_sync_status(None, None) == rambo.EINVAL
+    assert lib.rambo_query_seqs_ids_noalloc(None, None, 0, None, 0, None, None, 0, None, None) == rambo.EINVAL
+    assert lib.rambo_query_seqs_ids_noalloc_max_reads(None) == 0
     lib.rambo_destroy(None)
