@@ -5,6 +5,8 @@
   p = (1 - (1 - 1/m)^(eta n))^eta.
 * Lemma 4.1: a query q held by V sets is reported for a set that does not
   hold it with probability (p (1 - 1/B)^V + 1 - (1 - 1/B)^V)^R.
+* The same lemma with p averaged over random partitions, for sets of equal
+  size (the unconditional form, compared with the mean over many seeds).
 * The same lemma conditioned on the realised partition and cell fills (the
   quantity its proof averages): in repetition r, set i's cell passes for
   sure when it also holds one of q's true sets, and otherwise passes with
@@ -46,6 +48,34 @@ def lemma41(p: float, B: int, V: int, R: int) -> float:
     """Lemma 4.1: per-set false-positive probability."""
     miss = (1.0 - 1.0 / B) ** V
     return (p * miss + 1.0 - miss) ** R
+
+
+def cell_fpr_over_partitions(K: int, B: int, V: int, keys_in_cell, m: int, eta: int) -> float:
+    """The Bloom-filter false-positive rate p of the cell that holds a set
+    which does not hold the query, averaged over the random partition (the
+    p of Lemma 4.1 when the V holders of the query lie in other cells):
+    besides the set itself, each of the other K - 1 - V sets falls into its
+    cell with probability 1/B, so the cell holds s = 1 + n sets with
+    n ~ Binomial(K - 1 - V, 1/B); keys_in_cell(s) is the number of distinct
+    keys such a cell holds (a number: that many keys per set), and a cell of
+    N keys has p = (1 - (1 - 1/m)^(eta N))^eta (Sec. 2)."""
+    from scipy.stats import binom
+    n_other = K - 1 - V
+    n = np.arange(n_other + 1, dtype=np.float64)
+    pmf = binom.pmf(n, n_other, 1.0 / B)
+    if callable(keys_in_cell):
+        keys = np.array([float(keys_in_cell(int(x))) for x in 1 + n])
+    else:
+        keys = (1.0 + n) * float(keys_in_cell)
+    fill = -np.expm1(eta * keys * math.log1p(-1.0 / m))
+    return float(np.sum(pmf * fill ** eta))
+
+
+def lemma41_over_partitions(K: int, B: int, V: int, R: int, keys_in_cell, m: int, eta: int) -> float:
+    """Lemma 4.1 with p averaged over the partition as above (repetitions
+    draw independent partitions, so the per-repetition pass probabilities
+    multiply)."""
+    return lemma41(cell_fpr_over_partitions(K, B, V, keys_in_cell, m, eta), B, V, R)
 
 
 def lemma42_bound(p: float, B: int, V: int, R: int, K: int) -> float:
