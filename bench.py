@@ -104,9 +104,14 @@ def insert_rooflines(kernels: dict, n_win: int, n_bases: int, R: int, eta: int, 
     against the bound itself (2 x index + 16 B per target + input)."""
     RE = R * eta
     targets = n_win * RE
-    a_name = "k_bin_codes" if code_input else "k_bin_windows"
+    a_name = "k_bin_codes" if code_input else ("k_bin_pieces" if "k_bin_pieces" in kernels else "k_bin_windows")
     stage_k = {a_name: "%s_hold<%d, %d>" % (a_name, R, eta), "k_bin_regions": "k_bin_regions",
                "k_apply_regions": "k_apply_regions"}
+    if a_name == "k_bin_pieces":
+        stage_k[a_name] = "k_bin_pieces<%d, %d" % (R, eta)
+    # one stage-A launch per scratch batch; stages B and C launch once per
+    # group of coarse buckets in each batch
+    batches = kernels[a_name][1] if a_name in kernels else 1
     tr = measured_traffic(stage_k, workload)
     out = []
     if a_name in kernels:
@@ -121,17 +126,19 @@ def insert_rooflines(kernels: dict, n_win: int, n_bases: int, R: int, eta: int, 
                              tr.get("k_bin_regions"), calls))
     if "k_apply_regions" in kernels:
         ms, calls = kernels["k_apply_regions"]
-        idx = index_bytes * (2 * calls - (1 if fresh_first else 0))
+        idx = index_bytes * (2 * batches - (1 if fresh_first else 0))
         out.append(hbm_entry("k_apply_regions", (targets * 8 + idx) / calls, ms / calls,
                              "8 B record per bit target read + index written once per batch (and read back "
-                             "unless the index was all zero)", tr.get("k_apply_regions"), calls))
+                             "unless the index was all zero); a launch covers one group of regions",
+                             tr.get("k_apply_regions"), calls))
     total_ms = sum(kernels[k][0] for k in (a_name, "k_bin_regions", "k_apply_regions", "k_zero_u32")
                    if k in kernels)
     if total_ms > 0:
         byts = 2 * index_bytes + 16 * targets + (n_win * 8 if code_input else n_bases)
         e = hbm_entry("insert_pipeline", byts, total_ms, "partitioned bound of the whole insert: index read + "
                       "written once, 16 B per bit target, input once")
-        e["batches"] = kernels.get("k_bin_regions", (0, 1))[1]
+        e["batches"] = batches
+        e["groups_per_batch"] = kernels.get("k_bin_regions", (0, batches))[1] // max(1, batches)
         out.append(e)
     return out
 

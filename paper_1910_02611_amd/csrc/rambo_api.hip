@@ -934,7 +934,7 @@ int insert_seqs_pieces(rambo *h, const StageAPieces &AP, const uint32_t *set_ids
         pa.q_begin = q;
         pa.q_end = std::min(q + bp, q_up);
         clear_fill_counters(h, G, stream);
-        { StageScope sc(h, "k_bin_windows", stream);
+        { StageScope sc(h, "k_bin_pieces", stream);
         hipLaunchKernelGGL(AP.fn, dim3(nwg), dim3(kBlockP), AP.lds, stream, h->P, G, pa); }
         launch_stages_bc(h, G, fresh, stream);
         if ((rc = launch_check(h, "rambo_insert_seqs (partitioned)")))
