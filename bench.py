@@ -296,6 +296,13 @@ def section_served(args):
         sample = reqs[:200]
         sids = [srv.submit(o, c) for o, c in sample]
         mixed = [srv.wait(i, len(o) - 1)[0] for i, (o, _) in zip(sids, sample)]
+        res["server"] = srv.stats()
+    # (alone, on the index as it was in the mix: before the streaming inserts)
+    same = True
+    for (o, c), got in zip(sample, mixed):
+        alone, _ = g.query_seqs(to_dev(o, np.int64), to_dev(c, np.uint8))
+        same = same and bool(np.array_equal(alone.cpu().numpy().view(np.uint32), got))
+    with Server(g, max_slots=4, use_graphs=True) as srv:
         # streaming inserts among the queries at a quarter of the saturated
         # rate (Python driver): the same arrivals with and without them
         rate = 0.25 * res["saturated"]["qps"]
@@ -304,11 +311,6 @@ def section_served(args):
         ins = serve.insert_stream(5101, sets, max(1, int(arr[-1] / 0.02)), 0.02, 32, 5000)
         plain = serve.run_open_loop(srv, reqs[:n_ins_req], arr, g.W)
         with_ins = serve.run_open_loop(srv, reqs[:n_ins_req], arr, g.W, inserts=ins)
-        res["server"] = srv.stats()
-    same = True
-    for (o, c), got in zip(sample, mixed):
-        alone, _ = g.query_seqs(to_dev(o, np.int64), to_dev(c, np.uint8))
-        same = same and bool(np.array_equal(alone.cpu().numpy().view(np.uint32), got))
     sat = res["saturated"]
     log("served: saturated %.4g requests/s (%.4g reads/s)" % (sat["qps"], sat["reads_per_s"]))
     for p in res["points"]:

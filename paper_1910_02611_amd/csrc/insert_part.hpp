@@ -62,7 +62,7 @@ struct BinGeom {
 };
 
 __host__ __device__ constexpr size_t lds_bytes_stage_a(uint32_t na) { return kTileA * 12ull + na * 12ull + 64; }
-__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 4ull + nf * 12ull + 64; }
+__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 4ull + nf * 12ull + 64; }   // the smallest stage-B tile
 
 // A target whose run did not fit its slab is set with a global atomic right
 // away; its region is marked so that stage C reads the region back even into
@@ -74,12 +74,14 @@ __device__ __forceinline__ void fallback_or(const Params &P, const BinGeom &G, u
 }
 
 // Exclusive prefix sum of cnt[0..n) into start[0..n) by the whole
-// workgroup; returns the total.  wsum holds kWavesP words of LDS.
+// workgroup of BLK threads; returns the total.  wsum holds BLK / 64 words
+// of LDS.
+template <int BLK = kBlockP>
 __device__ __forceinline__ uint32_t block_exclusive_scan(const uint32_t *cnt, uint32_t *start, uint32_t n,
                                                          uint32_t *wsum)
 {
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-    const uint32_t per = (n + kBlockP - 1) / kBlockP;
+    const uint32_t per = (n + BLK - 1) / BLK;
     const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
     uint32_t s = 0;
     for (uint32_t b = b0; b < b1; ++b)
@@ -96,7 +98,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(const uint32_t *cnt, ui
     __syncthreads();
     uint32_t wbase = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kWavesP; ++w) {
+    for (int w = 0; w < BLK / kWave; ++w) {
         const uint32_t ws = wsum[w];
         wbase += (uint32_t)w < wv ? ws : 0u;
         total += ws;
@@ -119,7 +121,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(const uint32_t *cnt, ui
 // skip it.
 constexpr uint32_t kMaxBucketsPerThread = 8;   // 4096 buckets / 512 threads
 
-template <uint32_t kSlots>
+template <uint32_t kSlots, int BLK = kBlockP>
 struct RunReservationT {
     uint32_t pos[kSlots];
     uint32_t c[kSlots];
@@ -128,7 +130,7 @@ struct RunReservationT {
     {
 #pragma unroll
         for (uint32_t i = 0; i < kSlots; ++i) {
-            const uint32_t b = threadIdx.x + i * kBlockP;
+            const uint32_t b = threadIdx.x + i * BLK;
             c[i] = 0;
             pos[i] = 0;
             if (b < nb) {
@@ -144,7 +146,7 @@ struct RunReservationT {
     {
 #pragma unroll
         for (uint32_t i = 0; i < kSlots; ++i) {
-            const uint32_t b = threadIdx.x + i * kBlockP;
+            const uint32_t b = threadIdx.x + i * BLK;
             if (b >= nb)
                 continue;
             if (c[i] == 0) {
@@ -397,28 +399,36 @@ void k_bin_codes_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64
                                      });
 }
 
-// Stage B: block = (coarse bucket, tile of kTileB slots of its nwg chunks,
-// which lie one after the other).  A slot holds an entry when it is below
-// its chunk's fill count (and is not a sentinel).  The tile's entries stay
-// in registers; the counting atomic gives each its rank inside its region,
-// so after the scan it goes straight to its sorted LDS slot (4 bytes of LDS
-// per entry).
-__global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
+// Stage B: block = (coarse bucket, tile of TILE slots of its nwg chunks,
+// which lie one after the other), BLK threads.  A slot holds an entry when
+// it is below its chunk's fill count (and is not a sentinel).  The tile's
+// entries stay in registers; the counting atomic gives each its rank inside
+// its region, so after the scan it goes straight to its sorted LDS slot (4
+// bytes of LDS per entry).  Larger tiles give longer runs per region, so
+// fewer partly written memory segments.
+template <int BLK, uint32_t TILE>
+__host__ __device__ constexpr size_t lds_bytes_stage_b_t(uint32_t nf)
+{
+    return TILE * 4ull + nf * 12ull + (BLK / kWave) * 4ull;
+}
+
+template <int BLK, uint32_t TILE>
+__global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
 {
     extern __shared__ uint32_t lds[];
-    uint32_t *srt = lds;                // kTileB entries sorted by region
-    uint32_t *cnt = srt + kTileB;       // nf counts (reset by the reservation)
+    uint32_t *srt = lds;                // TILE entries sorted by region
+    uint32_t *cnt = srt + TILE;         // nf counts (reset by the reservation)
     uint32_t *lbase = cnt + G.nf;       // nf first sorted slots
     uint32_t *gbase = lbase + G.nf;     // nf first slab entries of the runs
-    uint32_t *wsum = gbase + G.nf;      // kWavesP
+    uint32_t *wsum = gbase + G.nf;      // BLK / 64
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     const uint32_t c = G.c0 + blockIdx.x / tiles_per_bucket;
     const uint32_t tile = blockIdx.x % tiles_per_bucket;
     const uint64_t span = (uint64_t)G.nwg * G.capA;   // slots of bucket c
-    const uint64_t t0 = (uint64_t)tile * kTileB;
+    const uint64_t t0 = (uint64_t)tile * TILE;
     if (t0 >= span)
         return;
-    const uint32_t n = (uint32_t)min((uint64_t)kTileB, span - t0);
+    const uint32_t n = (uint32_t)min((uint64_t)TILE, span - t0);
     const uint32_t *cfill = G.fillA + (uint64_t)c * G.nwg;
     {
         // leave at once when no chunk holds an entry in [t0, t0 + n)
@@ -431,22 +441,23 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     }
     const uint32_t *src = G.slabA + (uint64_t)c * span + t0;   // 16-byte aligned: capA, t0 are multiples of 4
     const double inv_cap = 1.0 / (double)G.capA;
-    for (uint32_t b = threadIdx.x; b < G.nf; b += kBlockP)
+    for (uint32_t b = threadIdx.x; b < G.nf; b += BLK)
         cnt[b] = 0;
     // unconditional loads (clamped to the last vector) so none waits for
     // another; entries past n are not counted
-    constexpr int kV = kTileB / 4 / kBlockP;
+    constexpr int kV = TILE / 4 / BLK;
+    static_assert(kV * 4 * BLK == (int)TILE, "tile of whole vectors per thread");
     u32x4 v[kV];
     const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
     const uint32_t n4 = (n + 3) / 4;
 #pragma unroll
     for (int i = 0; i < kV; ++i)
-        v[i] = s4[min((uint32_t)(i * kBlockP) + threadIdx.x, n4 - 1)];
+        v[i] = s4[min((uint32_t)(i * BLK) + threadIdx.x, n4 - 1)];
     __syncthreads();
     uint32_t rk[kV * 4];
 #pragma unroll
     for (int i = 0; i < kV; ++i) {
-        const uint32_t j = (uint32_t)(i * kBlockP) + threadIdx.x;
+        const uint32_t j = (uint32_t)(i * BLK) + threadIdx.x;
         const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
         // the vector's chunk (its 4 slots share one: capA is a multiple of 4)
         // and how many of its slots hold entries
@@ -468,10 +479,10 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
         }
     }
     __syncthreads();
-    const uint32_t total = block_exclusive_scan(cnt, lbase, G.nf, wsum);
+    const uint32_t total = block_exclusive_scan<BLK>(cnt, lbase, G.nf, wsum);
     uint32_t *fill = G.fillB + (uint64_t)(c - G.c0) * G.nf;
     uint32_t *slab = G.slabB + (uint64_t)(c - G.c0) * G.nf * G.capB;
-    RunReservation res;
+    RunReservationT<(kMaxBucketsPerThread * kBlockP + BLK - 1) / BLK, BLK> res;
     res.issue(cnt, G.nf, fill);
 #pragma unroll
     for (int i = 0; i < kV; ++i) {
@@ -485,7 +496,7 @@ __global__ __launch_bounds__(kBlockP) void k_bin_regions(Params P, BinGeom G, ui
     __syncthreads();
     const uint32_t maskB = (1u << G.rb) - 1;
     const uint64_t cbit = (uint64_t)c << (G.rb + G.fb);
-    for (uint32_t i = threadIdx.x; i < total; i += kBlockP) {
+    for (uint32_t i = threadIdx.x; i < total; i += BLK) {
         const uint32_t e = srt[i];
         const uint32_t f = e >> G.rb;
         const uint32_t g = gbase[f];

@@ -30,6 +30,8 @@ namespace rambo_dev {
 constexpr uint32_t kPieceLaneWindows = 128;                     // L
 constexpr uint32_t kPieceWindows = kWave * kPieceLaneWindows;   // windows per piece
 constexpr uint32_t kPieceDummy = 64;   // per-lane counters that sort the lanes' invalid targets past the valid ones
+constexpr int kBlockPc = 1024;          // workgroup of the piece kernel (one per CU: 4 waves per SIMD)
+constexpr int kWavesPc = kBlockPc / kWave;
 
 struct PieceArgs {
     const uint32_t *set_ids;
@@ -159,7 +161,7 @@ __device__ __forceinline__ uint32_t piece_round_scan(uint32_t *cnt, uint32_t *lb
 {
     const uint32_t nb = na + kPieceDummy;
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-    const uint32_t per = (nb + kBlockP - 1) / kBlockP;
+    const uint32_t per = (nb + kBlockPc - 1) / kBlockPc;
     const uint32_t b0 = min(threadIdx.x * per, nb), b1 = min(b0 + per, nb);
     uint32_t s = 0;
     for (uint32_t b = b0; b < b1; ++b)
@@ -176,7 +178,7 @@ __device__ __forceinline__ uint32_t piece_round_scan(uint32_t *cnt, uint32_t *lb
     __syncthreads();
     uint32_t wbase = 0;
 #pragma unroll
-    for (int w = 0; w < kWavesP; ++w)
+    for (int w = 0; w < kWavesPc; ++w)
         wbase += (uint32_t)w < wv ? wsum[w] : 0u;
     uint32_t run = wbase + incl - s;
     for (uint32_t b = b0; b < b1; ++b) {
@@ -201,7 +203,7 @@ __device__ __forceinline__ uint32_t piece_round_scan(uint32_t *cnt, uint32_t *lb
 template <int R_T, int ETA_T, int ST>
 __host__ __device__ constexpr uint32_t piece_tile()
 {
-    return (uint32_t)ST * kBlockP * R_T * ETA_T;
+    return (uint32_t)ST * kBlockPc * R_T * ETA_T;
 }
 
 template <int R_T, int ETA_T, int ST>
@@ -217,7 +219,7 @@ __host__ __device__ constexpr size_t lds_bytes_pieces(uint32_t na)
 // number of coarse buckets (shA <= 31), so a target's bucket and entry come
 // from 32-bit arithmetic on its position; otherwise the general 64-bit form.
 template <int R_T, int ETA_T, int ST, bool FAST>
-__global__ __launch_bounds__(kBlockP) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kBlockPc) __attribute__((amdgpu_waves_per_eu(4)))
 void k_bin_pieces(Params P, BinGeom G, PieceArgs A)
 {
     constexpr uint32_t RE = R_T * ETA_T;
@@ -234,7 +236,7 @@ void k_bin_pieces(Params P, BinGeom G, PieceArgs A)
     uint32_t *cnt = reinterpret_cast<uint32_t *>(dst + na);              // na + dummy
     uint32_t *lbase = cnt + na + kPieceDummy;                            // na + dummy
     uint32_t *cur = lbase + na + kPieceDummy;                            // na
-    uint32_t *wsum = cur + na;                                           // kWavesP
+    uint32_t *wsum = cur + na;                                           // kWavesPc
 
     const uint32_t wg = blockIdx.x, nwg = gridDim.x;
     const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
@@ -247,13 +249,13 @@ void k_bin_pieces(Params P, BinGeom G, PieceArgs A)
     const uint64_t nq = qe > A.q_begin ? qe - A.q_begin : 0;
     const uint64_t qa = A.q_begin + nq * wg / nwg, qz = A.q_begin + nq * (wg + 1) / nwg;
 
-    for (uint32_t b = threadIdx.x; b < na + kPieceDummy; b += kBlockP)
+    for (uint32_t b = threadIdx.x; b < na + kPieceDummy; b += kBlockPc)
         cnt[b] = 0;
-    for (uint32_t b = threadIdx.x; b < na; b += kBlockP)
+    for (uint32_t b = threadIdx.x; b < na; b += kBlockPc)
         cur[b] = 0;
     __syncthreads();
 
-    for (uint64_t q0 = qa; q0 < qz; q0 += kWavesP) {
+    for (uint64_t q0 = qa; q0 < qz; q0 += kWavesPc) {
         // the wave's piece: sequence s (the last one whose first piece is <= q)
         const uint64_t q = q0 + wv;
         bool live = q < qz;
@@ -346,7 +348,7 @@ void k_bin_pieces(Params P, BinGeom G, PieceArgs A)
                 sbk[pos] = (uint16_t)b;
             }
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < total_valid; i += kBlockP) {
+            for (uint32_t i = threadIdx.x; i < total_valid; i += kBlockPc) {
                 const uint32_t b = sbk[i];
                 const uint32_t e = srt[i];
                 const uint64_t d = dst[b];
@@ -362,7 +364,7 @@ void k_bin_pieces(Params P, BinGeom G, PieceArgs A)
         }
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < na; b += kBlockP)
+    for (uint32_t b = threadIdx.x; b < na; b += kBlockPc)
         G.fillA[(uint64_t)b * nwg + wg] = cur[b];
 }
 

@@ -4,7 +4,12 @@
     python -m paper_1910_02611_amd.profsum traffic --fetch DIR/F_counter_collection.csv \
         --write DIR/W_counter_collection.csv --copy-bytes N --title T --cmd C --json OUT.json > OUT.md
     python -m paper_1910_02611_amd.profsum counters DIR/X_counter_collection.csv --title T --cmd C > OUT.md
+    python -m paper_1910_02611_amd.profsum requests --rd DIR/R_counter_collection.csv \
+        --wr DIR/W_counter_collection.csv --title T --cmd C --json OUT.json > OUT.md
 
+The requests summary prices the L2-to-memory request counts by their size
+(32, 64 and 128 bytes); FETCH_SIZE's own formula counts 128-byte reads as
+64 bytes on this GPU, so a streaming read shows at half its size there.
 The traffic summary turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, each
 from its own run) into bytes per launch, each scaled by what the counter
 reads for the streaming copy kernel of known size (N bytes read and N bytes
@@ -100,6 +105,49 @@ def traffic_md(t: dict, title: str, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+RD_SIZES = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64), ("TCC_EA0_RDREQ_128B_sum", 128))
+
+
+def requests(rd_csv: str, wr_csv: str) -> dict:
+    """Bytes per launch from the L2-to-memory request counts split by size:
+    read = 32 n_32B + 64 n_64B + 128 n_128B (TCC_EA0_RDREQ_*_sum, one run),
+    written = 32 (n - n_64B) + 64 n_64B (TCC_EA0_WRREQ_sum and _64B_sum,
+    another run).  Requests of other sizes show as the difference between
+    TCC_EA0_RDREQ_sum and the three sized counts (reported, not priced)."""
+    rd = {c: per_dispatch(rd_csv, c) for c, _ in RD_SIZES}
+    rd_all = per_dispatch(rd_csv, "TCC_EA0_RDREQ_sum")
+    wr_all = per_dispatch(wr_csv, "TCC_EA0_WRREQ_sum")
+    wr64 = per_dispatch(wr_csv, "TCC_EA0_WRREQ_64B_sum")
+    mean = lambda v: sum(v) / len(v) if v else 0.0
+    kernels = {}
+    for k in sorted(set(rd_all) | set(wr_all)):
+        n = {c: mean(rd[c].get(k, [])) for c, _ in RD_SIZES}
+        rb = sum(n[c] * size for c, size in RD_SIZES)
+        other = mean(rd_all.get(k, [])) - sum(n.values())
+        w_all, w64 = mean(wr_all.get(k, [])), mean(wr64.get(k, []))
+        wb = 32.0 * (w_all - w64) + 64.0 * w64
+        kernels[k] = {"dispatches": max(len(rd_all.get(k, [])), len(wr_all.get(k, []))),
+                      "rd_32B": n[RD_SIZES[0][0]], "rd_64B": n[RD_SIZES[1][0]], "rd_128B": n[RD_SIZES[2][0]],
+                      "rd_other": other, "wr": w_all, "wr_64B": w64,
+                      "fetch_bytes": rb, "write_bytes": wb, "bytes": rb + wb}
+    return {"method": "request counts by size", "kernel_source_sha256": kernel_source_hash(), "kernels": kernels}
+
+
+def requests_md(t: dict, title: str, cmd: str, probes: str) -> str:
+    out = ["# %s" % title, "", "Commands (from the repository root on the MI355X host):", "", "```", cmd, "```", "",
+           "Bytes from the L2-to-memory request counters split by size (read = 32 n32 + 64 n64 + 128 n128; "
+           "written = 32 (n - n64) + 64 n64), per launch, averaged over the launches of each kernel.  " + probes,
+           "", "Kernel source hash: `%s`" % t["kernel_source_sha256"], "",
+           "| kernel | launches | rd 32B | rd 64B | rd 128B | rd other | HBM read / launch | wr | wr 64B | "
+           "HBM written / launch | total / launch |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, v in t["kernels"].items():
+        out.append("| %s | %d | %.4g | %.4g | %.4g | %.3g | %.4g B | %.4g | %.4g | %.4g B | %.4g B |" % (
+            k, v["dispatches"], v["rd_32B"], v["rd_64B"], v["rd_128B"], v["rd_other"], v["fetch_bytes"], v["wr"],
+            v["wr_64B"], v["write_bytes"], v["bytes"]))
+    return "\n".join(out) + "\n"
+
+
 def counters_md(path: str, title: str, cmd: str) -> str:
     """Per-kernel averages of every counter in a counter-collection CSV."""
     names = sorted({r["Counter_Name"] for r in csv.DictReader(open(path))})
@@ -144,6 +192,13 @@ def main():
     b.add_argument("--title", required=True)
     b.add_argument("--cmd", required=True)
     b.add_argument("--json")
+    d = sub.add_parser("requests")
+    d.add_argument("--rd", required=True)
+    d.add_argument("--wr", required=True)
+    d.add_argument("--title", required=True)
+    d.add_argument("--cmd", required=True)
+    d.add_argument("--probes", default="")
+    d.add_argument("--json")
     c = sub.add_parser("counters")
     c.add_argument("counter_csv")
     c.add_argument("--title", required=True)
@@ -153,6 +208,12 @@ def main():
         sys.stdout.write(trace_md(args.stats_csv, args.title, args.cmd))
     elif args.what == "counters":
         sys.stdout.write(counters_md(args.counter_csv, args.title, args.cmd))
+    elif args.what == "requests":
+        t = requests(args.rd, args.wr)
+        if args.json:
+            with open(args.json, "w") as f:
+                json.dump(t, f, indent=1)
+        sys.stdout.write(requests_md(t, args.title, args.cmd, args.probes))
     else:
         t = traffic(args.fetch, args.write, args.copy_bytes)
         if args.json:
