@@ -289,7 +289,7 @@ def section_served(args):
     log("served: insert %.1f ms (%.3g inserts/s)" % (ph["insert"], n_win / (ph["insert"] / 1e3)))
     log_rooflines(roofs)
     loads = [float(x) for x in args.serve_loads.split(",")]
-    with Server(g, max_slots=4, use_graphs=True) as srv:
+    with Server(g, max_slots=args.serve_slots, use_graphs=args.serve_graphs) as srv:
         serve.saturated(srv, reqs[: min(300, len(reqs))], g.W)   # warm-up
         res = serve.sweep_native(srv, batch, loads)
         # answers in the mix equal the same requests answered alone
@@ -302,7 +302,7 @@ def section_served(args):
     for (o, c), got in zip(sample, mixed):
         alone, _ = g.query_seqs(to_dev(o, np.int64), to_dev(c, np.uint8))
         same = same and bool(np.array_equal(alone.cpu().numpy().view(np.uint32), got))
-    with Server(g, max_slots=4, use_graphs=True) as srv:
+    with Server(g, max_slots=args.serve_slots, use_graphs=args.serve_graphs) as srv:
         # streaming inserts among the queries at a quarter of the saturated
         # rate (Python driver): the same arrivals with and without them
         rate = 0.25 * res["saturated"]["qps"]
@@ -314,16 +314,26 @@ def section_served(args):
     sat = res["saturated"]
     log("served: saturated %.4g requests/s (%.4g reads/s)" % (sat["qps"], sat["reads_per_s"]))
     for p in res["points"]:
-        log("  load %.2f: offered %.4g/s achieved %.4g/s  p50 %.3f ms  p99 %.3f ms"
-            % (p["load"], p["offered_qps"], p["qps"], p["p50_ms"], p["p99_ms"]))
+        log("  load %.2f: offered %.4g/s achieved %.4g/s  p50 %.3f ms  p99 %.3f ms (host queue p99 %.3f, "
+            "service p99 %.3f; cgroup CPU throttling %s; worker max loop gap %.0f us, enqueue %.0f us, "
+            "query %.0f us)"
+            % (p["load"], p["offered_qps"], p["qps"], p["p50_ms"], p["p99_ms"], p["queue_p99_ms"],
+               p["service_p99_ms"], "%d periods, %.1f ms" % (p["cpu_throttled_periods"], p["cpu_throttled_ms"])
+               if "cpu_throttled_ms" in p else "n/a", p["worker_max_loop_gap_us"], p["worker_max_enqueue_us"],
+               p["worker_max_query_us"]))
     log("served: 200 requests alone == in the mix: %s; with %d streaming inserts at 25%% load: query p50 %.3f "
         "p99 %.3f ms (without: %.3f / %.3f)" % (same, with_ins["inserts"], with_ins["p50_ms"], with_ins["p99_ms"],
                                                 plain["p50_ms"], plain["p99_ms"]))
-    keep = ("load", "offered_qps", "qps", "reads_per_s", "p50_ms", "p99_ms", "mean_ms")
+    keep = ("load", "offered_qps", "qps", "reads_per_s", "p50_ms", "p99_ms", "mean_ms", "queue_p50_ms",
+            "queue_p99_ms", "service_p99_ms", "cpu_throttled_periods", "cpu_throttled_ms", "worker_max_loop_gap_us",
+            "worker_max_enqueue_us", "worker_max_query_us")
     out = {
         "workload": "served: K=10000 genome sets (~6.6e9 31-mers), B=200, R=5, m=2^29, eta=2 (80 GiB); requests "
                     "of U{1..64} reads, log-uniform 150-5000 bp, 70%% set substrings; %d requests per load point, "
-                    "Poisson arrivals, native open-loop driver, 4 slots, graph replay" % len(reqs),
+                    "Poisson arrivals, native open-loop driver, %d slots, %s" % (
+                        len(reqs), args.serve_slots,
+                        "fixed slot buffers, graph replay" if args.serve_graphs else
+                        "batches admitted by device bytes from a 1 GiB pool"),
         "K": cfg["K"], "B": cfg["B"], "R": cfg["R"], "m": cfg["m"], "eta": cfg["eta"],
         "inserts": n_win, "index_bytes": g.index_bytes,
         "insert_ms": ph["insert"], "inserts_per_s": n_win / (ph["insert"] / 1e3),
@@ -331,7 +341,7 @@ def section_served(args):
         "kernel_launches": {k: v[1] for k, v in kernels.items()},
         "rooflines": sorted(roofs, key=lambda r: -r["ms"] * r.get("launches", 1)),
         "saturated": {k: sat[k] for k in ("qps", "reads_per_s", "p50_ms", "p99_ms")},
-        "points": [{k: p[k] for k in keep} for p in res["points"]],
+        "points": [{k: p[k] for k in keep if k in p} for p in res["points"]],
         "alone_equals_mixed": {"requests": len(sample), "identical": same},
         "with_inserts": dict({k: with_ins[k] for k in ("qps", "p50_ms", "p99_ms", "inserts", "insert_bases",
                                                        "insert_p50_ms", "insert_p99_ms")},
@@ -752,6 +762,9 @@ def main():
     ap.add_argument("--oracle-reads", type=int, default=5_000, help="reads of the batched section's oracle sample")
     ap.add_argument("--serve-requests", type=int, default=10_000, help="requests per serving load point")
     ap.add_argument("--serve-loads", default="0.1,0.25,0.4,0.55,0.7,0.85,1.0,1.2")
+    ap.add_argument("--serve-slots", type=int, default=4, help="batches in flight at once")
+    ap.add_argument("--serve-graphs", action="store_true",
+                    help="fixed per-slot buffers and graph replay instead of batches sized from a device pool")
     ap.add_argument("--cpu-insert-budget", type=int, default=60_000_000)
     ap.add_argument("--cpu-query-seconds", type=float, default=15.0)
     ap.add_argument("--insert-policy", type=int, default=0,

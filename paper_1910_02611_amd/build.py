@@ -9,7 +9,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librambo.so")
 SOURCES = ["rambo_api.hip", "roofline.hip"]
-HEADERS = ["device.hpp", "kernels.hpp", "insert_part.hpp", "query_queue.hpp", "query_ids.hpp", "serve.hpp"]
+HEADERS = ["device.hpp", "kernels.hpp", "insert_part.hpp", "insert_pieces.hpp", "query_queue.hpp", "query_ids.hpp",
+           "serve.hpp", "serve_pool.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++20", "-fPIC", "-shared", "-Wall",

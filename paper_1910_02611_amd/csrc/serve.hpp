@@ -6,7 +6,13 @@
 // batch of queued requests (host pack into pinned staging, one H2D copy of
 // offsets and one of bytes, the three work-queue kernels - replayed from a
 // hipGraph captured per slot when asked - and one D2H copy of masks and
-// counts), then sleeps briefly only when there is nothing to do.  An insert
+// counts), then sleeps briefly only when there is nothing to do.
+//
+// Device memory: without graphs, every batch takes a region of one device
+// pool sized for what it actually holds (its reads' bytes and offsets, K-bit
+// masks and per-read state), so a batch is admitted when the pool has room
+// for it and frees the room when it retires; with graphs, every slot owns
+// fixed buffers for the largest batch (a replayed graph keeps its pointers).  An insert
 // request is a barrier in the FIFO: batches stop at it, it runs once every
 // earlier batch has finished, and later requests wait for it, so answers are
 // those of running the requests one by one in submission order.
@@ -21,6 +27,7 @@
 #include <unordered_map>
 
 #include "rambo_serve.h"
+#include "serve_pool.hpp"
 
 namespace {
 
@@ -31,7 +38,7 @@ struct ServeRequest {
     uint64_t n_reads = 0;
     std::vector<uint64_t> offsets;   // rebased to 0
     std::vector<uint8_t> chars;
-    Clock::time_point t_submit, t_done;
+    Clock::time_point t_submit, t_start, t_done;   // submitted, its batch's work enqueued, answered
     std::vector<uint32_t> masks;     // n_reads * W
     std::vector<uint32_t> nk;        // n_reads
     bool done = false;
@@ -46,16 +53,19 @@ struct ServeSlot {
     void *dmem = nullptr;            // device: header+offsets, bytes, masks, counts, queue state
     uint64_t *d_hdr = nullptr;       // [0] = reads, [1..] = offsets
     uint8_t *d_chars = nullptr;
-    uint32_t *d_masks = nullptr;
-    uint32_t *d_nk = nullptr;
+    uint32_t *d_masks = nullptr;     // device addresses of h_masks, h_nk: the kernels
+    uint32_t *d_nk = nullptr;        //   write the answers straight to host memory
     ReadQueue rq{};
     void *hmem = nullptr;            // pinned host: header+offsets, bytes, masks, counts
+    uint8_t *hmem_dev = nullptr;     //   the same memory as the device addresses it
     uint64_t *h_hdr = nullptr;
     uint8_t *h_chars = nullptr;
     uint32_t *h_masks = nullptr;
     uint32_t *h_nk = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t region = rambo_pool::kNone;   // the batch's region of the device pool (pool mode)
+    uint64_t region_bytes = 0;
     bool busy = false;
     uint64_t n_reads = 0;
     std::vector<std::shared_ptr<ServeRequest>> reqs;
@@ -78,17 +88,34 @@ struct rambo_server {
     uint32_t inject_failures = 0;     // test hook: batches to fail on the host before they launch
     void *ins_mem = nullptr;          // device staging of insert requests (grown on demand)
     uint64_t ins_cap = 0;
+    bool by_bytes = false;            // batches take regions of the pool (no graphs)
+    void *pool_mem = nullptr;         // the pool's device memory (mem_budget bytes)
+    rambo_pool::Pool pool;            // guarded by mu
+    uint64_t mem_waits = 0;           // queued queries that waited for pool room
+    int64_t last_waiter = -1;
+    // worker timing (microseconds, maxima since the last reset): between two
+    // passes of its loop, one batch's enqueue (copies and launches), one
+    // completion query
+    double max_loop_gap_us = 0, max_enqueue_us = 0, max_query_us = 0;
+    bool worker_idle = false;
     int device = 0;
     bool timing_before = false;
 };
 
 namespace {
 
-uint64_t slot_device_bytes(const rambo *h, const rambo_serve_config &c)
+// Copy n_hdr and n_chr 16-byte words from mapped host memory to the
+// batch's header and bytes on the device.
+__global__ __launch_bounds__(kBlock) void k_pull_batch(const u32x4 *hdr_src, const u32x4 *chr_src, u32x4 *hdr_dst,
+                                                       u32x4 *chr_dst, uint64_t n_hdr, uint64_t n_chr)
 {
-    const uint64_t R = c.max_batch_reads;
-    return div_up(8 * (R + 2), 256) * 256 + div_up(c.max_batch_bytes, 256) * 256 +
-           div_up(4ull * R * h->W, 256) * 256 + div_up(4 * R, 256) * 256 + read_queue_bytes(h, R);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n_hdr + n_chr; i += stride) {
+        if (i < n_hdr)
+            hdr_dst[i] = hdr_src[i];
+        else
+            chr_dst[i - n_hdr] = chr_src[i - n_hdr];
+    }
 }
 
 void free_slot(ServeSlot &s)
@@ -108,40 +135,53 @@ void free_slot(ServeSlot &s)
     s = ServeSlot{};
 }
 
-int init_slot(rambo *h, const rambo_serve_config &c, ServeSlot &s)
+// Point slot s's device buffers at mem (laid out as batch_layout for
+// n_reads reads and n_bytes bytes).
+void place_slot(const rambo *h, ServeSlot &s, void *mem, uint64_t n_reads, uint64_t n_bytes)
+{
+    const rambo_pool::BatchLayout l = rambo_pool::batch_layout(n_reads, n_bytes, read_queue_bytes(h, n_reads));
+    uint8_t *d = static_cast<uint8_t *>(mem);
+    s.d_hdr = reinterpret_cast<uint64_t *>(d + l.hdr);
+    s.d_chars = d + l.chars;
+    s.rq = carve_read_queue(h, d + l.state, n_reads);
+}
+
+uint64_t batch_device_bytes(const rambo *h, uint64_t n_reads, uint64_t n_bytes)
+{
+    return rambo_pool::batch_layout(n_reads, n_bytes, read_queue_bytes(h, n_reads)).total;
+}
+
+int init_slot(rambo *h, const rambo_serve_config &c, ServeSlot &s, bool own_buffers)
 {
     const uint64_t R = c.max_batch_reads;
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&s.dmem, slot_device_bytes(h, c)) != hipSuccess) {
+        (own_buffers && hipMalloc(&s.dmem, batch_device_bytes(h, R, c.max_batch_bytes)) != hipSuccess)) {
         (void)hipGetLastError();
         return RAMBO_ENOMEM;
     }
-    uint8_t *d = static_cast<uint8_t *>(s.dmem);
-    s.d_hdr = reinterpret_cast<uint64_t *>(d);
-    d += div_up(8 * (R + 2), 256) * 256;
-    s.d_chars = d;
-    d += div_up(c.max_batch_bytes, 256) * 256;
-    s.d_masks = reinterpret_cast<uint32_t *>(d);
-    d += div_up(4ull * R * h->W, 256) * 256;
-    s.d_nk = reinterpret_cast<uint32_t *>(d);
-    d += div_up(4 * R, 256) * 256;
-    s.rq = carve_read_queue(h, d, R);
-    const uint64_t hb = 8 * (R + 2) + c.max_batch_bytes + 4ull * R * h->W + 4 * R + 64;
-    if (hipHostMalloc(&s.hmem, hb, hipHostMallocDefault) != hipSuccess) {
+    // header and bytes 256-aligned (the device pulls them in 16-byte words)
+    const uint64_t o_chars = div_up(8 * (R + 2), 256) * 256, o_masks = o_chars + div_up(c.max_batch_bytes, 256) * 256;
+    const uint64_t hb = o_masks + 4ull * R * h->W + 4 * R + 64;
+    void *dev = nullptr;
+    if (hipHostMalloc(&s.hmem, hb, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(&dev, s.hmem, 0) != hipSuccess) {
         (void)hipGetLastError();
         return RAMBO_ENOMEM;
     }
+    s.hmem_dev = static_cast<uint8_t *>(dev);
     uint8_t *p = static_cast<uint8_t *>(s.hmem);
     s.h_hdr = reinterpret_cast<uint64_t *>(p);
-    p += 8 * (R + 2);
-    s.h_chars = p;
-    p += c.max_batch_bytes;
-    p = reinterpret_cast<uint8_t *>(div_up(reinterpret_cast<uintptr_t>(p), 16) * 16);
+    s.h_chars = p + o_chars;
+    p += o_masks;
     s.h_masks = reinterpret_cast<uint32_t *>(p);
     p += 4ull * R * h->W;
     s.h_nk = reinterpret_cast<uint32_t *>(p);
-    if (c.use_graphs) {
+    s.d_masks = reinterpret_cast<uint32_t *>(s.hmem_dev + o_masks);
+    s.d_nk = reinterpret_cast<uint32_t *>(s.hmem_dev + o_masks + 4ull * R * h->W);
+    if (own_buffers)
+        place_slot(h, s, s.dmem, R, c.max_batch_bytes);
+    if (own_buffers && c.use_graphs) {
         // the three kernels with the read count taken from device memory
         if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return RAMBO_EHIP;
@@ -154,6 +194,16 @@ int init_slot(rambo *h, const rambo_serve_config &c, ServeSlot &s)
         }
     }
     return RAMBO_OK;
+}
+
+// Give slot s's pool region back (pool mode; the caller holds mu).
+void release_region(rambo_server *sv, ServeSlot &s)
+{
+    if (s.region != rambo_pool::kNone) {
+        sv->pool.release(s.region, s.region_bytes);
+        s.region = rambo_pool::kNone;
+        s.region_bytes = 0;
+    }
 }
 
 // Hand every request of slot s back with `status` (a failed batch: no
@@ -172,6 +222,7 @@ void fail_batch(rambo_server *sv, ServeSlot &s, int status)
         }
         sv->n_failed += 1;
         sv->n_requests += s.reqs.size();
+        release_region(sv, s);
     }
     sv->cv_done.notify_all();
     s.reqs.clear();
@@ -187,17 +238,38 @@ bool start_batch(rambo_server *sv, ServeSlot &s)
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         uint64_t reads = 0, bytes = 0;
-        while (!sv->queue.empty()) {
-            const auto &r = sv->queue.front();
-            if (r->insert)
-                break;
-            const uint64_t rb = r->offsets.back();
-            if (reads + r->n_reads > c.max_batch_reads || bytes + rb > c.max_batch_bytes)
-                break;
-            reads += r->n_reads;
-            bytes += rb;
-            s.reqs.push_back(r);
+        // pool mode: the largest region free now bounds the batch
+        const uint64_t room = sv->by_bytes ? sv->pool.largest_free() : ~0ull;
+        const auto at = [&](size_t i) {
+            const auto &r = sv->queue[i];
+            return rambo_pool::Queued{r->insert, r->n_reads, r->offsets.back()};
+        };
+        const auto need = [&](uint64_t n, uint64_t b) { return sv->by_bytes ? batch_device_bytes(sv->h, n, b) : 0; };
+        // a batch takes at most an equal share of the pool past its first
+        // request, so that every slot can run one
+        const uint64_t share = sv->by_bytes ? sv->pool.size() / sv->slots.size() : ~0ull;
+        const size_t take = rambo_pool::batch_take(sv->queue.size(), at, need, c.max_batch_reads, c.max_batch_bytes,
+                                                   room, share, reads, bytes);
+        if (take == 0 && !sv->queue.empty() && !sv->queue.front()->insert &&
+            sv->queue.front()->id != sv->last_waiter) {
+            ++sv->mem_waits;   // admitted when a running batch frees its region
+            sv->last_waiter = sv->queue.front()->id;
+        }
+        for (size_t i = 0; i < take; ++i) {
+            s.reqs.push_back(sv->queue.front());
             sv->queue.pop_front();
+        }
+        if (sv->by_bytes && !s.reqs.empty()) {
+            s.region_bytes = batch_device_bytes(sv->h, reads, bytes);
+            s.region = sv->pool.alloc(s.region_bytes);   // fits: at most the largest free region
+            if (s.region == rambo_pool::kNone) {
+                for (auto it = s.reqs.rbegin(); it != s.reqs.rend(); ++it)
+                    sv->queue.push_front(*it);
+                s.reqs.clear();
+                s.region_bytes = 0;
+                return false;
+            }
+            place_slot(sv->h, s, static_cast<uint8_t *>(sv->pool_mem) + s.region, reads, bytes);
         }
     }
     if (s.reqs.empty())
@@ -221,11 +293,21 @@ bool start_batch(rambo_server *sv, ServeSlot &s)
             injected = true;
         }
     }
+    const auto t_enq = Clock::now();
     hipError_t e = injected ? hipErrorUnknown : hipSuccess;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s.d_hdr, s.h_hdr, 8 * (reads + 2), hipMemcpyHostToDevice, s.stream);
-    if (e == hipSuccess && bytes)
-        e = hipMemcpyAsync(s.d_chars, s.h_chars, bytes, hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess) {
+        // header and bytes pulled from the mapped pinned staging by a kernel
+        // on the slot's stream, and the answers written back to it by the
+        // query kernels: no copy-engine transfers (the enqueue of one of a
+        // few hundred KB has been seen to block for 5-10 ms now and then)
+        const uint64_t n_hdr = div_up(8 * (reads + 2), 16), n_chr = div_up(bytes, 16);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(div_up(n_hdr + n_chr, kBlock), 1024);
+        hipLaunchKernelGGL(k_pull_batch, dim3(grid), dim3(kBlock), 0, s.stream,
+                           reinterpret_cast<const u32x4 *>(s.hmem_dev),
+                           reinterpret_cast<const u32x4 *>(s.hmem_dev + (s.h_chars - static_cast<uint8_t *>(s.hmem))),
+                           reinterpret_cast<u32x4 *>(s.d_hdr), reinterpret_cast<u32x4 *>(s.d_chars), n_hdr, n_chr);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         if (s.exec)
             e = hipGraphLaunch(s.exec, s.stream);
@@ -236,11 +318,15 @@ bool start_batch(rambo_server *sv, ServeSlot &s)
         }
     }
     if (e == hipSuccess)
-        e = hipMemcpyAsync(s.h_masks, s.d_masks, 4ull * reads * sv->h->W, hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s.h_nk, s.d_nk, 4 * reads, hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess)
         e = hipEventRecord(s.done_ev, s.stream);
+    if (e == hipSuccess) {
+        const auto t = Clock::now();
+        for (const auto &r : s.reqs)
+            r->t_start = t;
+        const double us = std::chrono::duration<double, std::micro>(t - t_enq).count();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->max_enqueue_us = std::max(sv->max_enqueue_us, us);
+    }
     if (e != hipSuccess) {
         if (!injected)
             (void)hipGetLastError();
@@ -273,6 +359,7 @@ void finish_batch(rambo_server *sv, ServeSlot &s)
         sv->n_batches += 1;
         sv->n_requests += s.reqs.size();
         sv->n_reads += s.n_reads;
+        release_region(sv, s);
     }
     sv->cv_done.notify_all();
     s.reqs.clear();
@@ -329,12 +416,32 @@ void finish_insert(rambo_server *sv, const std::shared_ptr<ServeRequest> &r)
 void serve_loop(rambo_server *sv)
 {
     (void)hipSetDevice(sv->device);   // the current device is per thread
+    auto t_pass = Clock::now();
     for (;;) {
         bool progress = false, any_busy = false;
+        {
+            const auto t = Clock::now();
+            const double gap = std::chrono::duration<double, std::micro>(t - t_pass).count();
+            t_pass = t;
+            bool waited;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                waited = sv->worker_idle;   // a gap spent blocked on an empty queue is not a stall
+                sv->worker_idle = false;
+                if (!waited)
+                    sv->max_loop_gap_us = std::max(sv->max_loop_gap_us, gap);
+            }
+        }
         for (ServeSlot &s : sv->slots) {
             if (!s.busy)
                 continue;
+            const auto t_q = Clock::now();
             const hipError_t q = hipEventQuery(s.done_ev);
+            {
+                const double us = std::chrono::duration<double, std::micro>(Clock::now() - t_q).count();
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->max_query_us = std::max(sv->max_query_us, us);
+            }
             if (q == hipSuccess) {
                 finish_batch(sv, s);
                 progress = true;
@@ -376,6 +483,7 @@ void serve_loop(rambo_server *sv)
             sv->cv_work.wait_for(lk, std::chrono::microseconds(20));
         } else {
             sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+            sv->worker_idle = true;
         }
     }
 }
@@ -400,25 +508,41 @@ extern "C" int rambo_serve_create(rambo_t *h, const rambo_serve_config *cfg_in, 
         c.max_batch_reads = 8192;
     if (c.max_slots > 16 || c.max_batch_reads > (1u << 24) || c.max_batch_bytes > (1ull << 34))
         return fail(h, RAMBO_EINVAL, "rambo_serve_create: configuration out of range");
-    const uint64_t per_slot = slot_device_bytes(h, c);
-    const uint64_t n_slots = std::min<uint64_t>(c.max_slots, c.mem_budget / per_slot);
+    // with graphs, every slot holds buffers for the largest batch; without,
+    // the batches share one pool of mem_budget bytes
+    const bool by_bytes = !c.use_graphs;
+    const uint64_t per_slot = batch_device_bytes(h, c.max_batch_reads, c.max_batch_bytes);
+    // (either way the budget must hold one batch of the largest size)
+    const uint64_t n_slots = by_bytes ? (c.mem_budget >= per_slot ? c.max_slots : 0)
+                                      : std::min<uint64_t>(c.max_slots, c.mem_budget / per_slot);
     if (n_slots == 0)
-        return fail(h, RAMBO_ENOMEM, "rambo_serve_create: budget holds no slot");
+        return fail(h, RAMBO_ENOMEM, "rambo_serve_create: budget holds no batch of the largest size");
     auto *sv = new (std::nothrow) rambo_server();
     if (!sv)
         return RAMBO_ENOMEM;
     sv->h = h;
     sv->cfg = c;
+    sv->by_bytes = by_bytes;
+    if (by_bytes) {
+        if (hipMalloc(&sv->pool_mem, c.mem_budget) != hipSuccess) {
+            (void)hipGetLastError();
+            delete sv;
+            return fail(h, RAMBO_ENOMEM, "rambo_serve_create: pool allocation failed");
+        }
+        sv->pool.reset(c.mem_budget);
+    }
     sv->slots.resize(n_slots);
     (void)hipGetDevice(&sv->device);
     const bool timing = h->timing;
     sv->timing_before = timing;
     h->timing = false;   // no timing events inside captured graphs or from the worker
     for (ServeSlot &s : sv->slots) {
-        const int rc = init_slot(h, c, s);
+        const int rc = init_slot(h, c, s, !by_bytes);
         if (rc) {
             for (ServeSlot &t : sv->slots)
                 free_slot(t);
+            if (sv->pool_mem)
+                (void)hipFree(sv->pool_mem);
             delete sv;
             h->timing = timing;
             return fail(h, rc, "rambo_serve_create: slot set-up failed");
@@ -448,6 +572,8 @@ extern "C" void rambo_serve_destroy(rambo_server_t *sv)
     }
     if (sv->ins_mem)
         (void)hipFree(sv->ins_mem);
+    if (sv->pool_mem)
+        (void)hipFree(sv->pool_mem);
     sv->h->timing = sv->timing_before;
     --sv->h->servers;
     delete sv;
@@ -461,6 +587,8 @@ extern "C" int64_t rambo_serve_submit(rambo_server_t *sv, const uint64_t *offset
     const uint64_t b0 = offsets[0], b1 = offsets[n_reads];
     if (b1 < b0 || n_reads > sv->cfg.max_batch_reads || b1 - b0 > sv->cfg.max_batch_bytes || (b1 > b0 && !chars))
         return RAMBO_EINVAL;
+    if (sv->by_bytes && batch_device_bytes(sv->h, n_reads, b1 - b0) > sv->pool.size())
+        return RAMBO_EINVAL;   // would never fit the pool
     auto r = std::make_shared<ServeRequest>();
     r->n_reads = n_reads;
     r->offsets.resize(n_reads + 1);
@@ -511,8 +639,12 @@ extern "C" int64_t rambo_serve_submit_insert(rambo_server_t *sv, const uint32_t 
     return r->id;
 }
 
-extern "C" int rambo_serve_wait(rambo_server_t *sv, int64_t id, uint32_t *masks, uint32_t *nkmers,
-                                double *latency_ms, int64_t timeout_us)
+namespace {
+
+// rambo_serve_wait, also giving the time from submission to the enqueue of
+// the request's batch (queue_ms, if not NULL).
+int wait_request(rambo_server_t *sv, int64_t id, uint32_t *masks, uint32_t *nkmers, double *latency_ms,
+                 double *queue_ms, int64_t timeout_us)
 {
     if (!sv)
         return RAMBO_EINVAL;
@@ -536,12 +668,23 @@ extern "C" int rambo_serve_wait(rambo_server_t *sv, int64_t id, uint32_t *masks,
         std::memcpy(nkmers, r->nk.data(), r->nk.size() * 4);
     if (latency_ms)
         *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    if (queue_ms)
+        *queue_ms = r->t_start >= r->t_submit
+                        ? std::chrono::duration<double, std::milli>(r->t_start - r->t_submit).count() : 0.0;
     return r->status;
+}
+
+}  // namespace
+
+extern "C" int rambo_serve_wait(rambo_server_t *sv, int64_t id, uint32_t *masks, uint32_t *nkmers,
+                                double *latency_ms, int64_t timeout_us)
+{
+    return wait_request(sv, id, masks, nkmers, latency_ms, nullptr, timeout_us);
 }
 
 extern "C" int rambo_serve_replay(rambo_server_t *sv, uint64_t n_req, const uint64_t *req_reads,
                                   const uint64_t *read_offsets, const uint8_t *chars, const double *arrival_s,
-                                  double *latency_ms, uint64_t *checksum)
+                                  double *latency_ms, double *queue_ms, uint64_t *checksum)
 {
     if (!sv || !req_reads || !read_offsets || !arrival_s || !latency_ms)
         return RAMBO_EINVAL;
@@ -595,10 +738,12 @@ extern "C" int rambo_serve_replay(rambo_server_t *sv, uint64_t n_req, const uint
         const uint64_t n = req_reads[i + 1] - req_reads[i];
         masks.resize(n * W);
         nk.resize(n);
-        double ms = 0;
-        if ((rc = rambo_serve_wait(sv, id, masks.data(), nk.data(), &ms, -1)))
+        double ms = 0, qms = 0;
+        if ((rc = wait_request(sv, id, masks.data(), nk.data(), &ms, &qms, -1)))
             break;
         latency_ms[i] = ms + lag[i];
+        if (queue_ms)
+            queue_ms[i] = qms + lag[i];
         for (uint32_t v : masks)
             sum = sum * 1000003u + v;
     }
@@ -631,5 +776,46 @@ extern "C" int rambo_serve_stats(rambo_server_t *sv, uint64_t *batches, uint64_t
         *reads = sv->n_reads;
     if (slots)
         *slots = (uint32_t)sv->slots.size();
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_serve_worker_stats(rambo_server_t *sv, double *max_loop_gap_us, double *max_enqueue_us,
+                                        double *max_query_us, int reset)
+{
+    if (!sv)
+        return RAMBO_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (max_loop_gap_us)
+        *max_loop_gap_us = sv->max_loop_gap_us;
+    if (max_enqueue_us)
+        *max_enqueue_us = sv->max_enqueue_us;
+    if (max_query_us)
+        *max_query_us = sv->max_query_us;
+    if (reset)
+        sv->max_loop_gap_us = sv->max_enqueue_us = sv->max_query_us = 0;
+    return RAMBO_OK;
+}
+
+extern "C" uint64_t rambo_serve_batch_bytes(const rambo_t *h, uint64_t n_reads, uint64_t n_bytes)
+{
+    return h ? batch_device_bytes(h, n_reads, n_bytes) : 0;
+}
+
+extern "C" int rambo_serve_mem_stats(rambo_server_t *sv, uint64_t *budget, uint64_t *in_use, uint64_t *peak,
+                                     uint64_t *waits)
+{
+    if (!sv)
+        return RAMBO_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const uint64_t fixed = sv->by_bytes ? 0 : batch_device_bytes(sv->h, sv->cfg.max_batch_reads,
+                                                                  sv->cfg.max_batch_bytes) * sv->slots.size();
+    if (budget)
+        *budget = sv->by_bytes ? sv->pool.size() : fixed;
+    if (in_use)
+        *in_use = sv->by_bytes ? sv->pool.used() : fixed;
+    if (peak)
+        *peak = sv->by_bytes ? sv->pool.peak() : fixed;
+    if (waits)
+        *waits = sv->mem_waits;
     return RAMBO_OK;
 }

@@ -114,7 +114,7 @@ EXPORTS = {
     "rambo_serve_submit_insert": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_uint64, ctypes.c_void_p]),
     "rambo_serve_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
-                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "rambo_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
@@ -122,6 +122,13 @@ EXPORTS = {
     "rambo_serve_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(ctypes.c_uint32)]),
+    "rambo_serve_worker_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                                ctypes.c_int]),
+    "rambo_serve_batch_bytes": (ctypes.c_uint64, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
+    "rambo_serve_mem_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 
@@ -490,11 +497,12 @@ class Server:
             raise RamboError(rc, "rambo_serve_wait")
         return masks, nk, lat.value
 
-    def replay(self, req_reads, read_offsets, chars, arrival_s):
+    def replay(self, req_reads, read_offsets, chars, arrival_s, with_queue=False):
         """Native open-loop drive (rambo_serve_replay): request i = reads
         req_reads[i] .. req_reads[i+1]-1 of the host CSR (read_offsets,
         chars), submitted at arrival_s[i] seconds.  Returns (latencies in ms,
-        answer checksum)."""
+        answer checksum), and with with_queue the host-queue part of each
+        latency (ms) as a third item."""
         import numpy as np
         rr = np.ascontiguousarray(req_reads, dtype=np.uint64)
         off = np.ascontiguousarray(read_offsets, dtype=np.uint64)
@@ -502,12 +510,22 @@ class Server:
         arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
         n = rr.size - 1
         lat = np.zeros(n, dtype=np.float64)
+        qms = np.zeros(n, dtype=np.float64)
         ck = ctypes.c_uint64()
         rc = lib().rambo_serve_replay(self._s, n, rr.ctypes.data, off.ctypes.data, ch.ctypes.data, arr.ctypes.data,
-                                      lat.ctypes.data, ctypes.byref(ck))
+                                      lat.ctypes.data, qms.ctypes.data, ctypes.byref(ck))
         if rc != OK:
             raise RamboError(rc, "rambo_serve_replay")
-        return lat, ck.value
+        return (lat, ck.value, qms) if with_queue else (lat, ck.value)
+
+    def worker_stats(self, reset: bool = False) -> dict:
+        """Worker-thread maxima in microseconds: loop gap, batch enqueue,
+        completion query (rambo_serve_worker_stats)."""
+        g, e, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().rambo_serve_worker_stats(self._s, ctypes.byref(g), ctypes.byref(e), ctypes.byref(q), int(reset))
+        if rc != OK:
+            raise RamboError(rc, "rambo_serve_worker_stats")
+        return {"max_loop_gap_us": g.value, "max_enqueue_us": e.value, "max_query_us": q.value}
 
     def inject_failures(self, n_batches: int):
         """Test hook: the next n_batches batches fail before launch (their
@@ -520,4 +538,7 @@ class Server:
         b, q, r = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         sl = ctypes.c_uint32()
         lib().rambo_serve_stats(self._s, ctypes.byref(b), ctypes.byref(q), ctypes.byref(r), ctypes.byref(sl))
-        return {"batches": b.value, "requests": q.value, "reads": r.value, "slots": sl.value}
+        bud, use, pk, wt = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        lib().rambo_serve_mem_stats(self._s, ctypes.byref(bud), ctypes.byref(use), ctypes.byref(pk), ctypes.byref(wt))
+        return {"batches": b.value, "requests": q.value, "reads": r.value, "slots": sl.value,
+                "mem_budget": bud.value, "mem_in_use": use.value, "mem_peak": pk.value, "mem_waits": wt.value}

@@ -92,14 +92,40 @@ def run_native(server: rambo.Server, batch: synth.SeqBatch, arrivals: np.ndarray
     requests of a served_requests batch submitted at their arrival times
     from a native thread, no Python between the requests."""
     ro = batch.meta["request_offsets"]
+    server.worker_stats(reset=True)
+    thr0 = cpu_throttling()
     t0 = time.perf_counter()
-    lat, check = server.replay(ro, batch.offsets, batch.chars, arrivals)
+    lat, check, qms = server.replay(ro, batch.offsets, batch.chars, arrivals, with_queue=True)
     span = time.perf_counter() - t0
+    thr1 = cpu_throttling()
     n = ro.size - 1
     reads = int(ro[-1] - ro[0])
-    return dict(requests=n, reads=reads, seconds=span, qps=n / span, reads_per_s=reads / span,
-                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                mean_ms=float(lat.mean()), checksum=int(check))
+    out = dict(requests=n, reads=reads, seconds=span, qps=n / span, reads_per_s=reads / span,
+               p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+               mean_ms=float(lat.mean()), checksum=int(check),
+               queue_p50_ms=float(np.percentile(qms, 50)), queue_p99_ms=float(np.percentile(qms, 99)),
+               service_p99_ms=float(np.percentile(lat - qms, 99)))
+    if thr0 is not None and thr1 is not None:
+        out["cpu_throttled_periods"] = thr1[0] - thr0[0]
+        out["cpu_throttled_ms"] = (thr1[1] - thr0[1]) / 1e3
+    out.update({"worker_" + k: v for k, v in server.worker_stats().items()})
+    return out
+
+
+def cpu_throttling():
+    """(periods throttled, microseconds throttled) of this process's cgroup
+    CPU quota so far (cpu.stat of cgroup v2, else v1), or None where
+    neither is readable."""
+    for path, key, scale in (("/sys/fs/cgroup/cpu.stat", "throttled_usec", 1),
+                             ("/sys/fs/cgroup/cpu/cpu.stat", "throttled_time", 1000),
+                             ("/sys/fs/cgroup/cpu,cpuacct/cpu.stat", "throttled_time", 1000)):
+        try:
+            with open(path) as f:
+                kv = dict(line.split() for line in f if line.strip())
+            return int(kv.get("nr_throttled", 0)), int(kv.get(key, 0)) // scale
+        except (OSError, ValueError):
+            continue
+    return None
 
 
 def sweep_native(server: rambo.Server, batch: synth.SeqBatch, fractions, seed: int = 5004) -> dict:

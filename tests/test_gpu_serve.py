@@ -126,8 +126,27 @@ def test_errors(served):
             srv.submit(np.array([0, 5000], np.uint64), np.zeros(5000, np.uint8))
         with pytest.raises(rb.RamboError):   # unknown id
             srv.wait(12345, 1, timeout_us=0)
-    with pytest.raises(rb.RamboError):        # budget too small for one slot
-        rb.Server(g, mem_budget=1024)
+    for graphs in (False, True):
+        with pytest.raises(rb.RamboError):    # budget too small for one batch of the largest size
+            rb.Server(g, mem_budget=1024, use_graphs=graphs)
+
+
+def test_admission_by_device_bytes(served):
+    # a pool that holds about one batch of the largest size: batches are
+    # sized by what their requests hold, so several small ones run at once,
+    # and requests wait in the queue for room; answers stay the oracle's
+    g, reqs, want = served
+    # room for one batch of 64 reads and 128 KiB (the largest request is
+    # 96 KB), so at most a few single-request batches at once for 16 slots
+    budget = rb.lib().rambo_serve_batch_bytes(g._h, 64, 128 << 10)
+    assert budget > 0
+    with rb.Server(g, max_slots=16, mem_budget=budget, max_batch_reads=64, max_batch_bytes=128 << 10) as srv:
+        m = mixed(srv, reqs)
+        st = srv.stats()
+    check(m, want)
+    assert st["mem_budget"] == budget // 256 * 256
+    assert 0 < st["mem_peak"] <= st["mem_budget"] and st["mem_in_use"] == 0
+    assert st["mem_waits"] > 0 and st["batches"] > 1
 
 
 @pytest.mark.parametrize("use_graphs", [False, True])
@@ -202,9 +221,9 @@ def test_native_replay_driver(served):
         want.append(o.query_seqs(off, ch, nthreads=8)[0])
     with rb.Server(g, max_slots=3, use_graphs=True) as srv:
         for arrivals in (np.zeros(ro.size - 1), synth.poisson_arrivals(7, ro.size - 1, 2000.0)):
-            lat, ck = srv.replay(ro, batch.offsets, batch.chars, arrivals)
+            lat, ck, qms = srv.replay(ro, batch.offsets, batch.chars, arrivals, with_queue=True)
             assert ck == _checksum(want)
-            assert (lat > 0).all()
+            assert (lat > 0).all() and (qms >= 0).all() and (qms <= lat).all()
         bad = ro.copy()
         bad[1] = bad[0]            # a request without reads
         with pytest.raises(rb.RamboError):
