@@ -154,6 +154,43 @@ def query_kmers_roofline(kernels, n_q, R, eta, S, W, workload):
                      calls)
 
 
+def tune_insert(g, insert, tag: str, args, reps: int = 2) -> dict | None:
+    """The insert autotuner's pick for this workload (applied to g), or None
+    with --no-tune-insert."""
+    if args.no_tune_insert:
+        return None
+    from paper_1910_02611_amd import autotune
+    t = time.time()
+    r = autotune.tune_insert(g, insert, tag, use_cache=False, reps=reps)
+    log("%s: insert tiles %s (automatic %s): %.1f ms vs %.1f ms automatic (%d shapes, %.1f s)"
+        % (tag, r["effective"], r["automatic"], r["seconds"] * 1e3, r["automatic_seconds"] * 1e3,
+           len(r.get("sweep", [])), time.time() - t))
+    return {k: v for k, v in r.items() if k != "cached"}
+
+
+def time_insert_graph(g, insert, reps: int = 3) -> dict:
+    """clear + insert recorded as one hipGraph and replayed, against the
+    eager calls: best replay time, and whether the replayed index equals the
+    eager one (digest of per-cell fills and sampled words)."""
+    import torch
+    from paper_1910_02611_amd import autotune
+    g.clear()
+    insert()
+    torch.cuda.synchronize()
+    ref = autotune.index_digest(g)
+
+    def step():
+        g.clear()
+        insert()
+
+    graph = autotune.capture(step)
+    t = autotune.time_graph(graph, reps)
+    got = autotune.index_digest(g)
+    same = bool(torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1]))
+    del graph
+    return {"replay_ms": t * 1e3, "identical": same}
+
+
 # ------------------------------------------------------------------ timing
 
 def time_steps(g, insert, query, steps: int, warmup: int):
@@ -228,6 +265,7 @@ def section_large(args):
     def query():
         state["r"] = g.query_seqs_ids(off, ch, ids=ids, nkmers=nk)
 
+    tuning = tune_insert(g, lambda: g.insert_seqs(*dsets), "large", args, reps=1)
     wall, ph, kernels = time_steps(g, lambda: g.insert_seqs(*dsets), query, args.steps, args.warmup)
     if g.sync_status() != 0:
         raise SystemExit("device error flag set (large)")
@@ -250,6 +288,7 @@ def section_large(args):
         "kernel_launches": {k: v[1] for k, v in kernels.items()},
         "rooflines": sorted(roofs, key=lambda r: -r["ms"] * r.get("launches", 1)),
         "answer_sets_hist_0_to_10plus": np.bincount(np.minimum(sizes, 10), minlength=11).tolist(),
+        "insert_tuning": tuning,
     }
     log("large: step %.1f ms: clear %.2f, insert %.1f ms (%.3g inserts/s), ID-list query %.2f ms (%.3g k-mer "
         "queries/s, %.3g reads/s)" % (res["ms_per_step"], ph["clear"], ph["insert"], res["inserts_per_s"],
@@ -374,6 +413,7 @@ def section_mid(args):
     codes = g.extract_kmers(qoff, qchars)[qoff[:-1]].contiguous()
     del qchars
     out = torch.empty((q.n, g.W), dtype=torch.int32, device="cuda")
+    tuning = tune_insert(g, lambda: g.insert_seqs(*dsets), "mid", args)
     wall, ph, kernels = time_steps(g, lambda: g.insert_seqs(*dsets), lambda: g.query_kmers(codes, out=out),
                                    args.steps, args.warmup)
     if g.sync_status() != 0:
@@ -390,10 +430,14 @@ def section_mid(args):
         "inserts_per_s": n_win / (ph["insert"] / 1e3), "k_mer_queries_per_s": q.n / (ph["query"] / 1e3),
         "kernel_ms": {k: v[0] for k, v in kernels.items()},
         "rooflines": roofs,
+        "insert_tuning": tuning,
     }
     log("mid: step %.2f ms: insert %.2f ms (%.3g inserts/s), query %.3f ms (%.3g queries/s)"
         % (res["ms_per_step"], ph["insert"], res["inserts_per_s"], ph["query"], res["k_mer_queries_per_s"]))
     log_rooflines(roofs)
+    res["insert_graph"] = time_insert_graph(g, lambda: g.insert_seqs(*dsets))
+    log("mid: clear + insert as one captured graph: %.2f ms per replay (eager insert %.2f ms), index identical %s"
+        % (res["insert_graph"]["replay_ms"], ph["insert"], res["insert_graph"]["identical"]))
     if not args.no_measured_ceilings:
         res["measured_ceilings"] = measured_ceilings(g.index_bytes, S, R * eta, res["k_mer_queries_per_s"],
                                                      kernels)
@@ -767,6 +811,8 @@ def main():
                     help="fixed per-slot buffers and graph replay instead of batches sized from a device pool")
     ap.add_argument("--cpu-insert-budget", type=int, default=60_000_000)
     ap.add_argument("--cpu-query-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune-insert", action="store_true",
+                    help="keep the automatic insert tiles instead of autotuning them on the large and mid inserts")
     ap.add_argument("--insert-policy", type=int, default=0,
                     help="rambo_set_insert_policy mode for the large, served and mid indexes (0 = automatic)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,

@@ -246,6 +246,36 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
 #define RAMBO_INSERT_PARTITIONED_WALKER 3
 int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
 
+/* Tile shapes of the partitioned insert (the index bits are the same for
+ * every choice; an autotuner picks them).  0 leaves a field automatic.
+ *   steps:        windows each lane hashes per round of the piece stage A,
+ *                 1 or 2 (automatic: 2 for R <= 5, 1 for R = 6; more steps
+ *                 give longer runs per coarse bucket but need more registers)
+ *   stage_b_tile: slab entries per stage-B tile, 8192, 16384 or 32768
+ *                 (automatic: about 16 entries per region, as LDS allows)
+ *   groups:       groups of coarse buckets that stages B and C run over,
+ *                 1, 2, 4 or 8 (automatic: the fewest that need the fewest
+ *                 scratch batches; slab B holds one group's regions)
+ *   fine_bits:    log2 of the 2^19-bit regions per coarse bucket, 8 to 12
+ *                 (automatic: about 1024 coarse buckets); must leave at most
+ *                 4096 coarse buckets, else RAMBO_EINVAL
+ * Values outside these sets give RAMBO_EINVAL; a stage-B tile whose LDS
+ * does not fit the regions of a coarse bucket, and more groups than coarse
+ * buckets, fall back to what fits (rambo_get_insert_tiles shows what is
+ * used).  A change releases the insert scratch (as rambo_set_insert_policy
+ * does), and applies from the next insert. */
+typedef struct rambo_insert_tiles {
+    uint32_t steps;
+    uint32_t stage_b_tile;
+    uint32_t groups;
+    uint32_t fine_bits;
+} rambo_insert_tiles;
+int rambo_set_insert_tiles(rambo_t *h, const rambo_insert_tiles *tiles);
+
+/* The shapes the partitioned insert uses now (after its last scratch
+ * sizing): every field filled in. */
+int rambo_get_insert_tiles(rambo_t *h, rambo_insert_tiles *out);
+
 /* How rambo_query_seqs and rambo_query_seqs_ids schedule a batch of reads
  * (the answers are the same either way): WAVE_PER_READ runs one wavefront
  * per read; QUEUE splits the reads into work items of chunk_bytes bytes that

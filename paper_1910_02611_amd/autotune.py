@@ -1,11 +1,14 @@
-"""Tile autotuner for the batched query launches.
+"""Tile autotuner for the batched query launches and the partitioned insert.
 
-Sweeps the work-queue shape of rambo_query_seqs (bytes per work item,
-persistent waves per compute unit) on a representative batch, times every
-candidate with HIP events on the current stream, keeps the fastest, and
-caches the choice in a JSON file keyed by device and index shape, so a later
-run (or the serving loop) starts from it.  Every candidate computes the same
-answers; the sweep checks that too.
+Queries: sweeps the work-queue shape of rambo_query_seqs (bytes per work
+item, persistent waves per compute unit) on a representative batch.
+Inserts: tunes the partitioned insert's tile shapes (rambo_set_insert_tiles:
+stage-A steps per round, stage-B tile, groups of coarse buckets of stages B
+and C, regions per coarse bucket) one at a time from the automatic choice,
+on the real insert.  Every candidate is timed with HIP events on the current
+stream, the fastest is kept and cached in a JSON file keyed by device, index
+shape and workload tag, so a later run starts from it.  Every candidate
+computes the same answers or index bits; the sweeps check that too.
 """
 from __future__ import annotations
 
@@ -135,6 +138,100 @@ def tune_query_seqs(g: rb.Rambo, offsets, chars, tag: str = "reads", use_cache: 
             best = sweep[-1]
     g.set_query_policy(best["mode"], best["chunk"], best["waves_per_cu"])
     choice = dict(best)
+    cache[key] = choice
+    if use_cache:
+        _store(cache)
+    return dict(choice, cached=False, sweep=sweep)
+
+
+def index_digest(g: rb.Rambo, samples: int = 64, words: int = 4096):
+    """Per-cell set-bit counts and `samples` spread chunks of index words: a
+    cheap stand-in for the whole index when comparing two inserts."""
+    fills = g.fill_counts().cpu()
+    total = g.index_bytes // 4
+    step = max(words, total // samples)
+    chunks = [g.index_words(o, min(words, total - o)).cpu() for o in range(0, total, step)]
+    return fills, torch.cat(chunks)
+
+
+def time_insert(g: rb.Rambo, insert, reps: int = 2) -> float:
+    """Best of reps, in seconds, of clear + insert() on torch's current stream
+    (the clear is outside the timed region)."""
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        g.clear()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        insert()
+        e.record(stream)
+        e.synchronize()
+        best = min(best, s.elapsed_time(e) / 1e3)
+    return best
+
+
+INSERT_KNOBS = {
+    "steps": (1, 2),
+    "stage_b_tile": (8192, 16384, 32768),
+    "groups": (1, 2, 4, 8),
+}
+
+
+def tune_insert(g: rb.Rambo, insert, tag: str, use_cache: bool = True, reps: int = 2, fine_bits_span: int = 1):
+    """Pick and apply the fastest tile shapes of the partitioned insert for
+    this workload: start from the automatic shapes, then try the values of
+    one knob at a time (steps, stage-B tile, regions per coarse bucket
+    within fine_bits_span of the automatic value, groups), keeping a value
+    when it is faster.  insert() must insert the workload into g (cleared
+    before each timing).  Returns the choice, its time and the sweep."""
+    key = _key(g, "insert|" + tag)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        c = cache[key]
+        g.set_insert_tiles(**c["tiles"])
+        return dict(c, cached=True)
+    g.set_insert_tiles()
+    base = g.insert_tiles()
+    cur = {"steps": 0, "stage_b_tile": 0, "groups": 0, "fine_bits": 0}
+    best_t = time_insert(g, insert, reps)
+    ref = index_digest(g)
+    sweep = [{"tiles": dict(cur), "effective": g.insert_tiles(), "seconds": best_t}]
+    knobs = dict(INSERT_KNOBS)
+    knobs["fine_bits"] = tuple(f for f in range(base["fine_bits"] - fine_bits_span, base["fine_bits"] + fine_bits_span + 1)
+                               if 8 <= f <= 12)
+    # shapes already timed, as the library resolves them (the groups that
+    # an automatic choice resolves to are known once an insert has run)
+    def resolved(tiles, eff):
+        return (eff["steps"], eff["stage_b_tile"], eff["fine_bits"], tiles["groups"] or auto_groups[eff["fine_bits"]])
+
+    auto_groups = {base["fine_bits"]: sweep[0]["effective"]["groups"]}
+    seen = {resolved(cur, sweep[0]["effective"])}
+    for name in ("steps", "stage_b_tile", "fine_bits", "groups"):
+        for v in knobs[name]:
+            trial = dict(cur, **{name: v})
+            try:
+                g.set_insert_tiles(**trial)
+            except rb.RamboError:
+                continue   # not possible for this index (LDS or bucket limits)
+            eff = g.insert_tiles()
+            if trial["groups"] == 0 and eff["fine_bits"] not in auto_groups:
+                auto_groups[eff["fine_bits"]] = -eff["fine_bits"]   # not known yet: a shape of its own
+            key = resolved(trial, eff)
+            if key in seen:
+                continue
+            seen.add(key)
+            t = time_insert(g, insert, reps)
+            fills, words = index_digest(g)
+            if not (torch.equal(fills, ref[0]) and torch.equal(words, ref[1])):
+                raise RuntimeError("insert tiles %s changed the index" % trial)
+            sweep.append({"tiles": dict(trial), "effective": g.insert_tiles(), "seconds": t})
+            if trial["groups"] == 0:
+                auto_groups[sweep[-1]["effective"]["fine_bits"]] = sweep[-1]["effective"]["groups"]
+            if t < best_t:
+                best_t, cur = t, trial
+    g.set_insert_tiles(**cur)
+    choice = {"tiles": cur, "effective": g.insert_tiles(), "seconds": best_t, "automatic": base,
+              "automatic_seconds": sweep[0]["seconds"]}
     cache[key] = choice
     if use_cache:
         _store(cache)

@@ -39,6 +39,7 @@ struct rambo {
     // partitioned insertion
     int insert_mode = RAMBO_INSERT_AUTO;
     uint64_t scratch_limit = 0;      // 0: chosen at first use
+    rambo_insert_tiles tiles{};      // requested tile shapes of the partitioned insert (0 = automatic)
     bool part_ok = false;            // geometry supports the partitioned path
     BinGeom bin{};
     uint64_t bin_targets = 0;        // targets per batch the scratch holds
@@ -603,8 +604,14 @@ struct StageB {
     size_t lds;
 };
 
-StageB stage_b(const BinGeom &G)
+StageB stage_b(const BinGeom &G, uint32_t want = 0)
 {
+    if (want == 32768 && lds_bytes_stage_b_t<1024, 32768>(G.nf) <= kMaxLds)
+        return {k_bin_regions<1024, 32768>, 1024, 32768, lds_bytes_stage_b_t<1024, 32768>(G.nf)};
+    if (want == 16384 && lds_bytes_stage_b_t<1024, 16384>(G.nf) <= kMaxLds)
+        return {k_bin_regions<1024, 16384>, 1024, 16384, lds_bytes_stage_b_t<1024, 16384>(G.nf)};
+    if (want == kTileB)
+        return {k_bin_regions<kBlockP, kTileB>, kBlockP, kTileB, lds_bytes_stage_b_t<kBlockP, kTileB>(G.nf)};
     if (G.nf >= 2048 && lds_bytes_stage_b_t<1024, 32768>(G.nf) <= kMaxLds)
         return {k_bin_regions<1024, 32768>, 1024, 32768, lds_bytes_stage_b_t<1024, 32768>(G.nf)};
     if (G.nf >= 1024 && lds_bytes_stage_b_t<1024, 16384>(G.nf) <= kMaxLds)
@@ -622,6 +629,8 @@ void plan_partition(rambo *h)
     G.fb = bits > G.rb + 10 + 8 ? bits - G.rb - 10 : 8;
     if (G.fb > 12)
         G.fb = 12;
+    if (h->tiles.fine_bits)
+        G.fb = h->tiles.fine_bits;
     G.nf = 1u << G.fb;
     const uint64_t na = div_up(total_bits, 1ull << (G.rb + G.fb));
     G.na = (uint32_t)na;
@@ -667,11 +676,16 @@ StageAPieces stage_a_pieces(const rambo *h)
     const bool fast = h->P.m_log2 > 0 && h->P.m_log2 <= 32 && shA <= 31 && rep_bits % (1ull << shA) == 0 &&
                       h->P.S_log2 <= shA;
     if (h->cfg.eta == 2 && G.na <= kMaxCoarse) {
-        switch (h->cfg.R) {
-        case 3: return make_pieces<3, 2, 2>(G.na, fast);
-        case 4: return make_pieces<4, 2, 2>(G.na, fast);
-        case 5: return make_pieces<5, 2, 2>(G.na, fast);
-        case 6: return make_pieces<6, 2, 1>(G.na, fast);
+        const uint32_t st = h->tiles.steps ? h->tiles.steps : (h->cfg.R <= 5 ? 2u : 1u);
+        switch (h->cfg.R * 10 + st) {
+        case 31: return make_pieces<3, 2, 1>(G.na, fast);
+        case 32: return make_pieces<3, 2, 2>(G.na, fast);
+        case 41: return make_pieces<4, 2, 1>(G.na, fast);
+        case 42: return make_pieces<4, 2, 2>(G.na, fast);
+        case 51: return make_pieces<5, 2, 1>(G.na, fast);
+        case 52: return make_pieces<5, 2, 2>(G.na, fast);
+        case 61: return make_pieces<6, 2, 1>(G.na, fast);
+        case 62: return make_pieces<6, 2, 2>(G.na, fast);
         default: break;
         }
     }
@@ -744,6 +758,8 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     uint64_t best_T = 0, best_batches = ~0ull;
     uint32_t best_ncb = G0.na;
     for (uint32_t ng = 1; ng <= 8 && ng <= G0.na; ng *= 2) {
+        if (h->tiles.groups && ng != std::min(h->tiles.groups, G0.na))
+            continue;
         const uint32_t ncb = (G0.na + ng - 1) / ng;
         auto fits = [&](uint64_t T) {
             const ScratchPlan p = scratch_plan(G0, T, h->piece_nwg, ncb);
@@ -783,8 +799,9 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
         hipFuncSetAttribute(AC.fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)AC.lds) != hipSuccess ||
         (AP.fn && hipFuncSetAttribute(reinterpret_cast<const void *>(AP.fn),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)AP.lds) != hipSuccess) ||
-        hipFuncSetAttribute(reinterpret_cast<const void *>(stage_b(G).fn),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage_b(G).lds) != hipSuccess) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(stage_b(G, h->tiles.stage_b_tile).fn),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)stage_b(G, h->tiles.stage_b_tile).lds) != hipSuccess) {
         (void)hipFree(h->bin_mem);
         h->bin_mem = nullptr;
         return fail(h, RAMBO_EHIP, "cannot raise the LDS limit of the insert kernels");
@@ -858,7 +875,7 @@ bool use_partitioned(const rambo *h, uint64_t n_chars)
 // group's regions; its fill counters are cleared between groups).
 void launch_stages_bc(rambo *h, const BinGeom &G, uint32_t fresh, hipStream_t stream)
 {
-    const StageB SB = stage_b(G);
+    const StageB SB = stage_b(G, h->tiles.stage_b_tile);
     const uint32_t tpb = (uint32_t)div_up((uint64_t)G.nwg * G.capA, SB.tile);
     const size_t ldsC = (1ull << (G.rb - 5)) * 4;
     for (uint32_t c0 = 0; c0 < G.na; c0 += G.ncb) {
@@ -1289,6 +1306,62 @@ extern "C" int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_by
     }
     h->insert_mode = mode;
     h->scratch_limit = scratch_bytes;
+    return RAMBO_OK;
+}
+
+// Release the insert scratch (kept for a captured insert that may replay).
+int release_scratch(rambo *h, const char *what)
+{
+    if (!h->bin_mem)
+        return RAMBO_OK;
+    const int rc = hip_check(h, hipDeviceSynchronize(), what);
+    if (rc)
+        return rc;
+    if (h->recorded_insert)
+        h->retired.push_back(h->bin_mem);
+    else
+        (void)hipFree(h->bin_mem);
+    h->bin_mem = nullptr;
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_set_insert_tiles(rambo_t *h, const rambo_insert_tiles *t)
+{
+    if (!h)
+        return RAMBO_EINVAL;
+    const rambo_insert_tiles w = t ? *t : rambo_insert_tiles{};
+    if (w.steps > 2 || (w.stage_b_tile && w.stage_b_tile != 8192 && w.stage_b_tile != 16384 &&
+                        w.stage_b_tile != 32768) ||
+        (w.groups && w.groups != 1 && w.groups != 2 && w.groups != 4 && w.groups != 8) ||
+        (w.fine_bits && (w.fine_bits < 8 || w.fine_bits > 12)))
+        return fail(h, RAMBO_EINVAL, "rambo_set_insert_tiles: value out of range");
+    const rambo_insert_tiles old = h->tiles;
+    if (std::memcmp(&old, &w, sizeof w) == 0)
+        return RAMBO_OK;
+    // the scratch is laid out for the old shapes: release it before the
+    // partition geometry changes
+    if (const int rc = release_scratch(h, "rambo_set_insert_tiles"))
+        return rc;
+    h->tiles = w;
+    plan_partition(h);
+    if (w.fine_bits && !h->part_ok) {
+        h->tiles = old;
+        plan_partition(h);
+        return fail(h, RAMBO_EINVAL, "rambo_set_insert_tiles: fine_bits leaves too many coarse buckets");
+    }
+    return RAMBO_OK;
+}
+
+extern "C" int rambo_get_insert_tiles(rambo_t *h, rambo_insert_tiles *out)
+{
+    if (!h || !out)
+        return RAMBO_EINVAL;
+    const BinGeom &G = h->bin;
+    const StageAPieces AP = stage_a_pieces(h);
+    out->steps = AP.fn ? (h->tiles.steps ? h->tiles.steps : (h->cfg.R <= 5 ? 2u : 1u)) : 0u;
+    out->stage_b_tile = stage_b(G, h->tiles.stage_b_tile).tile;
+    out->groups = h->bin_mem && G.ncb ? (G.na + G.ncb - 1) / G.ncb : h->tiles.groups;
+    out->fine_bits = G.fb;
     return RAMBO_OK;
 }
 

@@ -87,6 +87,8 @@ EXPORTS = {
                                               ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_set_insert_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]),
     "rambo_set_query_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
+    "rambo_set_insert_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rambo_get_insert_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rambo_get_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int]),
@@ -130,6 +132,11 @@ EXPORTS = {
                                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                              ctypes.POINTER(ctypes.c_uint64)]),
 }
+
+
+class InsertTiles(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint32), ("stage_b_tile", ctypes.c_uint32), ("groups", ctypes.c_uint32),
+                ("fine_bits", ctypes.c_uint32)]
 
 
 class ServeConfig(ctypes.Structure):
@@ -353,6 +360,17 @@ class Rambo:
     def set_insert_policy(self, mode: int = 0, scratch_bytes: int = 0):
         """INSERT_AUTO / INSERT_DIRECT / INSERT_PARTITIONED / INSERT_PARTITIONED_WALKER; same index bits."""
         self._check(lib().rambo_set_insert_policy(self._h, mode, scratch_bytes), "rambo_set_insert_policy")
+
+    def set_insert_tiles(self, steps: int = 0, stage_b_tile: int = 0, groups: int = 0, fine_bits: int = 0):
+        """Tile shapes of the partitioned insert (0 = automatic); same index bits."""
+        t = InsertTiles(steps, stage_b_tile, groups, fine_bits)
+        self._check(lib().rambo_set_insert_tiles(self._h, ctypes.byref(t)), "rambo_set_insert_tiles")
+
+    def insert_tiles(self) -> dict:
+        """The tile shapes the partitioned insert uses now."""
+        t = InsertTiles()
+        self._check(lib().rambo_get_insert_tiles(self._h, ctypes.byref(t)), "rambo_get_insert_tiles")
+        return {f: getattr(t, f) for f, _ in InsertTiles._fields_}
 
     def set_query_policy(self, mode: int = 0, chunk_bytes: int = 0, waves_per_cu: int = 0):
         """QUERY_AUTO / QUERY_WAVE_PER_READ / QUERY_QUEUE; same answers."""
