@@ -447,11 +447,44 @@ def section_mid(args):
                              "speedup_batched": res["k_mer_queries_per_s"] / rate}
         log("mid: plain one-launch-per-query path %.3g queries/s on %d, identical=%s"
             % (rate, args.plain_prefix, same))
+    res["skewed_reads"] = skewed_reads(g, sets)
     if not args.no_fold:
         res["fold"] = fold_timing(g)
     g.close()
     del out, codes, dsets
     torch.cuda.empty_cache()
+    return res
+
+
+def skewed_reads(g, sets, n_short: int = 20000, n_long: int = 16, long_len: int = 500_000) -> dict:
+    """A batch where one wave per read is unbalanced: n_short 150-bp reads
+    and n_long exact substrings of long_len bases (every window of these
+    hits, so no early exit).  The query autotuner sweeps both schedules;
+    the work queue splits the long reads into chunks that many waves take."""
+    import torch
+    from paper_1910_02611_amd import autotune, synth
+    from paper_1910_02611_amd.rambo import QUERY_QUEUE, QUERY_WAVE_PER_READ
+    lens = np.concatenate([np.full(n_short, 150), np.full(n_long, long_len)])
+    np.random.default_rng(1).shuffle(lens)
+    rd = synth.reads(3060, sets, lens.size, median_len=0, min_len=150, max_len=long_len, substr_frac=1.0,
+                     lengths=lens)
+    off, ch = to_dev(rd.offsets, np.int64), to_dev(rd.chars, np.uint8)
+    tune = autotune.tune_query_seqs(g, off, ch, tag="skewed-reads", use_cache=False)
+    out = torch.empty((rd.n, g.W), dtype=torch.int32, device="cuda")
+    nk = torch.empty(rd.n, dtype=torch.int32, device="cuda")
+    res = {"reads": rd.n, "long_reads": n_long, "long_len": int(rd.lengths().max()), "bases": int(rd.chars.size),
+           "tile": {k: tune[k] for k in ("mode", "chunk", "waves_per_cu")}}
+    ref = None
+    for name, mode in (("wave_per_read", QUERY_WAVE_PER_READ), ("work_queue", QUERY_QUEUE)):
+        g.set_query_policy(mode, tune["chunk"] if mode == QUERY_QUEUE and tune["mode"] == QUERY_QUEUE else 0,
+                           tune["waves_per_cu"] if mode == QUERY_QUEUE and tune["mode"] == QUERY_QUEUE else 0)
+        tm = autotune.time_query_seqs(g, off, ch, out, nk, reps=3)
+        ref = out.clone() if ref is None else ref
+        res[name] = {"ms": tm * 1e3, "reads_per_s": rd.n / tm, "identical": bool(torch.equal(out, ref))}
+    g.set_query_policy(0)
+    log("mid: skewed batch (%d x 150 bp + %d x %d bp): one wave per read %.3f ms, work queue %.3f ms (identical %s);"
+        " tuned %s" % (n_short, n_long, long_len, res["wave_per_read"]["ms"], res["work_queue"]["ms"],
+                       res["work_queue"]["identical"], res["tile"]))
     return res
 
 

@@ -216,10 +216,10 @@ def tune_insert(g: rb.Rambo, insert, tag: str, use_cache: bool = True, reps: int
             eff = g.insert_tiles()
             if trial["groups"] == 0 and eff["fine_bits"] not in auto_groups:
                 auto_groups[eff["fine_bits"]] = -eff["fine_bits"]   # not known yet: a shape of its own
-            key = resolved(trial, eff)
-            if key in seen:
+            shape = resolved(trial, eff)
+            if shape in seen:
                 continue
-            seen.add(key)
+            seen.add(shape)
             t = time_insert(g, insert, reps)
             fills, words = index_digest(g)
             if not (torch.equal(fills, ref[0]) and torch.equal(words, ref[1])):
