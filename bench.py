@@ -78,7 +78,12 @@ def measured_traffic(names: dict, workload: str) -> dict:
     t = load_traffic(os.path.join(PROFILES, "traffic_%s.json" % workload))
     if t is None:
         return {}
-    return {stage: t["kernels"][k]["bytes"] for stage, k in names.items() if k in t["kernels"]}
+    out = {}
+    for stage, k in names.items():   # a kernel name, or the start of one (template arguments)
+        hit = [n for n in t["kernels"] if n == k or n.startswith(k)]
+        if hit:
+            out[stage] = t["kernels"][hit[0]]["bytes"]
+    return out
 
 
 def hbm_entry(kernel, bytes_per_launch, ms_per_launch, what, traffic=None, launches=1):
@@ -161,11 +166,11 @@ def tune_insert(g, insert, tag: str, args, reps: int = 2) -> dict | None:
         return None
     from paper_1910_02611_amd import autotune
     t = time.time()
-    r = autotune.tune_insert(g, insert, tag, use_cache=False, reps=reps)
-    log("%s: insert tiles %s (automatic %s): %.1f ms vs %.1f ms automatic (%d shapes, %.1f s)"
+    r = autotune.tune_insert(g, insert, tag, reps=reps)
+    log("%s: insert tiles %s (automatic %s): %.1f ms vs %.1f ms automatic (%s, %.1f s)"
         % (tag, r["effective"], r["automatic"], r["seconds"] * 1e3, r["automatic_seconds"] * 1e3,
-           len(r.get("sweep", [])), time.time() - t))
-    return {k: v for k, v in r.items() if k != "cached"}
+           "from the tuning cache" if r["cached"] else "%d shapes timed" % len(r["sweep"]), time.time() - t))
+    return r
 
 
 def time_insert_graph(g, insert, reps: int = 3) -> dict:
@@ -274,6 +279,16 @@ def section_large(args):
     sizes = np.diff(id_off.cpu().numpy())
     RE = cfg["R"] * cfg["eta"]
     roofs = insert_rooflines(kernels, n_win, n_bases, cfg["R"], cfg["eta"], g.index_bytes, True, "large")
+    if "k_query_seqs" in kernels:
+        # reads with a non-empty answer probe every window in every
+        # repetition: R*eta rows of S/8 = 128 bytes each (one line); reads
+        # cut short by the early exit are not credited
+        ms, calls = kernels["k_query_seqs"]
+        full = int(nkm.cpu().numpy().astype(np.int64)[sizes > 0].sum())
+        tr = measured_traffic({"q": "k_query_seqs<"}, "large").get("q")
+        roofs.append(hbm_entry("k_query_seqs", full * RE * max(SECTOR, g.row_bits // 8) / calls, ms / calls,
+                               "R*eta rows of max(64, S/8) bytes per window of the reads with a non-empty answer "
+                               "(the early exit is not credited)", tr, calls))
     res = {
         "workload": "large: K=100000 genome sets (~1.3e10 31-mers), B=1000, R=6, m=2^27, eta=2 (96 GiB); "
                     "%d reads of 150 bp (80%% set substrings with 1%% substitutions) as set-ID lists" % rd.n,

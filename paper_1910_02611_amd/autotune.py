@@ -29,8 +29,8 @@ def cache_path() -> str:
 
 def _key(g: rb.Rambo, tag: str) -> str:
     dev = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return "%s|%s|K%d-B%d-R%d-e%d-m%d|%s" % (dev.name, getattr(dev, "gcnArchName", ""), g.K, g.B, g.R, g.eta,
-                                             g.m, tag)
+    return "%s|%d CUs|K%d-B%d-R%d-e%d-m%d|%s" % (getattr(dev, "gcnArchName", ""), dev.multi_processor_count, g.K,
+                                                g.B, g.R, g.eta, g.m, tag)
 
 
 def _load() -> dict:
@@ -177,12 +177,14 @@ INSERT_KNOBS = {
 }
 
 
-def tune_insert(g: rb.Rambo, insert, tag: str, use_cache: bool = True, reps: int = 2, fine_bits_span: int = 1):
+def tune_insert(g: rb.Rambo, insert, tag: str, use_cache: bool = True, reps: int = 2, fine_bits_span: int = 1,
+                min_gain: float = 0.02):
     """Pick and apply the fastest tile shapes of the partitioned insert for
     this workload: start from the automatic shapes, then try the values of
     one knob at a time (steps, stage-B tile, regions per coarse bucket
     within fine_bits_span of the automatic value, groups), keeping a value
-    when it is faster.  insert() must insert the workload into g (cleared
+    when it is faster by more than min_gain (so that timing noise does not
+    flip the choice).  insert() must insert the workload into g (cleared
     before each timing).  Returns the choice, its time and the sweep."""
     key = _key(g, "insert|" + tag)
     cache = _load() if use_cache else {}
@@ -227,7 +229,7 @@ def tune_insert(g: rb.Rambo, insert, tag: str, use_cache: bool = True, reps: int
             sweep.append({"tiles": dict(trial), "effective": g.insert_tiles(), "seconds": t})
             if trial["groups"] == 0:
                 auto_groups[sweep[-1]["effective"]["fine_bits"]] = sweep[-1]["effective"]["groups"]
-            if t < best_t:
+            if t < best_t * (1.0 - min_gain):
                 best_t, cur = t, trial
     g.set_insert_tiles(**cur)
     choice = {"tiles": cur, "effective": g.insert_tiles(), "seconds": best_t, "automatic": base,
