@@ -130,8 +130,14 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
     const uint32_t total = Q.items[n_reads];
 
     for (;;) {
+        // the pop is made by the wave's first active lane and broadcast from
+        // it, so every lane of the wave sees the same item even if control
+        // flow ever reached this point with some lanes off: a pop by a fixed
+        // lane that is off would leave the others on a stale item, never
+        // reaching the exit test below
+        const bool leader = lane == (uint32_t)__builtin_ctzll(__ballot(1));
         uint32_t item = 0;
-        if (lane == 0)
+        if (leader)
             item = atomicAdd(Q.counter, 1u);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total)
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
                 atomicOr(Q.dead + q, 1u);
         }
         uint32_t left = 0;
-        if (lane == 0)
+        if (lane == (uint32_t)__builtin_ctzll(__ballot(1)))
             left = __hip_atomic_fetch_sub(Q.remaining + q, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         left = __builtin_amdgcn_readfirstlane(left);
         if (left != 1)
