@@ -230,7 +230,7 @@ int rambo_query_seqs_plain(rambo_t *h, const uint64_t *offsets, uint64_t n_reads
  * sorts the targets by address into regions of the index and ORs each region
  * in on-chip memory, which avoids the device's atomic-rate limit on bulk
  * inserts; AUTO picks by the number of targets.  scratch_bytes caps the
- * device scratch of the partitioned path (0 = 85% of the free memory left
+ * device scratch of the partitioned path (0 = 95% of the free memory left
  * after keeping 8 GiB free, at most 192 GiB; the scratch takes about 8.5
  * bytes per bit target of a batch); larger inserts are processed in
  * batches, each of which reads and writes the index regions it touches.  The scratch is sized for

@@ -742,7 +742,7 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
             return fail(h, RAMBO_EHIP, "hipMemGetInfo failed");
-        limit = free_b > 2 * kScratchKeepFree ? (free_b - kScratchKeepFree) / 20 * 17 : free_b / 2;
+        limit = free_b > 2 * kScratchKeepFree ? (free_b - kScratchKeepFree) / 20 * 19 : free_b / 2;
         if (limit > kScratchMax)
             limit = kScratchMax;
     }
