@@ -650,6 +650,7 @@ struct StageAPieces {
     BinPiecesFn fn = nullptr;
     size_t lds = 0;
     uint32_t per_cu = 0;
+    uint32_t steps = 0;
 };
 
 template <int R_T, int ETA_T, int ST>
@@ -661,6 +662,7 @@ StageAPieces make_pieces(uint32_t na, bool fast)
     // 8 GiB index (fewer chunks written at once)
     a.per_cu = a.lds <= kMaxLds ? 1u : 0u;
     a.lds = std::max<size_t>(a.lds, kMaxLds / 2 + 1024);
+    a.steps = ST;
     if (a.per_cu)
         a.fn = fast ? k_bin_pieces<R_T, ETA_T, ST, true> : k_bin_pieces<R_T, ETA_T, ST, false>;
     return a;
@@ -676,7 +678,14 @@ StageAPieces stage_a_pieces(const rambo *h)
     const bool fast = h->P.m_log2 > 0 && h->P.m_log2 <= 32 && shA <= 31 && rep_bits % (1ull << shA) == 0 &&
                       h->P.S_log2 <= shA;
     if (h->cfg.eta == 2 && G.na <= kMaxCoarse) {
-        const uint32_t st = h->tiles.steps ? h->tiles.steps : (h->cfg.R <= 5 ? 2u : 1u);
+        // automatic: two steps per round for R <= 5 where the tile fits LDS
+        uint32_t st = h->tiles.steps ? h->tiles.steps : (h->cfg.R <= 5 ? 2u : 1u);
+        if (!h->tiles.steps && st == 2) {
+            const size_t lds2 = h->cfg.R == 3 ? lds_bytes_pieces<3, 2, 2>(G.na)
+                                : h->cfg.R == 4 ? lds_bytes_pieces<4, 2, 2>(G.na) : lds_bytes_pieces<5, 2, 2>(G.na);
+            if (lds2 > kMaxLds)
+                st = 1;
+        }
         switch (h->cfg.R * 10 + st) {
         case 31: return make_pieces<3, 2, 1>(G.na, fast);
         case 32: return make_pieces<3, 2, 2>(G.na, fast);
@@ -1358,7 +1367,7 @@ extern "C" int rambo_get_insert_tiles(rambo_t *h, rambo_insert_tiles *out)
         return RAMBO_EINVAL;
     const BinGeom &G = h->bin;
     const StageAPieces AP = stage_a_pieces(h);
-    out->steps = AP.fn ? (h->tiles.steps ? h->tiles.steps : (h->cfg.R <= 5 ? 2u : 1u)) : 0u;
+    out->steps = AP.fn ? AP.steps : 0u;
     out->stage_b_tile = stage_b(G, h->tiles.stage_b_tile).tile;
     out->groups = h->bin_mem && G.ncb ? (G.na + G.ncb - 1) / G.ncb : h->tiles.groups;
     out->fine_bits = G.fb;
