@@ -236,8 +236,8 @@ int orc_create(uint32_t K, uint32_t B, uint32_t R, uint32_t eta, uint32_t k, uin
         for (uint32_t j = 0; j < eta; j++)
             h->ps[(size_t)r * eta + j] = orc_splitmix64_next(&st);
 
-    /* R independent partitions of the K sets into B cells (Alg. 1, line
-     * "generate R partition hash functions"). */
+    /* R independent partitions of the K sets into B cells, drawn before any
+     * insertion (Alg. 1). */
     for (uint32_t r = 0; r < R; r++)
         for (uint32_t i = 0; i < K; i++)
             h->phi[(size_t)r * K + i] = (flags & ORC_FLAG_IDENTITY_PARTITION)

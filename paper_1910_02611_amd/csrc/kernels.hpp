@@ -1,6 +1,6 @@
 // RAMBO kernels for gfx950.
 //
-//  k_build_partition  phi_r(i) for all (r, i)                     (Alg. 1, line 1)
+//  k_build_partition  phi_r(i) for all (r, i)                     (Alg. 1)
 //  k_build_cellmask   SetIDs(M[b,r]) as K-bit masks                 (Alg. 2)
 //  k_extract          canonical code of every k-window            (Sec. 3.2.1, Sec. 5.2)
 //  k_insert_seqs      windows of set genomes -> atomicOr into rows (Alg. 1)
@@ -711,6 +711,26 @@ __device__ __forceinline__ bool any_rep_empty(const uint32_t *g, uint32_t R, uin
     return false;
 }
 
+// The same test by the whole wave (every lane gets the answer): lane l looks
+// at words l, l + 64, ... (SW a power of two, R <= 16), then one wave OR.
+__device__ __forceinline__ bool any_rep_empty_wave(const uint32_t *g, uint32_t R, uint32_t SW, uint32_t lane)
+{
+    const uint32_t sh = (uint32_t)__builtin_ctz(SW);
+    uint32_t nz = 0;   // bit r: some word of repetition r is not zero
+    for (uint32_t i = lane; i < R * SW; i += kWave)
+        nz |= g[i] ? 1u << (i >> sh) : 0u;
+    return wave_or(nz) != (1u << R) - 1u;
+}
+
+// Whether one repetition's SW words at g are all zero, by the whole wave.
+__device__ __forceinline__ bool rep_empty_wave(const uint32_t *g, uint32_t SW, uint32_t lane)
+{
+    uint32_t o = 0;
+    for (uint32_t w = lane; w < SW; w += kWave)
+        o |= g[w];
+    return __ballot(o != 0) == 0;
+}
+
 // Answer words from the partition instead of the cell masks: set i is in
 // the answer iff its cell phi_r(i) is positive in every repetition (the
 // union-then-intersection of Alg. 2, evaluated per set).  The same bits as
@@ -1276,8 +1296,12 @@ __global__ __launch_bounds__(kBlock) void k_query_kmers(Params P, const uint64_t
 // The per-slice ANDs are reduced over the lanes of the same slice and
 // folded into G (R x SW words of LDS); dead is set when some repetition is
 // empty.  Only the first n_it rounds run: a caller whose valid lanes are
-// the first WPI n_it ones (a short term set) skips the empty rounds.
-template <int SW, int R_T, int ETA_T>
+// the first WPI n_it ones (a short term set) skips the empty rounds.  PH
+// restricts the step to repetition 0 (kStepFirst) or to the others
+// (kStepRest).
+constexpr int kStepAll = 0, kStepFirst = 1, kStepRest = 2;
+
+template <int SW, int R_T, int ETA_T, int PH = kStepAll>
 __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bool valid, uint32_t *G, bool &dead,
                                                 uint32_t lane, int n_it = SW / 4)
 {
@@ -1304,34 +1328,35 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
         return v;
     };
     const u32x4 ones = {~0u, ~0u, ~0u, ~0u};
-    u32x4 acc0 = ones;
+    if constexpr (PH != kStepRest) {
+        u32x4 acc0 = ones;
 #pragma unroll 4
-    for (int it = 0; it < n_it; ++it) {
-        uint64_t h;
-        bool ok;
-        window(it, h, ok);
-        u32x4 a = ones;
-        if (ok) {
+        for (int it = 0; it < n_it; ++it) {
+            uint64_t h;
+            bool ok;
+            window(it, h, ok);
+            u32x4 a = ones;
+            if (ok) {
 #pragma unroll
-            for (int j = 0; j < ETA_T; ++j)
-                a &= slice(0, h, j);
+                for (int j = 0; j < ETA_T; ++j)
+                    a &= slice(0, h, j);
+            }
+            acc0 &= a;
         }
-        acc0 &= a;
-    }
-    acc0 = reduce(acc0);
-    if (sub == 0) {
-        G[part * 4 + 0] &= acc0.x;
-        G[part * 4 + 1] &= acc0.y;
-        G[part * 4 + 2] &= acc0.z;
-        G[part * 4 + 3] &= acc0.w;
-    }
-    wave_sync_lds();
-    uint32_t left = 0;
-    for (int w = 0; w < SW; ++w)
-        left |= G[w];
-    if (left == 0) {
-        dead = true;
-        return;
+        acc0 = reduce(acc0);
+        if (sub == 0) {
+            G[part * 4 + 0] &= acc0.x;
+            G[part * 4 + 1] &= acc0.y;
+            G[part * 4 + 2] &= acc0.z;
+            G[part * 4 + 3] &= acc0.w;
+        }
+        wave_sync_lds();
+        if (rep_empty_wave(G, SW, lane)) {
+            dead = true;
+            return;
+        }
+        if constexpr (PH == kStepFirst)
+            return;
     }
     if constexpr (R_T > 1) {
         u32x4 acc[R_T - 1];
@@ -1370,7 +1395,7 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
         }
     }
     wave_sync_lds();
-    dead = any_rep_empty(G, R_T, SW);
+    dead = any_rep_empty_wave(G, R_T, SW, lane);
 }
 
 // One step of Sec. 3.2.1: the group masks of the wave's terms (one per lane,
@@ -1379,8 +1404,9 @@ __device__ __forceinline__ void probe_step_wide(const Params &P, uint64_t hx, bo
 // repetition is empty (the first conclusive FALSE).  Repetition 0 first:
 // once its running AND has no cell left the answer is empty (the
 // intersection of Alg. 2), so the rows of the other repetitions are read
-// only while it has one.
-template <int SW, int R_T, int ETA_T>
+// only while it has one.  PH = kStepFirst reads repetition 0 only (dead when
+// it is empty), kStepRest the others only.
+template <int SW, int R_T, int ETA_T, int PH = kStepAll>
 __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, bool valid, uint32_t *G, bool &dead,
                                                uint32_t lane, uint32_t n_valid = kWave)
 {
@@ -1389,26 +1415,27 @@ __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, boo
     if constexpr (R_T > 0 && SW >= 8) {
         // n_valid: the valid lanes are among the first n_valid
         constexpr uint32_t WPI = kWave / (SW / 4);
-        probe_step_wide<SW, R_T, ETA_T>(P, hx, valid, G, dead, lane, (int)((n_valid + WPI - 1) / WPI));
+        probe_step_wide<SW, R_T, ETA_T, PH>(P, hx, valid, G, dead, lane, (int)((n_valid + WPI - 1) / WPI));
     } else if constexpr (R_T > 0) {
+        if constexpr (PH != kStepRest) {
 #pragma unroll 1
-        for (int sl = 0; sl < NSL; ++sl) {
-            uint32_t g0[1][L];
-            Probe<SW, L, 1, ETA_T>::run(P, hx, sl * L, valid, g0);
+            for (int sl = 0; sl < NSL; ++sl) {
+                uint32_t g0[1][L];
+                Probe<SW, L, 1, ETA_T>::run(P, hx, sl * L, valid, g0);
 #pragma unroll
-            for (int w = 0; w < L; ++w) {
-                const uint32_t a = wave_and(valid ? g0[0][w] : ~0u);
-                if (lane == 0)
-                    G[sl * L + w] &= a;
+                for (int w = 0; w < L; ++w) {
+                    const uint32_t a = wave_and(valid ? g0[0][w] : ~0u);
+                    if (lane == 0)
+                        G[sl * L + w] &= a;
+                }
             }
-        }
-        wave_sync_lds();
-        uint32_t left = 0;
-        for (int w = 0; w < SW; ++w)
-            left |= G[w];
-        if (left == 0) {
-            dead = true;
-            return;
+            wave_sync_lds();
+            if (rep_empty_wave(G, SW, lane)) {
+                dead = true;
+                return;
+            }
+            if constexpr (PH == kStepFirst)
+                return;
         }
         if constexpr (R_T > 1) {
 #pragma unroll 1
@@ -1426,11 +1453,12 @@ __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, boo
             }
         }
         wave_sync_lds();
-        dead = any_rep_empty(G, R_T, SW);
+        dead = any_rep_empty_wave(G, R_T, SW, lane);
     } else {
+        const uint32_t r0 = PH == kStepRest ? 1u : 0u, r1 = PH == kStepFirst ? 1u : P.R;
 #pragma unroll 1
         for (int sl = 0; sl < NSL; ++sl) {
-            for (uint32_t r = 0; r < P.R; ++r) {
+            for (uint32_t r = r0; r < r1; ++r) {
                 uint32_t acc[L];
                 probe_rep<SW, L>(P, hx, r, sl * L, valid, acc);
 #pragma unroll
@@ -1442,7 +1470,7 @@ __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, boo
             }
         }
         wave_sync_lds();
-        dead = any_rep_empty(G, P.R, SW);
+        dead = PH == kStepFirst ? rep_empty_wave(G, SW, lane) : any_rep_empty_wave(G, P.R, SW, lane);
     }
 }
 
@@ -1452,13 +1480,24 @@ __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, boo
 // (R x SW words of LDS, wave-private), and stops probing once some repetition
 // is empty (the first conclusive FALSE).  Valid windows are still counted, in
 // nk, to the end of the range.
+//
+// The windows go in blocks of kHashSteps steps: repetition 0 over the whole
+// block first, the other repetitions after it, from the window mixes that
+// the first pass left in LDS (hc: kHashSteps x 64 mixes, vc: kHashSteps
+// validity ballots, both wave-private).  The AND does not depend on the
+// order, and a read that some window rules out (a substitution, an absent
+// k-mer) usually empties repetition 0 at once, so it is dropped before the
+// other repetitions of the block's earlier windows are read.
+constexpr uint32_t kHashSteps = 4;
+
 template <int SW, int R_T, int ETA_T>
 __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t *chars, uint64_t pe,
                                                  uint64_t p_start, uint64_t p_stop, uint32_t *G, uint32_t &nk,
-                                                 bool &dead)
+                                                 bool &dead, uint64_t *hc, uint64_t *vc)
 {
     const uint32_t lane = lane_id();
     const uint64_t kmask = P.kmask;
+    const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
     auto read_byte = [&](uint64_t p, uint32_t &v, bool &bad) {
         v = p < pe ? base_value(chars[p]) : 4u;
         bad = v > 3u;
@@ -1467,29 +1506,53 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
     bool bad;
     read_byte(p_start + lane, v, bad);
     Group A = pack_group(v, bad, false);
-    for (uint64_t p = p_start; p < p_stop; p += kWave) {
-        read_byte(p + kWave + lane, v, bad);
-        const Group Bg = pack_group(v, bad, false);
-        uint64_t x = 0;
-        const bool valid = (p + lane < p_stop) && window_code(A, Bg, lane, P.k, kmask, x);
-        nk += (uint32_t)__popcll(__ballot(valid));
-        if (!dead)
-            and_terms_step<SW, R_T, ETA_T>(P, mix64(x), valid, G, dead, lane);
-        A = Bg;
+    for (uint64_t pb = p_start; pb < p_stop; pb += (uint64_t)kHashSteps * kWave) {
+        uint32_t n_st = 0;
+        for (uint64_t p = pb; p < p_stop && n_st < kHashSteps; p += kWave, ++n_st) {
+            read_byte(p + kWave + lane, v, bad);
+            const Group Bg = pack_group(v, bad, false);
+            uint64_t x = 0;
+            const bool valid = (p + lane < p_stop) && window_code(A, Bg, lane, P.k, kmask, x);
+            const uint64_t bal = __ballot(valid);
+            nk += (uint32_t)__popcll(bal);
+            A = Bg;
+            if (dead)
+                continue;
+            const uint64_t hx = mix64(x);
+            if (R > 1) {
+                hc[n_st * kWave + lane] = hx;
+                if (lane == 0)
+                    vc[n_st] = bal;
+            }
+            and_terms_step<SW, R_T, ETA_T, kStepFirst>(P, hx, valid, G, dead, lane);
+        }
+        if (dead || R == 1)
+            continue;
+        wave_sync_lds();
+        for (uint32_t st = 0; st < n_st && !dead; ++st)
+            and_terms_step<SW, R_T, ETA_T, kStepRest>(P, hc[st * kWave + lane], ((vc[st] >> lane) & 1u) != 0, G,
+                                                      dead, lane);
+        // the next block's first pass rewrites hc and vc only after every
+        // lane has read them here
+        wave_sync_lds();
     }
 }
 
 // Sec. 3.2.1: one wave per read.  The read is expanded once: by the partition
 // identity, AND over k-mers of the expanded answers equals the expansion of
-// the AND of the group masks.  Without a mask output the group masks and
-// the window count are stored in the per-read state instead (ID-list form).
+// the AND of the group masks.  Without a mask output the window count, an
+// empty flag and the group masks of a read not known to be empty are stored
+// in the per-read state instead (ID-list form).
 template <int SW, int R_T, int ETA_T>
 __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t *offsets, uint64_t n_reads,
                                                        const uint8_t *chars, uint64_t n_chars, uint32_t *out,
-                                                       uint32_t *out_nk, uint32_t *state_G, uint32_t *state_nk)
+                                                       uint32_t *out_nk, uint32_t *state_G, uint32_t *state_nk,
+                                                       uint32_t *state_dead)
 {
     constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
     __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
+    __shared__ uint64_t hcs[kWavesPerBlock][kHashSteps * kWave];
+    __shared__ uint64_t vcs[kWavesPerBlock][kHashSteps];
 
     const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
     const uint32_t lane = lane_id();
@@ -1508,16 +1571,21 @@ __global__ __launch_bounds__(kBlock) void k_query_seqs(Params P, const uint64_t 
         p0 = pe;
     uint32_t nk = 0;
     bool dead = false;
-    read_windows_and<SW, R_T, ETA_T>(P, chars, pe, p0, pe, G, nk, dead);
+    read_windows_and<SW, R_T, ETA_T>(P, chars, pe, p0, pe, G, nk, dead, hcs[wv], vcs[wv]);
     if (out_nk && lane == 0)
         out_nk[q] = nk;
     if (!out) {
-        // ID-list form: the final group masks and count go to the per-read
+        // ID-list form: the count, whether the answer is known to be empty,
+        // and (only when it is not) the final group masks go to the per-read
         // state that the ID kernels read
-        for (uint32_t i = lane; i < R * SW; i += kWave)
-            state_G[q * R * SW + i] = G[i];
-        if (lane == 0)
+        const bool empty = dead || nk == 0;
+        if (!empty)
+            for (uint32_t i = lane; i < R * SW; i += kWave)
+                state_G[q * R * SW + i] = G[i];
+        if (lane == 0) {
             state_nk[q] = nk;
+            state_dead[q] = empty ? 1u : 0u;
+        }
         return;
     }
     __shared__ uint16_t lst[kWavesPerBlock * kListCap];

@@ -24,17 +24,20 @@ namespace rambo_dev {
 constexpr int kErrOverflow = 4;
 constexpr uint32_t kScanTile = 1024;   // elements per block of the u64 scan (256 threads x 4)
 
-// Loads read q's final group masks (R x SW words) into the wave's LDS G and
-// tells whether its answer is empty (no valid window, or some repetition
-// without a positive cell).
+// Tells whether read q's answer is empty (no valid window, a repetition
+// that the probing already found empty, or some repetition without a
+// positive cell in the final group masks) and, when it may not be, loads
+// those masks (R x SW words) into the wave's LDS G.  The whole wave calls.
 __device__ __forceinline__ bool load_read_masks(const Params &P, const ReadQueue &Q, uint64_t q, uint32_t SW,
                                                 uint32_t *G, uint32_t lane)
 {
+    if (Q.dead[q] != 0 || Q.nk[q] == 0)
+        return true;
     const uint32_t rsw = P.R * SW;
     for (uint32_t i = lane; i < rsw; i += kWave)
         G[i] = Q.G[q * rsw + i];
     wave_sync_lds();
-    return Q.nk[q] == 0 || any_rep_empty(G, P.R, SW);
+    return any_rep_empty_wave(G, P.R, SW, lane);
 }
 
 // How a read's answer is enumerated.  By the partition identity, A is the
@@ -49,14 +52,16 @@ struct Enum {
     uint32_t cells;      // positive cells of rstar
 };
 
-__device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, uint32_t SW)
+// The whole wave plans: lane l takes words l, l + 64, ... of each
+// repetition, then wave sums.
+__device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, uint32_t SW, uint32_t lane)
 {
     Enum e{false, 0, 0};
     uint32_t best = 0xFFFFFFFFu, all_cells = 0;
     for (uint32_t r = 0; r < P.R; ++r) {
         const uint32_t *off = P.member_off + (uint64_t)r * (P.B + 1);
         uint32_t cand = 0, cells = 0;
-        for (uint32_t sw = 0; sw < SW; ++sw) {
+        for (uint32_t sw = lane; sw < SW; sw += kWave) {
             uint32_t bits = G[r * SW + sw];
             cells += __builtin_popcount(bits);
             while (bits) {
@@ -65,6 +70,8 @@ __device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, ui
                 cand += off[b + 1] - off[b];
             }
         }
+        cand = wave_sum_u32(cand);
+        cells = wave_sum_u32(cells);
         all_cells += cells;
         if (cand < best) {
             best = cand;
@@ -92,21 +99,30 @@ __device__ __forceinline__ bool member_passes(const Params &P, const uint32_t *G
 
 // Calls f(i, pass) for the candidates of rstar, 64 at a time on the wave's
 // lanes (lanes past the end get pass = false), cell by cell in ascending b.
+// The words of rstar with a positive cell are found 64 at a time by a
+// ballot.
 template <class F>
 __device__ __forceinline__ void for_candidates(const Params &P, const uint32_t *G, uint32_t SW, uint32_t rstar,
                                                uint32_t lane, F &&f)
 {
     const uint32_t *off = P.member_off + (uint64_t)rstar * (P.B + 1);
     const uint32_t *mem = P.members + (uint64_t)rstar * P.K;
-    for (uint32_t sw = 0; sw < SW; ++sw) {
-        uint32_t bits = G[rstar * SW + sw];
-        while (bits) {
-            const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
-            bits &= bits - 1;
-            for (uint32_t k0 = off[b]; k0 < off[b + 1]; k0 += kWave) {
-                const uint32_t k = k0 + lane;
-                const uint32_t i = k < off[b + 1] ? mem[k] : 0u;
-                f(i, k < off[b + 1] && member_passes(P, G, SW, rstar, i));
+    for (uint32_t sw0 = 0; sw0 < SW; sw0 += kWave) {
+        const uint32_t mine = sw0 + lane < SW ? G[rstar * SW + sw0 + lane] : 0u;
+        uint64_t words = __ballot(mine != 0);
+        while (words) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(words);
+            words &= words - 1;
+            const uint32_t sw = sw0 + l;
+            uint32_t bits = G[rstar * SW + sw];
+            while (bits) {
+                const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1;
+                for (uint32_t k0 = off[b]; k0 < off[b + 1]; k0 += kWave) {
+                    const uint32_t k = k0 + lane;
+                    const uint32_t i = k < off[b + 1] ? mem[k] : 0u;
+                    f(i, k < off[b + 1] && member_passes(P, G, SW, rstar, i));
+                }
             }
         }
     }
@@ -123,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uin
         const bool empty = load_read_masks(P, Q, q, SW, G, lane);
         uint32_t c = 0;
         if (!empty) {
-            const Enum e = plan_enum(P, G, SW);
+            const Enum e = plan_enum(P, G, SW, lane);
             if (e.by_members)
                 for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t, bool pass) { c += pass ? 1u : 0u; });
             else {
@@ -246,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uin
         if (o0 == o1 || o1 > cap)
             continue;
         load_read_masks(P, Q, q, SW, G, lane);
-        const Enum e = plan_enum(P, G, SW);
+        const Enum e = plan_enum(P, G, SW, lane);
         const uint32_t n = (uint32_t)(o1 - o0);
         if (e.by_members && e.cells == 1) {
             // one member list, ascending: passing members in list order

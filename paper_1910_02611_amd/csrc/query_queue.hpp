@@ -120,6 +120,8 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
     const uint64_t n_reads = batch_reads(n_host, n_dev);
     constexpr int RMAX = R_T > 0 ? R_T : (int)RAMBO_MAX_R;
     __shared__ uint32_t Gs[kWavesPerBlock][RMAX * SW];
+    __shared__ uint64_t hcs[kWavesPerBlock][kHashSteps * kWave];
+    __shared__ uint64_t vcs[kWavesPerBlock][kHashSteps];
     const uint32_t R = R_T > 0 ? (uint32_t)R_T : P.R;
     const uint32_t rsw = R * SW;
     const uint32_t lane = lane_id();
@@ -154,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_rq_persist(Params P, ReadQueue Q, co
         const bool was_dead = __hip_atomic_load(Q.dead + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         bool dead = was_dead;
         uint32_t nk = 0;
-        read_windows_and<SW, R_T, ETA_T>(P, chars, pe, ps, pstop, G, nk, dead);
+        read_windows_and<SW, R_T, ETA_T>(P, chars, pe, ps, pstop, G, nk, dead, hcs[threadIdx.x / kWave],
+                                         vcs[threadIdx.x / kWave]);
 
         if (lane == 0 && nk)
             atomicAdd(Q.nk + q, nk);

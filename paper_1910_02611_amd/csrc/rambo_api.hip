@@ -211,7 +211,7 @@ void launch_query_seqs_t(const rambo *h, const uint64_t *offsets, uint64_t n_rea
 {
     StageScope sc(h, "k_query_seqs", st);
     hipLaunchKernelGGL((k_query_seqs<SW, R_T, ETA_T>), dim3((uint32_t)div_up(n_reads, kWavesPerBlock)),
-                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk, rq.G, rq.nk);
+                       dim3(kBlock), 0, st, h->P, offsets, n_reads, chars, n_chars, out, nk, rq.G, rq.nk, rq.dead);
 }
 
 // Row widths of the workloads get kernels with compile-time R and eta (all
