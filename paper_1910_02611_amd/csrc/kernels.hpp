@@ -1481,13 +1481,16 @@ __device__ __forceinline__ void and_terms_step(const Params &P, uint64_t hx, boo
 // is empty (the first conclusive FALSE).  Valid windows are still counted, in
 // nk, to the end of the range.
 //
-// The windows go in blocks of kHashSteps steps: repetition 0 over the whole
-// block first, the other repetitions after it, from the window mixes that
-// the first pass left in LDS (hc: kHashSteps x 64 mixes, vc: kHashSteps
-// validity ballots, both wave-private).  The AND does not depend on the
-// order, and a read that some window rules out (a substitution, an absent
-// k-mer) usually empties repetition 0 at once, so it is dropped before the
-// other repetitions of the block's earlier windows are read.
+// The windows go in blocks of kHashSteps steps.  The block's window mixes
+// are computed first and kept in LDS (hc: kHashSteps x 64 mixes, vc:
+// kHashSteps validity ballots, both wave-private); then repetition 0 is
+// probed over the whole block, and the other repetitions after it.  Over
+// rows of 8 words or more, a first look at repetition 0 over the windows of
+// one probing round (kWave / (SW / 4) of them) spread evenly over the block
+// comes before: a substitution or an absent k-mer rules out the up to k
+// windows that cover it, so with spacing below k such a read usually ends
+// there.  The AND does not depend on the order (a row read twice changes
+// nothing), so only the rows read differ.
 constexpr uint32_t kHashSteps = 4;
 
 template <int SW, int R_T, int ETA_T>
@@ -1516,24 +1519,31 @@ __device__ __forceinline__ void read_windows_and(const Params &P, const uint8_t 
             const uint64_t bal = __ballot(valid);
             nk += (uint32_t)__popcll(bal);
             A = Bg;
-            if (dead)
-                continue;
-            const uint64_t hx = mix64(x);
-            if (R > 1) {
-                hc[n_st * kWave + lane] = hx;
+            if (!dead) {
+                hc[n_st * kWave + lane] = mix64(x);
                 if (lane == 0)
                     vc[n_st] = bal;
             }
-            and_terms_step<SW, R_T, ETA_T, kStepFirst>(P, hx, valid, G, dead, lane);
         }
-        if (dead || R == 1)
+        if (dead)
             continue;
         wave_sync_lds();
+        if constexpr (R_T > 0 && SW >= 8) {
+            constexpr uint32_t WPI = kWave / (SW / 4);
+            const uint32_t nw = (uint32_t)min<uint64_t>((uint64_t)n_st * kWave, p_stop - pb);
+            const uint32_t j = lane < WPI && WPI > 1 ? lane * (nw - 1) / (WPI - 1) : 0u;
+            const bool ok = lane < WPI && ((vc[j / kWave] >> (j % kWave)) & 1u) != 0;
+            and_terms_step<SW, R_T, ETA_T, kStepFirst>(P, hc[j], ok, G, dead, lane, WPI);
+        }
         for (uint32_t st = 0; st < n_st && !dead; ++st)
-            and_terms_step<SW, R_T, ETA_T, kStepRest>(P, hc[st * kWave + lane], ((vc[st] >> lane) & 1u) != 0, G,
-                                                      dead, lane);
-        // the next block's first pass rewrites hc and vc only after every
-        // lane has read them here
+            and_terms_step<SW, R_T, ETA_T, kStepFirst>(P, hc[st * kWave + lane], ((vc[st] >> lane) & 1u) != 0, G,
+                                                       dead, lane);
+        if (R > 1)
+            for (uint32_t st = 0; st < n_st && !dead; ++st)
+                and_terms_step<SW, R_T, ETA_T, kStepRest>(P, hc[st * kWave + lane], ((vc[st] >> lane) & 1u) != 0,
+                                                          G, dead, lane);
+        // the next block rewrites hc and vc only after every lane has read
+        // them here
         wave_sync_lds();
     }
 }
