@@ -484,26 +484,53 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
     uint32_t *slab = G.slabB + (uint64_t)(c - G.c0) * G.nf * G.capB;
     RunReservationT<(kMaxBucketsPerThread * kBlockP + BLK - 1) / BLK, BLK> res;
     res.issue(cnt, G.nf, fill);
+    // every sorted slot first (rk becomes the slot), then the LDS writes, so
+    // no read waits behind a write
 #pragma unroll
     for (int i = 0; i < kV; ++i) {
         const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (rk[i * 4 + q] != kNone)
-                srt[lbase[e[q] >> G.rb] + rk[i * 4 + q]] = e[q];
+                rk[i * 4 + q] += lbase[e[q] >> G.rb];
+    }
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+        const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (rk[i * 4 + q] != kNone)
+                srt[rk[i * 4 + q]] = e[q];
     }
     res.finish(gbase, G.nf, slab, G.capB);
     __syncthreads();
     const uint32_t maskB = (1u << G.rb) - 1;
     const uint64_t cbit = (uint64_t)c << (G.rb + G.fb);
-    for (uint32_t i = threadIdx.x; i < total; i += BLK) {
-        const uint32_t e = srt[i];
-        const uint32_t f = e >> G.rb;
-        const uint32_t g = gbase[f];
-        if (g == kFail)
-            fallback_or(P, G, cbit + e);
-        else
-            slab[(uint64_t)f * G.capB + g + (i - lbase[f])] = e & maskB;
+    // kOut sorted slots per thread at a time: their LDS reads are in flight
+    // together
+    constexpr uint32_t kOut = 8;
+    for (uint32_t i0 = threadIdx.x; i0 < total; i0 += BLK * kOut) {
+        uint32_t e[kOut], g[kOut], lb[kOut];
+#pragma unroll
+        for (uint32_t u = 0; u < kOut; ++u) {
+            const uint32_t i = i0 + u * BLK;
+            e[u] = i < total ? srt[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kOut; ++u) {
+            g[u] = gbase[e[u] >> G.rb];
+            lb[u] = lbase[e[u] >> G.rb];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kOut; ++u) {
+            const uint32_t i = i0 + u * BLK;
+            if (i < total) {
+                if (g[u] == kFail)
+                    fallback_or(P, G, cbit + e[u]);
+                else
+                    slab[(uint64_t)(e[u] >> G.rb) * G.capB + g[u] + (i - lb[u])] = e[u] & maskB;
+            }
+        }
     }
 }
 

@@ -340,22 +340,44 @@ void k_bin_pieces(Params P, BinGeom G, PieceArgs A)
             __syncthreads();
             const uint32_t total_valid = piece_round_scan(cnt, lbase, cur, dst, wsum, na, (uint64_t)wg * G.capA,
                                                           (uint64_t)nwg * G.capA, G.capA);
+            // every sorted slot first (hbr becomes slot | bucket << 16), then
+            // the LDS writes, so no read waits behind a write
 #pragma unroll
             for (uint32_t i = 0; i < NT; ++i) {
                 const uint32_t b = hbr[i] & 0xFFFFu;
-                const uint32_t pos = lbase[b] + (hbr[i] >> 16);
-                srt[pos] = he[i];
-                sbk[pos] = (uint16_t)b;
+                hbr[i] = (lbase[b] + (hbr[i] >> 16)) | (b << 16);
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < NT; ++i) {
+                srt[hbr[i] & 0xFFFFu] = he[i];
+                sbk[hbr[i] & 0xFFFFu] = (uint16_t)(hbr[i] >> 16);
             }
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < total_valid; i += kBlockPc) {
-                const uint32_t b = sbk[i];
-                const uint32_t e = srt[i];
-                const uint64_t d = dst[b];
-                if (d != kFail64)
-                    G.slabA[d + i] = e;
-                else
-                    fallback_or(P, G, ((uint64_t)b << shA) | e);
+            // kOut sorted slots per thread at a time: their LDS reads are in
+            // flight together
+            constexpr uint32_t kOut = 4;
+            for (uint32_t i0 = threadIdx.x; i0 < total_valid; i0 += kBlockPc * kOut) {
+                uint32_t b[kOut], e[kOut];
+                uint64_t d[kOut];
+#pragma unroll
+                for (uint32_t u = 0; u < kOut; ++u) {
+                    const uint32_t i = i0 + u * kBlockPc;
+                    b[u] = i < total_valid ? sbk[i] : 0u;
+                    e[u] = i < total_valid ? srt[i] : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kOut; ++u)
+                    d[u] = dst[b[u]];
+#pragma unroll
+                for (uint32_t u = 0; u < kOut; ++u) {
+                    const uint32_t i = i0 + u * kBlockPc;
+                    if (i < total_valid) {
+                        if (d[u] != kFail64)
+                            G.slabA[d[u] + i] = e[u];
+                        else
+                            fallback_or(P, G, ((uint64_t)b[u] << shA) | e[u]);
+                    }
+                }
             }
             // no barrier here: the next round's counting touches only cnt
             // (reset by the scan), and its scan, which rewrites lbase and

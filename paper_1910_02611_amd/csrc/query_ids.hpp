@@ -4,12 +4,14 @@
 // The ID form compacts the K-bit answer of Sec. 3.2.1 (Alg. 2's A).  It
 // starts from the per-read group masks that the work-queue launch leaves in
 // its state (run without the mask expansion), then
-//   k_ids_count : wave per read, |A|: either the candidate members of one
+//   k_ids_count : |A| per read: either the candidate members of one
 //                 repetition's positive cells tested against the others, or
 //                 the popcounts of the expanded K-bit words;
 //   k_scan64_*  : exclusive scan of the counts into id_offsets (n+1 entries);
-//   k_ids_write : wave per read, the same enumeration again, writing the IDs
-//                 in ascending order at their wave-prefix positions.
+//   k_ids_write : the same enumeration again, writing the IDs in ascending
+//                 order at their wave-prefix positions.
+// Both take 64 consecutive reads per wave: the lanes check them at once and
+// the wave then works through the ones with a (possibly) non-empty answer.
 // A read whose list would end beyond the caller's capacity is not written and
 // the sticky overflow bit is raised; id_offsets is always complete.
 //
@@ -24,15 +26,18 @@ namespace rambo_dev {
 constexpr int kErrOverflow = 4;
 constexpr uint32_t kScanTile = 1024;   // elements per block of the u64 scan (256 threads x 4)
 
-// Tells whether read q's answer is empty (no valid window, a repetition
-// that the probing already found empty, or some repetition without a
-// positive cell in the final group masks) and, when it may not be, loads
-// those masks (R x SW words) into the wave's LDS G.  The whole wave calls.
+// Whether read q's answer is known to be empty without its masks: no valid
+// window, or a repetition the probing already found empty.
+__device__ __forceinline__ bool read_known_empty(const ReadQueue &Q, uint64_t q)
+{
+    return Q.dead[q] != 0 || Q.nk[q] == 0;
+}
+
+// Loads read q's final group masks (R x SW words) into the wave's LDS G and
+// tells whether some repetition has no positive cell.  The whole wave calls.
 __device__ __forceinline__ bool load_read_masks(const Params &P, const ReadQueue &Q, uint64_t q, uint32_t SW,
                                                 uint32_t *G, uint32_t lane)
 {
-    if (Q.dead[q] != 0 || Q.nk[q] == 0)
-        return true;
     const uint32_t rsw = P.R * SW;
     for (uint32_t i = lane; i < rsw; i += kWave)
         G[i] = Q.G[q * rsw + i];
@@ -128,31 +133,45 @@ __device__ __forceinline__ void for_candidates(const Params &P, const uint32_t *
     }
 }
 
+// Wave per 64 consecutive reads: lane l checks read q0 + l, and only the
+// reads not known to be empty are enumerated, one after the other by the
+// whole wave (most reads of a batch usually are empty, and one coalesced
+// check replaces a dependent load per read).
 __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
                                                       uint64_t *counts)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     uint32_t *G = lds + (threadIdx.x / kWave) * (P.R * SW);
-    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
-    for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; q < n_reads; q += stride) {
-        const bool empty = load_read_masks(P, Q, q, SW, G, lane);
-        uint32_t c = 0;
-        if (!empty) {
-            const Enum e = plan_enum(P, G, SW, lane);
-            if (e.by_members)
-                for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t, bool pass) { c += pass ? 1u : 0u; });
-            else {
-                uint32_t cost;
-                const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
-                for (uint32_t w = lane; w < P.W; w += kWave)
-                    c += __builtin_popcount(expand_word(P, G, SW, w, neg));
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock * kWave;
+    for (uint64_t q0 = ((uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kWave; q0 < n_reads;
+         q0 += stride) {
+        const uint64_t ql = q0 + lane;
+        uint64_t todo = __ballot(ql < n_reads && !read_known_empty(Q, ql));
+        uint32_t mine = 0;   // the count of read ql
+        while (todo) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint64_t q = q0 + l;
+            uint32_t c = 0;
+            if (!load_read_masks(P, Q, q, SW, G, lane)) {
+                const Enum e = plan_enum(P, G, SW, lane);
+                if (e.by_members)
+                    for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t, bool pass) { c += pass ? 1u : 0u; });
+                else {
+                    uint32_t cost;
+                    const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
+                    for (uint32_t w = lane; w < P.W; w += kWave)
+                        c += __builtin_popcount(expand_word(P, G, SW, w, neg));
+                }
             }
+            c = wave_sum_u32(c);
+            if (lane == l)
+                mine = c;
+            wave_sync_lds();
         }
-        c = wave_sum_u32(c);
-        if (lane == 0)
-            counts[q] = c;
-        wave_sync_lds();
+        if (ql < n_reads)
+            counts[ql] = mine;
     }
 }
 
@@ -256,61 +275,69 @@ __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uin
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t *G = lds + wv * (P.R * SW);
     uint32_t *buf = lds + kWavesPerBlock * (P.R * SW) + wv * kSortCap;
-    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
-    for (uint64_t q = (uint64_t)blockIdx.x * kWavesPerBlock + wv; q < n_reads; q += stride) {
-        const uint64_t o0 = id_offsets[q], o1 = id_offsets[q + 1];
-        if (o0 == o1 || o1 > cap)
-            continue;
-        load_read_masks(P, Q, q, SW, G, lane);
-        const Enum e = plan_enum(P, G, SW, lane);
-        const uint32_t n = (uint32_t)(o1 - o0);
-        if (e.by_members && e.cells == 1) {
-            // one member list, ascending: passing members in list order
-            uint64_t base = o0;
-            for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
-                const uint64_t bal = __ballot(pass);
-                if (pass)
-                    ids[base + __popcll(bal & ((1ull << lane) - 1))] = i;
-                base += __popcll(bal);
-            });
-        } else if (e.by_members && n <= kSortCap) {
-            // several lists: gather in LDS, sort, write
-            uint32_t fill = 0;
-            for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
-                const uint64_t bal = __ballot(pass);
-                if (pass)
-                    buf[fill + __popcll(bal & ((1ull << lane) - 1))] = i;
-                fill += __popcll(bal);
-            });
-            uint32_t n_pad = 1;
-            while (n_pad < n)
-                n_pad <<= 1;
-            for (uint32_t t = n + lane; t < n_pad; t += kWave)
-                buf[t] = 0xFFFFFFFFu;
-            wave_sync_lds();
-            wave_bitonic_sort(buf, n_pad, lane);
-            for (uint32_t t = lane; t < n; t += kWave)
-                ids[o0 + t] = buf[t];
-        } else {
-            uint64_t base = o0;
-            uint32_t cost;
-            const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
-            for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
-                const uint32_t w = w0 + lane;
-                uint32_t word = w < P.W ? expand_word(P, G, SW, w, neg) : 0u;
-                const uint32_t c = __builtin_popcount(word);
-                uint64_t pos = base + wave_excl_scan_u32(c, lane);
-                while (word) {
-                    const uint32_t b = (uint32_t)__builtin_ctz(word);
-                    word &= word - 1;
-                    if (pos < o1)
-                        ids[pos] = w * 32 + b;
-                    ++pos;
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock * kWave;
+    for (uint64_t q0 = ((uint64_t)blockIdx.x * kWavesPerBlock + wv) * kWave; q0 < n_reads; q0 += stride) {
+        // lane l checks read q0 + l; the reads with a list that fits are
+        // written one after the other by the whole wave
+        const uint64_t ql = q0 + lane;
+        const uint64_t a0 = ql < n_reads ? id_offsets[ql] : 0, a1 = ql < n_reads ? id_offsets[ql + 1] : 0;
+        uint64_t todo = __ballot(a1 > a0 && a1 <= cap);
+        while (todo) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint64_t q = q0 + l;
+            const uint64_t o0 = readlane64(a0, l), o1 = readlane64(a1, l);
+            load_read_masks(P, Q, q, SW, G, lane);
+            const Enum e = plan_enum(P, G, SW, lane);
+            const uint32_t n = (uint32_t)(o1 - o0);
+            if (e.by_members && e.cells == 1) {
+                // one member list, ascending: passing members in list order
+                uint64_t base = o0;
+                for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
+                    const uint64_t bal = __ballot(pass);
+                    if (pass)
+                        ids[base + __popcll(bal & ((1ull << lane) - 1))] = i;
+                    base += __popcll(bal);
+                });
+            } else if (e.by_members && n <= kSortCap) {
+                // several lists: gather in LDS, sort, write
+                uint32_t fill = 0;
+                for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
+                    const uint64_t bal = __ballot(pass);
+                    if (pass)
+                        buf[fill + __popcll(bal & ((1ull << lane) - 1))] = i;
+                    fill += __popcll(bal);
+                });
+                uint32_t n_pad = 1;
+                while (n_pad < n)
+                    n_pad <<= 1;
+                for (uint32_t t = n + lane; t < n_pad; t += kWave)
+                    buf[t] = 0xFFFFFFFFu;
+                wave_sync_lds();
+                wave_bitonic_sort(buf, n_pad, lane);
+                for (uint32_t t = lane; t < n; t += kWave)
+                    ids[o0 + t] = buf[t];
+            } else {
+                uint64_t base = o0;
+                uint32_t cost;
+                const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
+                for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
+                    const uint32_t w = w0 + lane;
+                    uint32_t word = w < P.W ? expand_word(P, G, SW, w, neg) : 0u;
+                    const uint32_t c = __builtin_popcount(word);
+                    uint64_t pos = base + wave_excl_scan_u32(c, lane);
+                    while (word) {
+                        const uint32_t b = (uint32_t)__builtin_ctz(word);
+                        word &= word - 1;
+                        if (pos < o1)
+                            ids[pos] = w * 32 + b;
+                        ++pos;
+                    }
+                    base += wave_sum_u32(c);
                 }
-                base += wave_sum_u32(c);
             }
+            wave_sync_lds();
         }
-        wave_sync_lds();
     }
 }
 

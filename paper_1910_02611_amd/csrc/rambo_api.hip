@@ -1496,7 +1496,7 @@ int query_seqs_ids_on(rambo *h, const ReadQueue &rq, uint64_t *scan_part, const 
         with_row_words(h, QuerySeqsLaunch{h, offsets, n_reads, chars, n_chars, nullptr, out_nkmers, stream, rq});
     else
         launch_read_queue(h, rq, offsets, n_reads, nullptr, n_reads, chars, n_chars, nullptr, out_nkmers, stream);
-    const uint64_t waves = std::min<uint64_t>(n_reads, (uint64_t)h->num_cus * 16);
+    const uint64_t waves = std::min<uint64_t>(div_up(n_reads, kWave), (uint64_t)h->num_cus * 32);
     const dim3 grid((uint32_t)div_up(waves, kWavesPerBlock));
     const size_t lds = (size_t)kWavesPerBlock * h->cfg.R * h->SW * 4;
     {
