@@ -62,7 +62,7 @@ struct BinGeom {
 };
 
 __host__ __device__ constexpr size_t lds_bytes_stage_a(uint32_t na) { return kTileA * 12ull + na * 12ull + 64; }
-__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 4ull + nf * 12ull + 64; }   // the smallest stage-B tile
+__host__ __device__ constexpr size_t lds_bytes_stage_b(uint32_t nf) { return kTileB * 4ull + nf * 8ull; }   // the smallest stage-B tile
 
 // A target whose run did not fit its slab is set with a global atomic right
 // away; its region is marked so that stage C reads the region back even into
@@ -405,22 +405,26 @@ void k_bin_codes_hold(Params P, BinGeom G, const uint32_t *set_ids, const uint64
 // entries stay in registers; the counting atomic gives each its rank inside
 // its region, so after the scan it goes straight to its sorted LDS slot (4
 // bytes of LDS per entry).  Larger tiles give longer runs per region, so
-// fewer partly written memory segments.
+// fewer partly written memory segments.  LDS: the sorted tile, then two
+// words per region (the count, which the reservation turns into the run's
+// first slab entry, and the first sorted slot); the scan's wave sums use
+// the tile's space before any entry is sorted into it.
 template <int BLK, uint32_t TILE>
 __host__ __device__ constexpr size_t lds_bytes_stage_b_t(uint32_t nf)
 {
-    return TILE * 4ull + nf * 12ull + (BLK / kWave) * 4ull;
+    return TILE * 4ull + nf * 8ull;
 }
 
 template <int BLK, uint32_t TILE>
 __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32_t tiles_per_bucket)
 {
     extern __shared__ uint32_t lds[];
+    static_assert(BLK / kWave <= TILE, "wave sums fit the tile");
     uint32_t *srt = lds;                // TILE entries sorted by region
-    uint32_t *cnt = srt + TILE;         // nf counts (reset by the reservation)
+    uint32_t *cnt = srt + TILE;         // nf counts (read and reset by the reservation) ...
+    uint32_t *gbase = cnt;              // ... whose finish stores the runs' first slab entries there
     uint32_t *lbase = cnt + G.nf;       // nf first sorted slots
-    uint32_t *gbase = lbase + G.nf;     // nf first slab entries of the runs
-    uint32_t *wsum = gbase + G.nf;      // BLK / 64
+    uint32_t *wsum = srt;               // BLK / 64, only while the scan runs
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     const uint32_t c = G.c0 + blockIdx.x / tiles_per_bucket;
     const uint32_t tile = blockIdx.x % tiles_per_bucket;
