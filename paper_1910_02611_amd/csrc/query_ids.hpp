@@ -12,6 +12,8 @@
 //                 order at their wave-prefix positions.
 // Both take 64 consecutive reads per wave: the lanes check them at once and
 // the wave then works through the ones with a (possibly) non-empty answer.
+// A short list found by k_ids_count is kept in the read's mask words, and
+// k_ids_write only copies it.
 // A read whose list would end beyond the caller's capacity is not written and
 // the sticky overflow bit is raised; id_offsets is always complete.
 //
@@ -133,19 +135,56 @@ __device__ __forceinline__ void for_candidates(const Params &P, const uint32_t *
     }
 }
 
+// Largest list a wave sorts in LDS when the candidates come from several
+// cells (their lists interleave); longer lists take the word expansion.
+constexpr uint32_t kSortCap = 1024;
+
+__device__ __forceinline__ void wave_bitonic_sort(uint32_t *a, uint32_t n_pad, uint32_t lane)
+{
+    for (uint32_t k = 2; k <= n_pad; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = lane; i < n_pad; i += kWave) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            wave_sync_lds();
+        }
+}
+
+// A read's answer of at most min(R*SW, kSortCap) IDs is kept, ascending, in
+// the read's own R*SW mask words once counted (the count kernel has the
+// masks in LDS by then), so the write kernel copies it instead of
+// enumerating the answer again.
+__device__ __forceinline__ bool list_in_slot(uint64_t n, uint32_t rsw)
+{
+    return n <= rsw && n <= kSortCap;
+}
+
 // Wave per 64 consecutive reads: lane l checks read q0 + l, and only the
 // reads not known to be empty are enumerated, one after the other by the
 // whole wave (most reads of a batch usually are empty, and one coalesced
-// check replaces a dependent load per read).
+// check replaces a dependent load per read).  The IDs go to the wave's LDS
+// buffer as they are found (sorted when they come from several cells) and,
+// when the list is short enough, into the read's mask slot.
 __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
                                                       uint64_t *counts)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
-    uint32_t *G = lds + (threadIdx.x / kWave) * (P.R * SW);
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t rsw = P.R * SW;
+    uint32_t *G = lds + wv * rsw;
+    uint32_t *buf = lds + kWavesPerBlock * rsw + wv * kSortCap;
+    const uint64_t below = (1ull << lane) - 1;
     const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock * kWave;
-    for (uint64_t q0 = ((uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kWave; q0 < n_reads;
-         q0 += stride) {
+    for (uint64_t q0 = ((uint64_t)blockIdx.x * kWavesPerBlock + wv) * kWave; q0 < n_reads; q0 += stride) {
         const uint64_t ql = q0 + lane;
         uint64_t todo = __ballot(ql < n_reads && !read_known_empty(Q, ql));
         uint32_t mine = 0;   // the count of read ql
@@ -156,16 +195,46 @@ __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uin
             uint32_t c = 0;
             if (!load_read_masks(P, Q, q, SW, G, lane)) {
                 const Enum e = plan_enum(P, G, SW, lane);
-                if (e.by_members)
-                    for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t, bool pass) { c += pass ? 1u : 0u; });
-                else {
+                if (e.by_members) {
+                    for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
+                        const uint64_t bal = __ballot(pass);
+                        const uint32_t at = c + (uint32_t)__popcll(bal & below);
+                        if (pass && at < kSortCap)
+                            buf[at] = i;
+                        c += (uint32_t)__popcll(bal);
+                    });
+                    if (e.cells > 1 && list_in_slot(c, rsw)) {
+                        uint32_t n_pad = 1;
+                        while (n_pad < c)
+                            n_pad <<= 1;
+                        for (uint32_t t = c + lane; t < n_pad; t += kWave)
+                            buf[t] = 0xFFFFFFFFu;
+                        wave_sync_lds();
+                        wave_bitonic_sort(buf, n_pad, lane);
+                    }
+                } else {
                     uint32_t cost;
                     const uint32_t neg = complement_reps(P, G, P.R, SW, &cost);
-                    for (uint32_t w = lane; w < P.W; w += kWave)
-                        c += __builtin_popcount(expand_word(P, G, SW, w, neg));
+                    for (uint32_t w0 = 0; w0 < P.W; w0 += kWave) {
+                        const uint32_t w = w0 + lane;
+                        uint32_t word = w < P.W ? expand_word(P, G, SW, w, neg) : 0u;
+                        const uint32_t wc = __builtin_popcount(word);
+                        uint32_t at = c + wave_excl_scan_u32(wc, lane);
+                        while (word) {
+                            const uint32_t b = (uint32_t)__builtin_ctz(word);
+                            word &= word - 1;
+                            if (at < kSortCap)
+                                buf[at] = w * 32 + b;
+                            ++at;
+                        }
+                        c += wave_sum_u32(wc);
+                    }
                 }
+                wave_sync_lds();
+                if (list_in_slot(c, rsw))
+                    for (uint32_t t = lane; t < c; t += kWave)
+                        Q.G[q * rsw + t] = buf[t];
             }
-            c = wave_sum_u32(c);
             if (lane == l)
                 mine = c;
             wave_sync_lds();
@@ -244,29 +313,6 @@ __global__ __launch_bounds__(256) void k_scan64_add(uint64_t *y, uint64_t n, con
         y[i] += part[i / kScanTile];
 }
 
-// Largest list a wave sorts in LDS when the candidates come from several
-// cells (their lists interleave); longer lists take the word expansion.
-constexpr uint32_t kSortCap = 1024;
-
-__device__ __forceinline__ void wave_bitonic_sort(uint32_t *a, uint32_t n_pad, uint32_t lane)
-{
-    for (uint32_t k = 2; k <= n_pad; k <<= 1)
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = lane; i < n_pad; i += kWave) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const uint32_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        a[i] = y;
-                        a[l] = x;
-                    }
-                }
-            }
-            wave_sync_lds();
-        }
-}
-
 __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uint64_t n_reads, uint32_t SW,
                                                       const uint64_t *id_offsets, uint32_t *ids, uint64_t cap)
 {
@@ -287,9 +333,15 @@ __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uin
             todo &= todo - 1;
             const uint64_t q = q0 + l;
             const uint64_t o0 = readlane64(a0, l), o1 = readlane64(a1, l);
+            const uint32_t n = (uint32_t)(o1 - o0);
+            if (list_in_slot(n, P.R * SW)) {
+                // the count kernel left the list in the read's mask slot
+                for (uint32_t t = lane; t < n; t += kWave)
+                    ids[o0 + t] = Q.G[q * P.R * SW + t];
+                continue;
+            }
             load_read_masks(P, Q, q, SW, G, lane);
             const Enum e = plan_enum(P, G, SW, lane);
-            const uint32_t n = (uint32_t)(o1 - o0);
             if (e.by_members && e.cells == 1) {
                 // one member list, ascending: passing members in list order
                 uint64_t base = o0;

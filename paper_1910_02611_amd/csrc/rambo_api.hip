@@ -1501,7 +1501,8 @@ int query_seqs_ids_on(rambo *h, const ReadQueue &rq, uint64_t *scan_part, const 
     const size_t lds = (size_t)kWavesPerBlock * h->cfg.R * h->SW * 4;
     {
         StageScope sc(h, "k_ids_count", stream);
-        hipLaunchKernelGGL(k_ids_count, grid, dim3(kBlock), lds, stream, h->P, rq, n_reads, h->SW, id_offsets);
+        hipLaunchKernelGGL(k_ids_count, grid, dim3(kBlock), lds + (size_t)kWavesPerBlock * kSortCap * 4, stream, h->P,
+                           rq, n_reads, h->SW, id_offsets);
     }
     const uint64_t nb = div_up(n_reads, kScanTile);
     {
