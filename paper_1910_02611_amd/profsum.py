@@ -43,6 +43,7 @@ def kernel_source_hash() -> str:
 def short_name(full: str) -> str:
     """rambo_dev::k_bin_windows_hold<4, 2>(...) -> k_bin_windows_hold<4, 2>"""
     s = re.sub(r"^void ", "", full)
+    s = s.replace("(anonymous namespace)::", "")
     s = s.split("(")[0]
     return s.replace("rambo_dev::", "")
 
