@@ -270,6 +270,7 @@ def section_large(args):
     def query():
         state["r"] = g.query_seqs_ids(off, ch, ids=ids, nkmers=nk)
 
+    pattern = stage_a_write_pattern(g) if not args.no_measured_ceilings else None
     tuning = tune_insert(g, lambda: g.insert_seqs(*dsets), "large", args, reps=1)
     wall, ph, kernels = time_steps(g, lambda: g.insert_seqs(*dsets), query, args.steps, args.warmup)
     if g.sync_status() != 0:
@@ -289,6 +290,15 @@ def section_large(args):
         roofs.append(hbm_entry("k_query_seqs", full * RE * max(SECTOR, g.row_bits // 8) / calls, ms / calls,
                                "R*eta rows of max(64, S/8) bytes per window of the reads with a non-empty answer "
                                "(the early exit is not credited)", tr, calls))
+    if pattern is not None and "k_bin_pieces" in kernels:
+        ms, calls = kernels["k_bin_pieces"]
+        ent = n_win * RE * 4 / calls / (ms / calls / 1e3) / 1e9
+        pattern["stage_a_entries_GBps"] = ent
+        pattern["stage_a_frac_of_misaligned"] = ent / pattern["misaligned"]["GBps"]
+        log("large: stage A writes its 4-byte entries at %.0f GB/s: %.0f%% of the %.0f GB/s its write pattern "
+            "sustains alone (%.0f GB/s with aligned runs)" % (ent, 100 * pattern["stage_a_frac_of_misaligned"],
+                                                              pattern["misaligned"]["GBps"],
+                                                              pattern["aligned"]["GBps"]))
     res = {
         "workload": "large: K=100000 genome sets (~1.3e10 31-mers), B=1000, R=6, m=2^27, eta=2 (96 GiB); "
                     "%d reads of 150 bp (80%% set substrings with 1%% substitutions) as set-ID lists" % rd.n,
@@ -304,6 +314,7 @@ def section_large(args):
         "rooflines": sorted(roofs, key=lambda r: -r["ms"] * r.get("launches", 1)),
         "answer_sets_hist_0_to_10plus": np.bincount(np.minimum(sizes, 10), minlength=11).tolist(),
         "insert_tuning": tuning,
+        "stage_a_write_pattern": pattern,
     }
     log("large: step %.1f ms: clear %.2f, insert %.1f ms (%.3g inserts/s), ID-list query %.2f ms (%.3g k-mer "
         "queries/s, %.3g reads/s)" % (res["ms_per_step"], ph["clear"], ph["insert"], res["inserts_per_s"],
@@ -501,6 +512,27 @@ def skewed_reads(g, sets, n_short: int = 20000, n_long: int = 16, long_len: int 
         " tuned %s" % (n_short, n_long, long_len, res["wave_per_read"]["ms"], res["work_queue"]["ms"],
                        res["work_queue"]["identical"], res["tile"]))
     return res
+
+
+REGION_BITS = 19   # the insert's index regions (stage C): 2^19 bits, 64 KiB of LDS
+
+
+def stage_a_write_pattern(g, gib: float = 8.0) -> dict:
+    """The write pattern of the insert's stage A measured alone on this GPU
+    (before the first insert allocates its scratch): runs of 16 four-byte
+    entries appended to one chunk per (coarse bucket, workgroup), as many
+    buckets as this index has and one workgroup per CU, with runs starting
+    inside 64-byte segments (as the binning's running cursors do) and, for
+    reference, aligned to them."""
+    import torch
+    from paper_1910_02611_amd import roofline
+    fb = g.insert_tiles()["fine_bits"]
+    streams = -(-g.index_bytes * 8 // (1 << (REGION_BITS + fb)))
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    out = roofline.append(int(gib * 2**30), streams, 16, cus)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()   # the probe's buffer must not shrink the insert's scratch
+    return out
 
 
 def measured_ceilings(index_bytes: int, S: int, RE: int, q_per_s: float, kernels: dict) -> dict:

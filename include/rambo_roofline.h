@@ -10,7 +10,8 @@
  * random-access ceiling next to the datasheet one.
  *
  * All pointers are device pointers owned by the caller; calls are
- * asynchronous on `stream`; return 0 or RAMBO_EINVAL (rambo.h codes).
+ * asynchronous on `stream` (host out-parameters are written before the
+ * call returns); return 0 or RAMBO_EINVAL (rambo.h codes).
  */
 #ifndef RAMBO_ROOFLINE_H
 #define RAMBO_ROOFLINE_H
@@ -34,6 +35,21 @@ int rambo_roofline_gather(const void *buf, uint64_t buf_bytes, uint32_t access_b
  * random words of buf (buf_words words). */
 int rambo_roofline_atomic_or(uint32_t *buf, uint64_t buf_words, uint64_t n_access, uint64_t seed,
                              hipStream_t stream);
+
+/* The write pattern of the partitioned insert's binning (stage A): each of
+ * n_workgroups workgroups of 1024 threads owns a chunk of every one of
+ * `streams` buckets of buf (buf_words words; chunk (b, g) holds cap =
+ * buf_words / (streams * n_workgroups) words, rounded down to a multiple of
+ * 16) and each round appends a run of `run` 32-bit words to each of its
+ * chunks, consecutive lanes writing consecutive words, for as many rounds as
+ * fit.  With `misaligned` != 0 every chunk's runs start 0..15 words into its
+ * first 64-byte segment (from mix64 of the bucket and the workgroup), so runs
+ * start and end inside segments as appends at a running cursor do; with 0
+ * every run of 16 words fills one aligned segment.  *written_words (host
+ * memory) receives the words the launch writes.  RAMBO_EINVAL when a chunk
+ * cannot hold one run. */
+int rambo_roofline_append(uint32_t *buf, uint64_t buf_words, uint32_t streams, uint32_t run, uint32_t misaligned,
+                          uint32_t n_workgroups, uint64_t *written_words, hipStream_t stream);
 
 /* Streaming copy of bytes (a multiple of 16) from src to dst: the
  * sequential-bandwidth reference and the calibration kernel of the memory

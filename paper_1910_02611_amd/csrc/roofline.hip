@@ -1,6 +1,8 @@
 // Memory-system probes for the RAMBO access patterns (include/rambo_roofline.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "rambo.h"
 #include "rambo_roofline.h"
@@ -60,6 +62,28 @@ __global__ __launch_bounds__(kBlock) void k_atomic_or(uint32_t *buf, uint64_t n_
         const uint64_t h = mix64(seed + first + a);
         atomicOr(buf + __umul64hi(h, n_words), 1u << (h & 31u));
     }
+}
+
+// The write pattern of the partitioned insert's binning: workgroup g owns a
+// chunk of every one of `streams` buckets (chunk (b, g) at (b * nwg + g) *
+// cap words) and each round appends a run of `run` words to each, the lanes
+// writing consecutive words; with `misaligned` each chunk starts its runs
+// 0..15 words into its first 64-byte segment (mix64 of the bucket and the
+// workgroup), so runs start and end inside segments, as appends at a
+// running cursor do.
+constexpr int kAppendBlock = 1024;
+
+__global__ __launch_bounds__(kAppendBlock) void k_append(uint32_t *buf, uint32_t streams, uint32_t run,
+                                                         uint32_t rounds, uint64_t cap, uint32_t misaligned)
+{
+    const uint32_t g = blockIdx.x, nwg = gridDim.x;
+    const uint32_t per_round = streams * run;
+    for (uint32_t r = 0; r < rounds; ++r)
+        for (uint32_t i = threadIdx.x; i < per_round; i += kAppendBlock) {
+            const uint32_t b = i / run, j = i % run;
+            const uint32_t off = misaligned ? (uint32_t)(mix64(((uint64_t)b << 32) | g) & 15u) : 0u;
+            buf[((uint64_t)b * nwg + g) * cap + off + (uint64_t)r * run + j] = i ^ r;
+        }
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *src, uint4 *dst, uint64_t n)
@@ -125,5 +149,23 @@ extern "C" int rambo_roofline_copy(const void *src, void *dst, uint64_t bytes, h
     const uint64_t n = bytes / 16;
     hipLaunchKernelGGL(k_copy, dim3(256 * 64), dim3(kBlock), 0, stream, static_cast<const uint4 *>(src),
                        static_cast<uint4 *>(dst), n);
+    return hipGetLastError() == hipSuccess ? RAMBO_OK : RAMBO_EHIP;
+}
+
+extern "C" int rambo_roofline_append(uint32_t *buf, uint64_t buf_words, uint32_t streams, uint32_t run,
+                                     uint32_t misaligned, uint32_t n_workgroups, uint64_t *written_words,
+                                     hipStream_t stream)
+{
+    if (!buf || !written_words || streams == 0 || run == 0 || n_workgroups == 0)
+        return RAMBO_EINVAL;
+    // chunk of cap words per (bucket, workgroup), a multiple of 16; a run
+    // starts at most 15 words in, so rounds * run + 15 <= cap
+    const uint64_t cap = buf_words / ((uint64_t)streams * n_workgroups) / 16 * 16;
+    if (cap < 16 + (uint64_t)run)
+        return RAMBO_EINVAL;
+    const uint64_t rounds = std::min<uint64_t>((cap - 15) / run, 0xFFFFFFFFull);
+    *written_words = rounds * run * streams * n_workgroups;
+    hipLaunchKernelGGL(k_append, dim3(n_workgroups), dim3(kAppendBlock), 0, stream, buf, streams, run,
+                       (uint32_t)rounds, cap, misaligned ? 1u : 0u);
     return hipGetLastError() == hipSuccess ? RAMBO_OK : RAMBO_EHIP;
 }

@@ -108,6 +108,9 @@ EXPORTS = {
                                              ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
     "rambo_roofline_atomic_or": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                                 ctypes.c_void_p]),
+    "rambo_roofline_append": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.c_void_p]),
     "rambo_roofline_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     # include/rambo_serve.h
     "rambo_serve_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),

@@ -5,6 +5,9 @@ measure(buf_bytes) runs, over one device buffer of buf_bytes:
   * random non-returning 32-bit atomicOr (the insertion of a bit, Alg. 1),
   * a streaming copy (sequential reference),
 and returns accesses per second and bytes per second for each.
+append(buf_bytes, streams) measures the binning's write pattern: runs of 16
+words appended to `streams` per-workgroup chunks, with runs starting inside
+64-byte segments (as at a running cursor) and aligned to them.
 """
 from __future__ import annotations
 
@@ -61,6 +64,29 @@ def measure(buf_bytes: int, n_access: int = 1 << 27, sizes=GATHER_SIZES, buf: to
         assert L.rambo_roofline_copy(buf.data_ptr(), buf.data_ptr() + half, half, st) == 0
     t = _time(c)
     out["copy"] = {"bytes": half, "GBps_read_plus_write": 2 * half / t / 1e9}
+    return out
+
+
+def append(buf_bytes: int, streams: int, run: int = 16, n_workgroups: int = 256,
+           buf: torch.Tensor | None = None) -> dict:
+    """Bytes per second of the binning's write pattern (rambo_roofline_append)
+    over one buffer: misaligned (runs start 0..15 words into a segment) and
+    aligned runs."""
+    import ctypes
+    L = lib()
+    st = torch.cuda.current_stream().cuda_stream
+    if buf is None:
+        buf = torch.empty(buf_bytes // 4, dtype=torch.int32, device="cuda")
+    out = {"buffer_bytes": buf.numel() * 4, "streams": streams, "run_words": run, "workgroups": n_workgroups}
+    for name, mis in (("misaligned", 1), ("aligned", 0)):
+        words = ctypes.c_uint64(0)
+
+        def f(mis=mis, words=words):
+            rc = L.rambo_roofline_append(buf.data_ptr(), buf.numel(), streams, run, mis, n_workgroups,
+                                         ctypes.byref(words), st)
+            assert rc == 0
+        t = _time(f)
+        out[name] = {"bytes": words.value * 4, "GBps": words.value * 4 / t / 1e9}
     return out
 
 
