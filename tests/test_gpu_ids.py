@@ -124,3 +124,69 @@ def test_wide_ids_and_fills(K, B, R, m, n_anc, glen):
     m_gpu, nk = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
     want, _ = o.query_seqs(rd.offsets, rd.chars, nthreads=8)
     assert np.array_equal(host_u32(m_gpu), want)
+
+
+@pytest.fixture(scope="module")
+def wide_long():
+    """1 024-bit rows (B = 1 000, R = 6) over set genomes of about 1.5 kbp, so
+    reads span several 256-window blocks of the read probing."""
+    cfg = dict(K=20_000, B=1000, R=6, m=1 << 14, eta=2, k=31)
+    sets = synth.genome_sets(1177, K=cfg["K"], n_ancestors=60, ancestor_len=1500)
+    o, g = make_pair(cfg, seed=2177)
+    o.insert_seqs(sets.set_ids, sets.offsets, sets.chars, 8)
+    gpu_insert_seqs(g, sets)
+    assert g.sync_status() == rb.OK
+    return cfg, sets, o, g
+
+
+def long_reads(sets, seed):
+    """Reads of 31..1 400 bp (85% substrings with a few substitutions), every
+    7th in lower case and every 11th with an N, plus the edge reads."""
+    rd = synth.reads(seed, sets, 600, median_len=400, min_len=31, max_len=1400, substr_frac=0.85,
+                     read_sub_rate=0.002)
+    chars = rd.chars.copy()
+    rng = np.random.default_rng(seed)
+    for q in range(rd.n):
+        a, b = int(rd.offsets[q]), int(rd.offsets[q + 1])
+        if q % 7 == 0:
+            chars[a:b] = np.char.lower(chars[a:b].view("S1")).view(np.uint8)
+        if q % 11 == 0 and b > a:
+            chars[a + int(rng.integers(0, b - a))] = ord("N")
+    return with_edges(synth.SeqBatch(chars, rd.offsets))
+
+
+@pytest.fixture(scope="module")
+def long_batch(wide_long):
+    """The long-read batch and the oracle's answers to it (computed once)."""
+    cfg, sets, o, g = wide_long
+    rd = long_reads(sets, 3177)
+    want, w_nk = o.query_seqs(rd.offsets, rd.chars, nthreads=16)
+    lists = [oracle.mask_to_ids(row, cfg["K"]) for row in want]
+    w_off = np.zeros(len(lists) + 1, np.int64)
+    np.cumsum([len(x) for x in lists], out=w_off[1:])
+    w_ids = np.array([i for x in lists for i in x], np.int64)
+    return rd, want, w_nk.astype(np.int64), w_off, w_ids
+
+
+@pytest.mark.parametrize("mode,chunk", [(rb.QUERY_WAVE_PER_READ, 0), (rb.QUERY_QUEUE, 256), (rb.QUERY_QUEUE, 1024)])
+def test_multi_block_reads_match_oracle(wide_long, long_batch, mode, chunk):
+    """The read probing takes repetition 0 over a block of windows (after a
+    first look at a few spread over it) before the other repetitions: answers
+    and ID lists for reads of one to six blocks, split or not into queue
+    chunks, equal the oracle's term-by-term ones."""
+    cfg, sets, o, g = wide_long
+    rd, want, w_nk, w_off, w_ids = long_batch
+    g.set_query_policy(mode, chunk, 8 if chunk else 0)
+    try:
+        off, got, nk = gpu_ids(g, rd)
+        assert np.array_equal(nk, w_nk)
+        assert np.array_equal(off, w_off)
+        assert np.array_equal(got, w_ids)
+        m_gpu, nk2 = g.query_seqs(dev(rd.offsets, np.int64), dev(rd.chars, np.uint8))
+        assert np.array_equal(host_u32(m_gpu), want)
+        assert np.array_equal(nk2.cpu().numpy().astype(np.int64), w_nk)
+    finally:
+        g.set_query_policy()
+    # the batch holds both kinds of reads
+    sizes = np.diff(w_off)
+    assert (sizes > 0).sum() > 50 and (sizes == 0).sum() > 50
