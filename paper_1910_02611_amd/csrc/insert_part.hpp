@@ -30,6 +30,7 @@
 namespace rambo_dev {
 
 constexpr uint32_t kRegionLog2Max = 19;         // regions of at most 2^19 bits (64 KiB of LDS)
+constexpr uint32_t kXcds = 8;                   // accelerator complex dies: workgroups are dealt to them in turn
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kFail = 0xFFFFFFFFu;
 constexpr uint16_t kNoBucket = 0xFFFFu;
@@ -426,8 +427,16 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
     uint32_t *lbase = cnt + G.nf;       // nf first sorted slots
     uint32_t *wsum = srt;               // BLK / 64, only while the scan runs
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    const uint32_t c = G.c0 + blockIdx.x / tiles_per_bucket;
-    const uint32_t tile = blockIdx.x % tiles_per_bucket;
+    // workgroup i runs on XCD i mod kXcds; the group's coarse buckets are
+    // dealt to the XCDs (buckets x, x + kXcds, ... to XCD x), so every region
+    // of a bucket is written through one XCD's L2, which can join the runs
+    // that different tiles append next to each other
+    const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    const uint32_t cl = x + kXcds * (j / tiles_per_bucket);
+    if (cl >= G.ncb)
+        return;
+    const uint32_t c = G.c0 + cl;
+    const uint32_t tile = j % tiles_per_bucket;
     const uint64_t span = (uint64_t)G.nwg * G.capA;   // slots of bucket c
     const uint64_t t0 = (uint64_t)tile * TILE;
     if (t0 >= span)

@@ -891,13 +891,15 @@ void launch_stages_bc(rambo *h, const BinGeom &G, uint32_t fresh, hipStream_t st
         BinGeom Gg = G;
         Gg.c0 = c0;
         const uint32_t ncb = std::min(G.ncb, G.na - c0);
+        Gg.ncb = ncb;   // stage B's grid rounds the group up to whole rounds of XCDs and skips the rest
         const uint64_t regions = group_regions(G, c0, ncb);
         if (c0 > 0) {
             StageScope sc(h, "k_zero_u32", stream);
             hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(kBlock), 0, stream, G.fillB, regions);
         }
         { StageScope sc(h, "k_bin_regions", stream);
-        hipLaunchKernelGGL(SB.fn, dim3(ncb * tpb), dim3(SB.blk), SB.lds, stream, h->P, Gg, tpb); }
+        hipLaunchKernelGGL(SB.fn, dim3((uint32_t)(div_up(ncb, kXcds) * kXcds * tpb)), dim3(SB.blk), SB.lds, stream,
+                           h->P, Gg, tpb); }
         { StageScope sc(h, "k_apply_regions", stream);
         hipLaunchKernelGGL(k_apply_regions, dim3((uint32_t)regions), dim3(kBlock), ldsC, stream, h->P, Gg, fresh); }
     }
