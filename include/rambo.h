@@ -252,12 +252,14 @@ int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
  *                 1 or 2 (automatic: 2 for R <= 5, 1 for R = 6; more steps
  *                 give longer runs per coarse bucket but need more registers)
  *   stage_b_tile: slab entries per stage-B tile, 8192, 16384 or 32768
- *                 (automatic: about 16 entries per region, as LDS allows)
+ *                 (automatic: 32768 from 2048 regions per coarse bucket,
+ *                 16384 from 1024, else 8192)
  *   groups:       groups of coarse buckets that stages B and C run over,
  *                 1, 2, 4 or 8 (automatic: the fewest that need the fewest
  *                 scratch batches; slab B holds one group's regions)
  *   fine_bits:    log2 of the 2^19-bit regions per coarse bucket, 8 to 12
- *                 (automatic: about 1024 coarse buckets); must leave at most
+ *                 (automatic: the fewest that give each coarse bucket at
+ *                 least 32 entries per stage-A round); must leave at most
  *                 4096 coarse buckets, else RAMBO_EINVAL
  * Values outside these sets give RAMBO_EINVAL; a stage-B tile whose LDS
  * does not fit the regions of a coarse bucket, and more groups than coarse

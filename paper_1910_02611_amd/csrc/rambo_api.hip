@@ -623,12 +623,19 @@ void plan_partition(rambo *h)
 {
     const uint64_t total_words = (uint64_t)h->cfg.R * h->words_per_rep;
     const uint64_t total_bits = total_words * 32;
-    const uint32_t bits = log2_exact(total_bits);
     BinGeom &G = h->bin;
     G.rb = kRegionLog2;
-    G.fb = bits > G.rb + 10 + 8 ? bits - G.rb - 10 : 8;
-    if (G.fb > 12)
-        G.fb = 12;
+    // the fewest regions per coarse bucket (from 2^8) that give a stage-A
+    // round (automatic steps) at least 32 entries per coarse bucket: with
+    // shorter runs the open 128-byte line each workgroup keeps per bucket
+    // no longer stays in an XCD's L2 between rounds (measured on the 96 GiB
+    // insert: 768 -> 384 buckets, stage A 87.6 -> 72.9 ms per launch, stage
+    // B 10.4 -> 11.5 ms at 4 096 regions per bucket; on the 80 GiB one the
+    // two-step rounds already give 32 at 640 buckets)
+    const uint64_t round_targets = (uint64_t)(h->cfg.R <= 5 ? 2 : 1) * kBlockPc * h->cfg.R * h->cfg.eta;
+    G.fb = 8;
+    while (G.fb < 12 && div_up(total_bits, 1ull << (G.rb + G.fb)) * 32 > round_targets)
+        ++G.fb;
     if (h->tiles.fine_bits)
         G.fb = h->tiles.fine_bits;
     G.nf = 1u << G.fb;
