@@ -514,7 +514,7 @@ def skewed_reads(g, sets, n_short: int = 20000, n_long: int = 16, long_len: int 
     return res
 
 
-REGION_BITS = 19   # the insert's index regions (stage C): 2^19 bits, 64 KiB of LDS
+REGION_BITS = 20   # the insert's index regions (stage C): 2^20 bits, 128 KiB of LDS
 
 
 def stage_a_write_pattern(g, gib: float = 8.0) -> dict:

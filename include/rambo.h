@@ -257,9 +257,10 @@ int rambo_set_insert_policy(rambo_t *h, int mode, uint64_t scratch_bytes);
  *   groups:       groups of coarse buckets that stages B and C run over,
  *                 1, 2, 4 or 8 (automatic: the fewest that need the fewest
  *                 scratch batches; slab B holds one group's regions)
- *   fine_bits:    log2 of the 2^19-bit regions per coarse bucket, 8 to 12
- *                 (automatic: the fewest that give each coarse bucket at
- *                 least 32 entries per stage-A round); must leave at most
+ *   fine_bits:    log2 of the 2^20-bit regions per coarse bucket, 8 to 12
+ *                 (automatic: up to 11 while 256 coarse buckets remain, more
+ *                 while a stage-A round gives a bucket fewer than 32
+ *                 entries); must leave at most
  *                 4096 coarse buckets, else RAMBO_EINVAL
  * Values outside these sets give RAMBO_EINVAL; a stage-B tile whose LDS
  * does not fit the regions of a coarse bucket, and more groups than coarse

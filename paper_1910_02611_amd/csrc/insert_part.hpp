@@ -29,7 +29,8 @@
 
 namespace rambo_dev {
 
-constexpr uint32_t kRegionLog2Max = 19;         // regions of at most 2^19 bits (64 KiB of LDS)
+constexpr uint32_t kRegionLog2Max = 20;         // regions of at most 2^20 bits (128 KiB of LDS)
+constexpr int kBlockC = 1024;                   // workgroup of stage C (one per CU: its region fills most of the LDS)
 constexpr uint32_t kXcds = 8;                   // accelerator complex dies: workgroups are dealt to them in turn
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kFail = 0xFFFFFFFFu;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
 // known to have been all zero before this batch (nothing inserted since it
 // was created or cleared): a region that no fallback atomic touched starts
 // from zero in LDS instead of being read.
-__global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, uint32_t fresh)
+__global__ __launch_bounds__(kBlockC) void k_apply_regions(Params P, BinGeom G, uint32_t fresh)
 {
     extern __shared__ uint32_t lds[];   // 2^rb / 32 words
     const uint64_t gl = blockIdx.x;                       // in the group's slab B
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, u
     u32x4 *l4 = reinterpret_cast<u32x4 *>(lds);
     const u32x4 *g4 = reinterpret_cast<const u32x4 *>(P.index + w0);
     const uint32_t nw4 = nw / 4;
-    constexpr int kRegion4PerThread = (1u << (kRegionLog2Max - 5)) / 4 / kBlock;
+    constexpr int kRegion4PerThread = (1u << (kRegionLog2Max - 5)) / 4 / kBlockC;
     constexpr int kBatch = 8;
     const u32x4 *s4 = reinterpret_cast<const u32x4 *>(G.slabB + gl * G.capB);   // capB is a multiple of 4
     const uint64_t n4 = (n + 3) / 4;
@@ -579,21 +580,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, u
     if (fresh && !G.dirty[g]) {
 #pragma unroll
         for (int i = 0; i < kBatch; ++i)
-            ev[i] = s4[min((uint64_t)i * kBlock + threadIdx.x, n4 - 1)];
+            ev[i] = s4[min((uint64_t)i * kBlockC + threadIdx.x, n4 - 1)];
         const u32x4 zero = {0u, 0u, 0u, 0u};
-        for (uint32_t j = threadIdx.x; j < nw4; j += kBlock)
+        for (uint32_t j = threadIdx.x; j < nw4; j += kBlockC)
             l4[j] = zero;
     } else {
         u32x4 rv[kRegion4PerThread];
 #pragma unroll
         for (int i = 0; i < kRegion4PerThread; ++i)
-            rv[i] = g4[min((uint32_t)(i * kBlock) + threadIdx.x, nw4 - 1)];
+            rv[i] = g4[min((uint32_t)(i * kBlockC) + threadIdx.x, nw4 - 1)];
 #pragma unroll
         for (int i = 0; i < kBatch; ++i)
-            ev[i] = s4[min((uint64_t)i * kBlock + threadIdx.x, n4 - 1)];
+            ev[i] = s4[min((uint64_t)i * kBlockC + threadIdx.x, n4 - 1)];
 #pragma unroll
         for (int i = 0; i < kRegion4PerThread; ++i) {
-            const uint32_t j = i * kBlock + threadIdx.x;
+            const uint32_t j = i * kBlockC + threadIdx.x;
             if (j < nw4)
                 l4[j] = rv[i];
         }
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, u
     auto apply = [&](uint64_t j0) {
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
-            const uint64_t j = j0 + (uint64_t)i * kBlock + threadIdx.x;
+            const uint64_t j = j0 + (uint64_t)i * kBlockC + threadIdx.x;
             const uint32_t e[4] = {ev[i].x, ev[i].y, ev[i].z, ev[i].w};
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -611,15 +612,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_regions(Params P, BinGeom G, u
         }
     };
     apply(0);
-    for (uint64_t j0 = (uint64_t)kBatch * kBlock; j0 < n4; j0 += (uint64_t)kBatch * kBlock) {
+    for (uint64_t j0 = (uint64_t)kBatch * kBlockC; j0 < n4; j0 += (uint64_t)kBatch * kBlockC) {
 #pragma unroll
         for (int i = 0; i < kBatch; ++i)
-            ev[i] = s4[min(j0 + (uint64_t)i * kBlock + threadIdx.x, n4 - 1)];
+            ev[i] = s4[min(j0 + (uint64_t)i * kBlockC + threadIdx.x, n4 - 1)];
         apply(j0);
     }
     __syncthreads();
     u32x4 *o4 = reinterpret_cast<u32x4 *>(P.index + w0);
-    for (uint32_t i = threadIdx.x; i < nw4; i += kBlock)
+    for (uint32_t i = threadIdx.x; i < nw4; i += kBlockC)
         o4[i] = l4[i];
 }
 

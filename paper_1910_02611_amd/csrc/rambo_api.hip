@@ -573,7 +573,7 @@ void launch_read_queue(rambo *h, const ReadQueue &rq, const uint64_t *offsets, u
 
 // ------------------------------------------------- partitioned insertion
 
-constexpr uint32_t kRegionLog2 = kRegionLog2Max;   // 64 KiB of LDS per region
+constexpr uint32_t kRegionLog2 = kRegionLog2Max;   // 128 KiB of LDS per region
 constexpr uint32_t kMaxCoarse = 4096;       // stage-A LDS: tile plus 3 words per coarse bucket
 constexpr size_t kMaxLds = 160 * 1024;      // LDS per workgroup on gfx950
 constexpr double kAtomicRate = 1.7e10;      // measured random atomicOr/s over a large buffer
@@ -625,16 +625,19 @@ void plan_partition(rambo *h)
     const uint64_t total_bits = total_words * 32;
     BinGeom &G = h->bin;
     G.rb = kRegionLog2;
-    // the fewest regions per coarse bucket (from 2^8) that give a stage-A
-    // round (automatic steps) at least 32 entries per coarse bucket: with
-    // shorter runs the open 128-byte line each workgroup keeps per bucket
-    // no longer stays in an XCD's L2 between rounds (measured on the 96 GiB
-    // insert: 768 -> 384 buckets, stage A 87.6 -> 72.9 ms per launch, stage
-    // B 10.4 -> 11.5 ms at 4 096 regions per bucket; on the 80 GiB one the
-    // two-step rounds already give 32 at 640 buckets)
+    // Regions per coarse bucket: as many as stage B's largest tile serves
+    // with runs of 16 (2^11) while at least 256 coarse buckets remain, then
+    // more (to 2^12) while a stage-A round (automatic steps) would give a
+    // bucket fewer than 32 entries: with shorter runs the open 128-byte line
+    // each workgroup keeps per bucket no longer stays in an XCD's L2 between
+    // rounds.  Measured on the 96 GiB insert: 768 -> 384 coarse buckets took
+    // stage A from 87.6 to 72.9 ms per launch.
+    auto coarse = [&](uint32_t fb) { return div_up(total_bits, 1ull << (G.rb + fb)); };
     const uint64_t round_targets = (uint64_t)(h->cfg.R <= 5 ? 2 : 1) * kBlockPc * h->cfg.R * h->cfg.eta;
     G.fb = 8;
-    while (G.fb < 12 && div_up(total_bits, 1ull << (G.rb + G.fb)) * 32 > round_targets)
+    while (G.fb < 11 && coarse(G.fb + 1) >= 256)
+        ++G.fb;
+    while (G.fb < 12 && coarse(G.fb) * 32 > round_targets)
         ++G.fb;
     if (h->tiles.fine_bits)
         G.fb = h->tiles.fine_bits;
@@ -813,6 +816,8 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
     const StageACodes AC = stage_a_codes(h);
     if (hipFuncSetAttribute(binA, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds) != hipSuccess ||
         hipFuncSetAttribute(AC.fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)AC.lds) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_apply_regions), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((1u << (G.rb - 5)) * 4)) != hipSuccess ||
         (AP.fn && hipFuncSetAttribute(reinterpret_cast<const void *>(AP.fn),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)AP.lds) != hipSuccess) ||
         hipFuncSetAttribute(reinterpret_cast<const void *>(stage_b(G, h->tiles.stage_b_tile).fn),
@@ -908,7 +913,7 @@ void launch_stages_bc(rambo *h, const BinGeom &G, uint32_t fresh, hipStream_t st
         hipLaunchKernelGGL(SB.fn, dim3((uint32_t)(div_up(ncb, kXcds) * kXcds * tpb)), dim3(SB.blk), SB.lds, stream,
                            h->P, Gg, tpb); }
         { StageScope sc(h, "k_apply_regions", stream);
-        hipLaunchKernelGGL(k_apply_regions, dim3((uint32_t)regions), dim3(kBlock), ldsC, stream, h->P, Gg, fresh); }
+        hipLaunchKernelGGL(k_apply_regions, dim3((uint32_t)regions), dim3(kBlockC), ldsC, stream, h->P, Gg, fresh); }
     }
 }
 

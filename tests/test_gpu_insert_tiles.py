@@ -48,7 +48,7 @@ def test_tiles_give_the_oracle_index(pair, tiles):
     g.insert_seqs(dev(sets.set_ids, np.int32), dev(sets.offsets, np.int64), dev(sets.chars, np.uint8))
     assert g.sync_status() == rb.OK
     eff = g.insert_tiles()
-    na = max(1, (1 << 30) >> (19 + eff["fine_bits"]))   # coarse buckets
+    na = max(1, (1 << 30) >> (20 + eff["fine_bits"]))   # coarse buckets (regions of 2^20 bits)
     for k, v in tiles.items():
         assert eff[k] == (min(v, na) if k == "groups" else v), (k, eff)
     got, pad = index_bits(g)
