@@ -810,7 +810,7 @@ int ensure_scratch(rambo *h, uint64_t want_targets)
         return fail(h, RAMBO_ENOMEM, "insert scratch allocation failed");
     }
     BinGeom &G = h->bin;
-    // stages A and B use more than the default 64 KiB of dynamic LDS
+    // stages A, B and C use more than the default 64 KiB of dynamic LDS
     const StageA A = stage_a(h);
     const void *binA = A.hold ? reinterpret_cast<const void *>(A.hold) : reinterpret_cast<const void *>(A.generic);
     const StageACodes AC = stage_a_codes(h);
