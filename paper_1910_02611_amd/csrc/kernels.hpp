@@ -612,11 +612,19 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum of v over the 64 lanes (every lane gets it); call with the whole wave
+// active.  The DPP pattern of wave_and: each step adds a disjoint partner
+// group inside a row of 16 lanes (pairs, quads, half rows, rows), then the
+// four row sums are read out.
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
-    for (int d = 32; d >= 1; d >>= 1)
-        v += __shfl_xor(v, d, kWave);
-    return v;
+    constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kQuadSwap1, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kQuadSwap2, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kHalfMirror, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kMirror, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
 __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t lane)
