@@ -265,17 +265,21 @@ def section_large(args):
     off, ch = to_dev(rd.offsets, np.int64), to_dev(rd.chars, np.uint8)
     ids = torch.empty(16 << 20, dtype=torch.int32, device="cuda")
     nk = torch.empty(rd.n, dtype=torch.int32, device="cuda")
+    id_offsets = torch.empty(rd.n + 1, dtype=torch.int64, device="cuda")
     state = {}
 
     def query():
-        state["r"] = g.query_seqs_ids(off, ch, ids=ids, nkmers=nk)
+        # asynchronous: every kernel of the ID-list query runs in the timed
+        # phase; the overflow status is checked once the steps are done
+        state["r"] = g.query_seqs_ids(off, ch, ids=ids, nkmers=nk, id_offsets=id_offsets, wait=False)
 
     pattern = stage_a_write_pattern(g) if not args.no_measured_ceilings else None
     tuning = tune_insert(g, lambda: g.insert_seqs(*dsets), "large", args, reps=1)
     wall, ph, kernels = time_steps(g, lambda: g.insert_seqs(*dsets), query, args.steps, args.warmup)
     if g.sync_status() != 0:
-        raise SystemExit("device error flag set (large)")
+        raise SystemExit("device error flag set (large): an ID list did not fit, or a bad input")
     id_off, got_ids, nkm = state["r"]
+    got_ids = got_ids[:int(id_off[-1].item())]
     kmers = int(nkm.to(torch.int64).sum())
     sizes = np.diff(id_off.cpu().numpy())
     RE = cfg["R"] * cfg["eta"]

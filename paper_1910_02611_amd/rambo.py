@@ -298,17 +298,31 @@ class Rambo:
                     "rambo_query_seqs")
         return out, nkmers
 
-    def query_seqs_ids(self, offsets, chars, ids=None, nkmers=None, stream=None):
+    def query_seqs_ids(self, offsets, chars, ids=None, nkmers=None, stream=None, id_offsets=None,
+                       wait: bool = True):
         """Answers as ascending set-ID lists: (id_offsets int64 [n+1], ids
         int32 [total], window counts int32 [n]).  Synchronises `stream`; when
         the given (or first guessed) capacity is too small, calls again with
-        exactly the capacity needed."""
+        exactly the capacity needed.  With wait=False: one asynchronous call
+        into the given buffers (ids is the capacity), returned whole; the
+        caller reads the list sizes from id_offsets and checks sync_status
+        (EOVERFLOW: some list did not fit) once the stream is done."""
         n = offsets.numel() - 1
-        id_off = torch.empty(max(n, 0) + 1, dtype=torch.int64, device=offsets.device)
+        id_off = id_offsets if id_offsets is not None else \
+            torch.empty(max(n, 0) + 1, dtype=torch.int64, device=offsets.device)
+        if id_off.numel() < n + 1:
+            raise ValueError("id_offsets must hold n + 1 entries")
         if nkmers is None:
             nkmers = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
         if ids is None:
             ids = torch.empty(max(1024, 4 * n), dtype=torch.int32, device=offsets.device)
+        if not wait:
+            rc = lib().rambo_query_seqs_ids(self._h, _dptr(offsets, _U64, "offsets"), n,
+                                            _dptr(chars, (torch.uint8,), "chars"), chars.numel(), id_off.data_ptr(),
+                                            ids.data_ptr(), ids.numel(), _dptr(nkmers, _U32, "nkmers"),
+                                            _stream(stream))
+            self._check(rc, "rambo_query_seqs_ids")
+            return id_off, ids, nkmers
         for _ in range(2):
             rc = lib().rambo_query_seqs_ids(self._h, _dptr(offsets, _U64, "offsets"), n,
                                             _dptr(chars, (torch.uint8,), "chars"), chars.numel(), id_off.data_ptr(),

@@ -190,3 +190,24 @@ def test_multi_block_reads_match_oracle(wide_long, long_batch, mode, chunk):
     # the batch holds both kinds of reads
     sizes = np.diff(w_off)
     assert (sizes > 0).sum() > 50 and (sizes == 0).sum() > 50
+
+
+def test_ids_without_waiting(tiny):
+    """wait=False: one asynchronous call into the caller's buffers; after the
+    stream is done the lists equal the synchronous form's, and a capacity
+    that is too small shows as EOVERFLOW (the offsets stay complete)."""
+    cfg, sets, o, g = tiny
+    rd = synth.config_batched_reads(sets, 800, seed=3014)
+    offs, chars = dev(rd.offsets, np.int64), dev(rd.chars, np.uint8)
+    w_off, w_ids, w_nk = g.query_seqs_ids(offs, chars)
+    id_off = torch.empty(rd.n + 1, dtype=torch.int64, device="cuda")
+    ids = torch.empty(int(w_off[-1].item()) + 16, dtype=torch.int32, device="cuda")
+    off, got, nk = g.query_seqs_ids(offs, chars, ids=ids, id_offsets=id_off, wait=False)
+    assert g.sync_status() == rb.OK
+    assert torch.equal(off, w_off) and torch.equal(nk[:rd.n], w_nk)
+    assert torch.equal(got[:int(off[-1].item())], w_ids)
+    small = torch.empty(max(1, int(w_off[-1].item()) // 2), dtype=torch.int32, device="cuda")
+    off2, _, _ = g.query_seqs_ids(offs, chars, ids=small, id_offsets=id_off, wait=False)
+    assert g.sync_status() == rb.EOVERFLOW
+    assert torch.equal(off2, w_off)
+    assert g.sync_status() == rb.OK
