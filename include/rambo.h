@@ -115,7 +115,7 @@ typedef struct rambo rambo_t;
 
 /* Create an index: validate cfg, derive the seeds, build phi_r and the cell
  * membership tables on the device (SetIDs(M[b,r]) of Alg. 2), allocate and
- * zero the R*B Bloom filters (Alg. 1, first two steps).  Synchronous.
+ * zero the R*B Bloom filters (the set-up of Alg. 1).  Synchronous.
  * Returns RAMBO_EINVAL for a bad cfg, RAMBO_ENOMEM, RAMBO_EHIP. */
 int rambo_create(const rambo_config *cfg, rambo_t **out);
 
