@@ -11,7 +11,11 @@ sets that hold all of its 31-mers.
 
 One step = zero the index + insert every set (partitioned insert, in as
 many scratch batches as the insert needs) + answer every read
-(rambo_query_seqs_ids).  Inputs are resident in device memory before timing.
+(rambo_query_seqs_ids, called asynchronously into buffers sized beforehand;
+its overflow status is checked after the timed steps).  Inputs are resident
+in device memory before timing.  Before the first insert the large section
+also measures the insert's stage-A write pattern alone
+(rambo_roofline_append) and reports stage A against it.
 `value` is k-mer queries per second of the query phase (every valid 31-mer
 window of the reads is one k-mer query answered); inserts per second of the
 insert phase are reported beside it.  Phase times come from HIP events on
