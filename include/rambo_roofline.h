@@ -46,8 +46,9 @@ int rambo_roofline_atomic_or(uint32_t *buf, uint64_t buf_words, uint64_t n_acces
  * first 64-byte segment (from mix64 of the bucket and the workgroup), so runs
  * start and end inside segments as appends at a running cursor do; with 0
  * every run of 16 words fills one aligned segment.  *written_words (host
- * memory) receives the words the launch writes.  RAMBO_EINVAL when a chunk
- * cannot hold one run. */
+ * memory) receives the words the launch writes.  RAMBO_EINVAL for a null
+ * pointer, a zero count, streams * run above 2^32 - 1 or a chunk that cannot
+ * hold one run. */
 int rambo_roofline_append(uint32_t *buf, uint64_t buf_words, uint32_t streams, uint32_t run, uint32_t misaligned,
                           uint32_t n_workgroups, uint64_t *written_words, hipStream_t stream);
 

@@ -156,7 +156,8 @@ extern "C" int rambo_roofline_append(uint32_t *buf, uint64_t buf_words, uint32_t
                                      uint32_t misaligned, uint32_t n_workgroups, uint64_t *written_words,
                                      hipStream_t stream)
 {
-    if (!buf || !written_words || streams == 0 || run == 0 || n_workgroups == 0)
+    if (!buf || !written_words || streams == 0 || run == 0 || n_workgroups == 0 ||
+        (uint64_t)streams * run > 0xFFFFFFFFull)   // a round's words are counted in 32 bits
         return RAMBO_EINVAL;
     // chunk of cap words per (bucket, workgroup), a multiple of 16; a run
     // starts at most 15 words in, so rounds * run + 15 <= cap

@@ -61,3 +61,14 @@ def test_null_handle_calls(lib):
     assert lib.rambo_query_seqs_ids_noalloc(None, None, 0, None, 0, None, None, 0, None, None) == rambo.EINVAL
     assert lib.rambo_query_seqs_ids_noalloc_max_reads(None) == 0
     lib.rambo_destroy(None)
+
+
+def test_probe_arguments_are_checked_on_the_host(lib):
+    # rejected before any launch: a round of streams * run words past 32 bits,
+    # a null output, a buffer whose chunks cannot hold one run
+    written = ctypes.c_uint64(0)
+    dummy = ctypes.c_void_p(4096)
+    assert lib.rambo_roofline_append(dummy, 1 << 40, 1 << 20, 1 << 13, 0, 1, ctypes.byref(written), None) \
+        == rambo.EINVAL
+    assert lib.rambo_roofline_append(dummy, 1 << 20, 16, 16, 0, 1, None, None) == rambo.EINVAL
+    assert lib.rambo_roofline_append(dummy, 64, 4, 16, 1, 2, ctypes.byref(written), None) == rambo.EINVAL

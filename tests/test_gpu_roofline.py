@@ -48,3 +48,4 @@ def test_append_rejects_a_small_buffer():
     rc = L.rambo_roofline_append(buf.data_ptr(), 64, 4, 16, 1, 2, ctypes.byref(written),
                                  torch.cuda.current_stream().cuda_stream)
     assert rc == EINVAL
+
