@@ -467,15 +467,13 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
 #pragma unroll
     for (int i = 0; i < kV; ++i)
         v[i] = s4[min((uint32_t)(i * BLK) + threadIdx.x, n4 - 1)];
-    __syncthreads();
-    uint32_t rk[kV * 4];
+    // each vector's chunk (its 4 slots share one: capA is a multiple of 4)
+    // and that chunk's fill, loaded for every vector before any is used so
+    // that the loads are in flight together
+    uint32_t gv[kV], fv[kV];
 #pragma unroll
     for (int i = 0; i < kV; ++i) {
-        const uint32_t j = (uint32_t)(i * BLK) + threadIdx.x;
-        const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
-        // the vector's chunk (its 4 slots share one: capA is a multiple of 4)
-        // and how many of its slots hold entries
-        const uint64_t p = t0 + 4ull * j;
+        const uint64_t p = t0 + 4ull * ((uint32_t)(i * BLK) + threadIdx.x);
         uint64_t g = 0;
         if (G.nwg > 1) {
             g = (uint64_t)((double)p * inv_cap);
@@ -484,11 +482,30 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
             else if ((g + 1) * G.capA <= p)
                 ++g;
         }
-        const uint64_t gs = g * G.capA;
-        const uint64_t lim = j * 4 < n ? min((uint64_t)cfill[min(g, (uint64_t)G.nwg - 1)], G.capA) : 0;
+        gv[i] = (uint32_t)min(g, (uint64_t)G.nwg - 1);
+        fv[i] = cfill[gv[i]];
+    }
+    // how many of each vector's slots hold entries (0..4), 4 bits per vector
+    static_assert(kV <= 8, "slot counts of 4 bits fit one word");
+    uint32_t nv = 0;
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+        const uint32_t j = (uint32_t)(i * BLK) + threadIdx.x;
+        const uint64_t p = t0 + 4ull * j;
+        const uint64_t end = (uint64_t)gv[i] * G.capA + min((uint64_t)fv[i], G.capA);   // past the chunk's entries
+        uint32_t a = end > p ? (uint32_t)min(end - p, (uint64_t)4) : 0u;
+        a = j * 4 < n ? min(a, n - j * 4) : 0u;
+        nv |= a << (4 * i);
+    }
+    __syncthreads();
+    uint32_t rk[kV * 4];
+#pragma unroll
+    for (int i = 0; i < kV; ++i) {
+        const uint32_t e[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+        const uint32_t a = (nv >> (4 * i)) & 15u;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const bool ok = j * 4 + q < n && p + q - gs < lim && e[q] != kSentinel;
+            const bool ok = (uint32_t)q < a && e[q] != kSentinel;
             rk[i * 4 + q] = ok ? atomicAdd(&cnt[e[q] >> G.rb], 1u) : kNone;
         }
     }
@@ -519,6 +536,7 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
     res.finish(gbase, G.nf, slab, G.capB);
     __syncthreads();
     const uint32_t maskB = (1u << G.rb) - 1;
+    const uint32_t capB32 = (uint32_t)G.capB;   // below 2^31 (the scratch plan's bound)
     const uint64_t cbit = (uint64_t)c << (G.rb + G.fb);
     // kOut sorted slots per thread at a time: their LDS reads are in flight
     // together
@@ -542,7 +560,7 @@ __global__ __launch_bounds__(BLK) void k_bin_regions(Params P, BinGeom G, uint32
                 if (g[u] == kFail)
                     fallback_or(P, G, cbit + e[u]);
                 else
-                    slab[(uint64_t)(e[u] >> G.rb) * G.capB + g[u] + (i - lb[u])] = e[u] & maskB;
+                    slab[(uint64_t)(e[u] >> G.rb) * capB32 + g[u] + (i - lb[u])] = e[u] & maskB;
             }
         }
     }
