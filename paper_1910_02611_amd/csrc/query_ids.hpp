@@ -59,26 +59,61 @@ struct Enum {
     uint32_t cells;      // positive cells of rstar
 };
 
-// The whole wave plans: lane l takes words l, l + 64, ... of each
-// repetition, then wave sums.
-__device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, uint32_t SW, uint32_t lane)
+// The whole wave plans in one pass over the words of every repetition: lane
+// l takes words l, l + 64, ... of the R*SW.  A positive cell's candidates are
+// its member count (from member_off); the counts of the first cell of four
+// words per lane are loaded together before any is used, so a read whose
+// words hold one positive cell each costs one round trip to memory instead
+// of one per repetition.  The per-repetition sums (candidates, then positive
+// cells) gather in acc, 2 R words of the wave's LDS.
+__device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, uint32_t SW, uint32_t lane,
+                                          uint32_t *acc)
 {
-    Enum e{false, 0, 0};
-    uint32_t best = 0xFFFFFFFFu, all_cells = 0;
-    for (uint32_t r = 0; r < P.R; ++r) {
-        const uint32_t *off = P.member_off + (uint64_t)r * (P.B + 1);
-        uint32_t cand = 0, cells = 0;
-        for (uint32_t sw = lane; sw < SW; sw += kWave) {
-            uint32_t bits = G[r * SW + sw];
-            cells += __builtin_popcount(bits);
-            while (bits) {
-                const uint32_t b = sw * 32 + (uint32_t)__builtin_ctz(bits);
-                bits &= bits - 1;
-                cand += off[b + 1] - off[b];
+    const uint32_t R = P.R, rsw = R * SW;
+    const uint32_t sw_log = (uint32_t)__builtin_ctz(SW);   // SW is a power of two
+    for (uint32_t i = lane; i < 2 * R; i += kWave)
+        acc[i] = 0;
+    wave_sync_lds();
+    constexpr uint32_t kU = 4;   // words per lane whose loads are in flight together
+    for (uint32_t w0 = lane; w0 < rsw; w0 += kU * kWave) {
+        uint32_t bits[kU], r_of[kU], lo[kU], hi[kU];
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            const uint32_t w = w0 + u * kWave;
+            bits[u] = w < rsw ? G[w] : 0u;
+            r_of[u] = w < rsw ? w >> sw_log : 0u;
+            lo[u] = hi[u] = 0;
+            if (bits[u]) {
+                const uint32_t *off = P.member_off + (uint64_t)r_of[u] * (P.B + 1);
+                const uint32_t b = (w - r_of[u] * SW) * 32 + (uint32_t)__builtin_ctz(bits[u]);
+                lo[u] = off[b];
+                hi[u] = off[b + 1];
             }
         }
-        cand = wave_sum_u32(cand);
-        cells = wave_sum_u32(cells);
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            if (!bits[u])
+                continue;
+            const uint32_t r = r_of[u];
+            uint32_t cand = hi[u] - lo[u];
+            // the word's further cells, one at a time
+            const uint32_t *off = P.member_off + (uint64_t)r * (P.B + 1);
+            const uint32_t base = (w0 + u * kWave - r * SW) * 32;
+            uint32_t m = bits[u] & (bits[u] - 1);
+            while (m) {
+                const uint32_t b = base + (uint32_t)__builtin_ctz(m);
+                m &= m - 1;
+                cand += off[b + 1] - off[b];
+            }
+            atomicAdd(&acc[r], cand);
+            atomicAdd(&acc[R + r], (uint32_t)__builtin_popcount(bits[u]));
+        }
+    }
+    wave_sync_lds();
+    Enum e{false, 0, 0};
+    uint32_t best = 0xFFFFFFFFu, all_cells = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t cand = acc[r], cells = acc[R + r];
         all_cells += cells;
         if (cand < best) {
             best = cand;
@@ -86,7 +121,7 @@ __device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, ui
             e.cells = cells;
         }
     }
-    e.by_members = (uint64_t)best * (P.R - 1) <= (uint64_t)P.W * all_cells;
+    e.by_members = (uint64_t)best * (R - 1) <= (uint64_t)P.W * all_cells;
     return e;
 }
 
@@ -194,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uin
             const uint64_t q = q0 + l;
             uint32_t c = 0;
             if (!load_read_masks(P, Q, q, SW, G, lane)) {
-                const Enum e = plan_enum(P, G, SW, lane);
+                const Enum e = plan_enum(P, G, SW, lane, buf);
                 if (e.by_members) {
                     for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
                         const uint64_t bal = __ballot(pass);
@@ -341,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_ids_write(Params P, ReadQueue Q, uin
                 continue;
             }
             load_read_masks(P, Q, q, SW, G, lane);
-            const Enum e = plan_enum(P, G, SW, lane);
+            const Enum e = plan_enum(P, G, SW, lane, buf);
             if (e.by_members && e.cells == 1) {
                 // one member list, ascending: passing members in list order
                 uint64_t base = o0;
