@@ -126,17 +126,36 @@ __device__ __forceinline__ Enum plan_enum(const Params &P, const uint32_t *G, ui
 }
 
 // Whether set i is in every repetition's positive cells other than rstar.
+// The first other repetition is tested alone (most candidates fail there);
+// for the lanes that pass it, the cells of the remaining repetitions are
+// loaded kRB at a time before any is tested, so their loads are in flight
+// together.
 __device__ __forceinline__ bool member_passes(const Params &P, const uint32_t *G, uint32_t SW, uint32_t rstar,
                                               uint32_t i)
 {
-    for (uint32_t r = 0; r < P.R; ++r) {
-        if (r == rstar)
-            continue;
-        const uint32_t b = P.phi[(uint64_t)r * P.K + i];
-        if (!((G[r * SW + (b >> 5)] >> (b & 31)) & 1u))
-            return false;
+    const uint32_t r1 = rstar == 0 ? 1u : 0u;
+    if (r1 >= P.R)
+        return true;
+    const uint32_t b1 = P.phi[(uint64_t)r1 * P.K + i];
+    if (!((G[r1 * SW + (b1 >> 5)] >> (b1 & 31)) & 1u))
+        return false;
+    constexpr uint32_t kRB = 4;
+    bool pass = true;
+    for (uint32_t r0 = r1 + 1; r0 < P.R && pass; r0 += kRB) {
+        uint32_t cell[kRB];
+#pragma unroll
+        for (uint32_t j = 0; j < kRB; ++j) {
+            const uint32_t r = r0 + j;
+            cell[j] = r < P.R && r != rstar ? P.phi[(uint64_t)r * P.K + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kRB; ++j) {
+            const uint32_t r = r0 + j;
+            if (r < P.R && r != rstar)
+                pass = pass && ((G[r * SW + (cell[j] >> 5)] >> (cell[j] & 31)) & 1u);
+        }
     }
-    return true;
+    return pass;
 }
 
 // Calls f(i, pass) for the candidates of rstar, 64 at a time on the wave's
