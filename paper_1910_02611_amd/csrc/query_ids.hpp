@@ -242,12 +242,41 @@ __global__ __launch_bounds__(kBlock) void k_ids_count(Params P, ReadQueue Q, uin
         const uint64_t ql = q0 + lane;
         uint64_t todo = __ballot(ql < n_reads && !read_known_empty(Q, ql));
         uint32_t mine = 0;   // the count of read ql
+        // the next read's masks are loaded while this one is enumerated
+        // (reads of at most kPre * 64 mask words)
+        constexpr uint32_t kPre = 3;
+        const bool pre = rsw <= kPre * kWave;
+        uint32_t nxt[kPre];
+        auto fetch = [&](uint64_t qn) {
+#pragma unroll
+            for (uint32_t u = 0; u < kPre; ++u) {
+                const uint32_t i = lane + u * kWave;
+                nxt[u] = i < rsw ? Q.G[qn * rsw + i] : 0u;
+            }
+        };
+        if (pre && todo)
+            fetch(q0 + __builtin_ctzll(todo));
         while (todo) {
             const uint32_t l = (uint32_t)__builtin_ctzll(todo);
             todo &= todo - 1;
             const uint64_t q = q0 + l;
             uint32_t c = 0;
-            if (!load_read_masks(P, Q, q, SW, G, lane)) {
+            bool empty;
+            if (pre) {
+#pragma unroll
+                for (uint32_t u = 0; u < kPre; ++u) {
+                    const uint32_t i = lane + u * kWave;
+                    if (i < rsw)
+                        G[i] = nxt[u];
+                }
+                wave_sync_lds();
+                empty = any_rep_empty_wave(G, P.R, SW, lane);
+                if (todo)
+                    fetch(q0 + __builtin_ctzll(todo));
+            } else {
+                empty = load_read_masks(P, Q, q, SW, G, lane);
+            }
+            if (!empty) {
                 const Enum e = plan_enum(P, G, SW, lane, buf);
                 if (e.by_members) {
                     for_candidates(P, G, SW, e.rstar, lane, [&](uint32_t i, bool pass) {
